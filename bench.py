@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark: Eisenstein-discriminant classification at d ~ 10^11 on one MI355X.
+
+One step = one classification of the whole workload range (sieve, walks,
+counts) through the C ABI, with device-resident outputs.  Prints ONE JSON
+line (see the keys below).  The workload is the last 10^8-window below 10^11
+(about 10.1 million members of D), whose Eisenstein count the paper prints
+in Table 1 (3,345,503); the bench checks it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method auto|baby|infra]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "discriminants classified/sec and baby-steps/sec at d≈1e11; p99 query latency"
+TABLE1_LARGE = 3345503
+
+# 32-bit VALU lane-operations per second of MI355X: 256 CUs x 4 SIMD x 16
+# lanes x 2.4 GHz.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic lane-operations of one reduction step (partial quotient with
+# exact correction, the P and Q updates, the Z/3 residue, two exit tests).
+OPS_PER_BABY_STEP = 16
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(a: int, b: int, target_s: float = 15.0):
+    """The oracle (full-period walk, mod-2 mode) on a bounded random sample of
+    the members of D in [a, b), timed on this host's cores."""
+    import numpy as np
+    import oracle
+    from paper_2507_06579_amd import workloads
+    bits, _ = oracle.sqfree_range(a, b)
+    n = oracle.num_candidates(a, b)
+    d0 = oracle.first_candidate(a)
+    idx = np.flatnonzero(np.unpackbits(bits, bitorder="little")[:n])
+    cores = os.cpu_count() or 1
+    rng_idx = workloads.sample_indices(idx.size, idx.size, seed=7)
+    members = d0 + 8 * idx[rng_idx].astype(np.uint64)
+    # calibrate on a small batch, then size the sample for about target_s
+    k0 = min(4 * cores, members.size)
+    t = time.perf_counter()
+    oracle.classify_list(members[:k0], nthreads=cores)
+    dt0 = max(time.perf_counter() - t, 1e-3)
+    k = int(min(members.size - k0, max(cores, k0 * target_s / dt0)))
+    sample = members[k0:k0 + k]
+    t = time.perf_counter()
+    _, steps = oracle.classify_list(sample, nthreads=cores)
+    dt = time.perf_counter() - t
+    return {"value": round(sample.size / dt, 2), "unit": "discriminants/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{sample.size} random members of D in [{a}, {b}), full-period walk "
+                      f"({steps} rho steps, {dt:.1f} s on {cores} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", default="auto", choices=["auto", "baby", "infra"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the per-d walks "
+                                   "are independent, and sharding ranges across GPUs is "
+                                   "described in DESIGN.md but not run"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_06579_amd as eis
+    from paper_2507_06579_amd import workloads
+
+    a, b = workloads.LARGE
+    method = {"auto": eis.Method.AUTO, "baby": eis.Method.BABY, "infra": eis.Method.INFRA}[args.method]
+    n = eis.eis_num_candidates(a, b)
+    nb = (n + 7) // 8
+    dev = torch.device("cuda:0")
+    sq = torch.zeros(nb, dtype=torch.uint8, device=dev)
+    eb = torch.zeros(nb, dtype=torch.uint8, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    ctx = eis.Context(device=0, method=method)
+
+    def step():
+        ctx.eis_classify_async(a, b, sq.data_ptr(), eb.data_ptr(), counts.data_ptr(), 0)
+
+    log(f"workload [{a}, {b}) candidates={n} method={args.method}")
+    for i in range(args.warmup):
+        step()
+        rc = ctx.eis_last_error()
+        if rc != 0:
+            raise SystemExit(f"warmup step failed: {eis.eis_strerror(rc)}")
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    base = ctx.eis_get_stats()
+    walk_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        rc = ctx.eis_last_error()  # synchronises the context stream
+        if rc != 0:
+            raise SystemExit(f"step failed: {eis.eis_strerror(rc)}")
+        walk_ms.append(ctx.eis_get_stats()["last_walk_ms"])
+        log(f"step {i + 1}/{args.steps} walk {walk_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ctx.eis_get_stats()
+    n_sq, n_e = counts.cpu().tolist()
+    if n_e != TABLE1_LARGE:
+        raise SystemExit(f"pi_E of the window is {n_e}, Table 1 says {TABLE1_LARGE}")
+    discs = st["discriminants"] - base["discriminants"]
+    baby = st["baby_steps"] - base["baby_steps"]
+    giant = st["giant_steps"] - base["giant_steps"]
+    value = discs / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    avg_walk_s = sum(walk_ms) / len(walk_ms) / 1e3
+    ops_per_launch = OPS_PER_BABY_STEP * baby / args.steps
+    achieved = ops_per_launch / avg_walk_s
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "kernel": "k_walk_baby",
+                "ops_per_unit": OPS_PER_BABY_STEP, "units_per_launch": int(baby / args.steps),
+                "avg_launch_ms": round(avg_walk_s * 1e3, 3)}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "discriminants/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32/fp32-exact",
+        "data": "synthetic: the integer range itself (no dataset)",
+        "config": {"workload": f"large height: all d = 5 mod 8 in [{a}, {b})",
+                   "candidates": n, "members_of_D": n_sq, "pi_E": n_e,
+                   "method": args.method},
+        "baby_steps_per_s": round(baby / elapsed, 1),
+        "giant_steps_per_s": round(giant / elapsed, 1),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(a, b)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

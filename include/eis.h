@@ -1,0 +1,182 @@
+/*
+ * eis.h -- C ABI of libeis, an MI355X (gfx950) implementation of the search
+ * for Eisenstein discriminants of Breuer & Punch, "Quadratic units and cubic
+ * fields".
+ *
+ * Problem (Section 1 of the paper): for every candidate d in a half-open
+ * range [a, b) decide whether d lies in
+ *     D = { d > 0 : d = 5 (mod 8), d squarefree }   and in
+ *     E = { d in D : eps_d = 1 (mod 2 O_K) },
+ * where eps_d is the fundamental unit of Q(sqrt d) and O_K = Z[(1+sqrt d)/2],
+ * and count both sets (pi_D, pi_E).  pi_E(x) is the n_eis of [5, x+1).
+ *
+ * Method (Appendix A): the cycle of reduced principal ideals of O_K is
+ * walked with the reduction map rho (baby steps), optionally combined with
+ * the infrastructure giant steps of Algorithm "Infrastructure" using NUCOMP,
+ * NUDUPL and NUCOMPchoose, while the relative generators are carried as
+ * elements of (O_K/2O_K)^* ~ F_4^* ~ Z/3.  The result per d is exact:
+ * no heuristic, no tolerance.
+ *
+ * Conventions shared by every call:
+ *  - Candidate lattice.  d_i = d0 + 8 i, i = 0 .. n-1, where d0 is the least
+ *    d >= a with d = 5 (mod 8) and n = eis_num_candidates(a, b).
+ *  - Bitmaps.  Bit i of a bitmap is bit (i % 8) of byte i / 8 (LSB first);
+ *    a bitmap for [a, b) is ceil(n / 8) bytes; the unused high bits of the
+ *    last byte are written as 0.
+ *  - Ranges.  a >= b is an empty range: OK, zero counts, nothing written.
+ *    b > EIS_MAX_D gives EIS_ERANGE.
+ *  - Errors.  Every call returns an eis_status (0 = OK, < 0 = error).  On
+ *    error, caller-owned outputs are left untouched.  No C++ exception
+ *    crosses this boundary.
+ *  - Ownership.  The library owns everything inside an eis_ctx (device
+ *    memory, streams, queues); pointers passed in are borrowed for the
+ *    duration of the call (or, for the _async call, until the stream has
+ *    passed the work).
+ *  - Threads.  One eis_ctx may be used by one host thread at a time, except
+ *    eis_submit, eis_wait, eis_cancel and eis_get_stats, which are safe to
+ *    call from any thread.
+ *  - There is no CPU fallback: an eis_ctx needs a gfx950 device, and
+ *    eis_create fails with EIS_EDEVICE without one.
+ */
+#ifndef EIS_H
+#define EIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EIS_ABI_VERSION 1
+
+/* Largest supported exclusive upper bound b.  The baby-step walk keeps every
+ * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
+ * composition checks every 64-bit product against overflow. */
+#define EIS_MAX_D 1000000000000ULL /* 10^12 */
+
+typedef struct eis_ctx eis_ctx;
+
+typedef enum {
+    EIS_OK = 0,
+    EIS_EINVAL = -1,     /* bad argument (NULL pointer, short buffer, bad config) */
+    EIS_ERANGE = -2,     /* b > EIS_MAX_D */
+    EIS_ENOMEM = -3,     /* device memory or the memory budget exhausted */
+    EIS_EDEVICE = -4,    /* no usable gfx950 device, or a HIP runtime error */
+    EIS_EBUSY = -5,      /* serving queue full (eis_submit) */
+    EIS_ECANCELED = -6,  /* request was cancelled (eis_wait) */
+    EIS_ETIMEDOUT = -7,  /* eis_wait timed out; the request is still pending */
+    EIS_EINTERNAL = -8   /* a walk exceeded max_steps_per_d or an internal check
+                            failed; no result bit was produced for it */
+} eis_status;
+
+typedef enum {
+    EIS_METHOD_BABY = 0,  /* rho steps only, to the half-period symmetry point */
+    EIS_METHOD_INFRA = 1, /* baby window + infrastructure giant steps */
+    EIS_METHOD_AUTO = 2   /* per-range choice by height (autotuned) */
+} eis_method;
+
+typedef struct {
+    int device;                /* HIP device ordinal */
+    int method;                /* an eis_method */
+    uint64_t mem_budget_bytes; /* device bytes the context may hold; 0 = 1/4 of free memory */
+    uint64_t max_steps_per_d;  /* per-d step budget; 0 = default (2^28) */
+    double window_scale;       /* giant-step method: baby window = window_scale * d^(1/4)
+                                  reduction steps; 0 = autotuned */
+    uint32_t serve_slots;      /* serving: max requests in flight; 0 = default (64) */
+    uint32_t flags;            /* reserved, must be 0 */
+    const char *tune_cache_path; /* autotuner JSON cache; NULL = no persistence */
+} eis_config;
+
+typedef struct {
+    uint64_t launches;         /* kernel launches issued */
+    uint64_t discriminants;    /* members of D classified */
+    uint64_t baby_steps;       /* rho steps executed on the device */
+    uint64_t giant_steps;      /* giant steps (NUCOMP / NUDUPL) executed */
+    uint64_t refills;          /* lane refills in the walk kernels */
+    uint64_t requests_done;    /* serving requests completed */
+    double last_walk_ms;       /* device time of the last walk launch(es) */
+    double last_total_ms;      /* device time of the last whole classify */
+} eis_stats;
+
+/* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */
+void eis_config_default(eis_config *cfg);
+
+/* Create a context on cfg->device.  *out receives the context.
+ * EIS_EDEVICE without a gfx950 device, EIS_EINVAL on a bad config. */
+int eis_create(const eis_config *cfg, eis_ctx **out);
+
+/* Destroy a context (waits for its outstanding work).  NULL is a no-op. */
+void eis_destroy(eis_ctx *ctx);
+
+/* Number of candidates d = 5 (mod 8) with a <= d < b (Section 1: D is a
+ * subset of this lattice).  Pure host arithmetic, no context needed. */
+uint64_t eis_num_candidates(uint64_t a, uint64_t b);
+
+/* d0: least d >= a with d = 5 (mod 8). */
+uint64_t eis_first_candidate(uint64_t a);
+
+/* Counts only: *n_sqfree = #(D n [a,b)) and *n_eis = #(E n [a,b))
+ * (Section 1, pi_D and pi_E).  Either output pointer may be NULL. */
+int eis_count(eis_ctx *ctx, uint64_t a, uint64_t b, uint64_t *n_sqfree, uint64_t *n_eis);
+
+/* Flags and counts into caller-owned HOST buffers (Section 1, the sets D, E):
+ * sqfree_bits bit i = [d_i in D], eis_bits bit i = [d_i in E] (eis is a
+ * subset of sqfree).  Either bitmap may be NULL; a non-NULL bitmap needs
+ * len_bytes >= ceil(n / 8), else EIS_EINVAL.  Synchronous. */
+int eis_classify(eis_ctx *ctx, uint64_t a, uint64_t b, uint8_t *sqfree_bits,
+                 uint8_t *eis_bits, size_t len_bytes, uint64_t *n_sqfree, uint64_t *n_eis);
+
+/* Same as eis_classify, with DEVICE outputs, enqueued on the HIP stream
+ * `hip_stream` (a hipStream_t; NULL = the context's own stream).
+ * d_sqfree_bits / d_eis_bits: device buffers of ceil(n/8) bytes or NULL.
+ * d_counts2: device uint64_t[2] receiving {n_sqfree, n_eis}, or NULL.
+ * Returns after enqueueing; results are valid once the stream reaches them.
+ * Step-budget overruns are reported by the next synchronous call on this
+ * context, or by eis_last_error. */
+int eis_classify_async(eis_ctx *ctx, uint64_t a, uint64_t b, void *d_sqfree_bits,
+                       void *d_eis_bits, uint64_t *d_counts2, void *hip_stream);
+
+/* Status of the last completed asynchronous call (EIS_OK or EIS_EINTERNAL);
+ * synchronises the context's stream. */
+int eis_last_error(eis_ctx *ctx);
+
+/* n ranges [a[k], b[k]) counted in one batched launch sequence: the sieve of
+ * every range, then ONE persistent walk kernel over a global queue ordered
+ * by estimated cost, then the counts (Section 1 counts, per range).
+ * n_sqfree / n_eis: caller-owned host arrays of n entries (either NULL).
+ * Overlapping ranges are allowed and are counted independently. */
+int eis_count_batch(eis_ctx *ctx, const uint64_t *a, const uint64_t *b, size_t n,
+                    uint64_t *n_sqfree, uint64_t *n_eis);
+
+/* ----- Serving (continuous batching of range-count queries) ----------- */
+
+/* Queue the count of [a, b).  *ticket receives a handle for eis_wait.
+ * EIS_EBUSY when serve_slots requests are already queued or running, or
+ * when the request alone exceeds mem_budget_bytes (never admissible). */
+int eis_submit(eis_ctx *ctx, uint64_t a, uint64_t b, uint64_t *ticket);
+
+/* Wait up to timeout_us microseconds (< 0 = forever) for a ticket.  On
+ * EIS_OK the counts are written and the ticket is retired.  EIS_ETIMEDOUT
+ * leaves it pending; EIS_ECANCELED / EIS_EINTERNAL retire it. */
+int eis_wait(eis_ctx *ctx, uint64_t ticket, int64_t timeout_us, uint64_t *n_sqfree,
+             uint64_t *n_eis);
+
+/* Cancel a pending ticket (its eis_wait returns EIS_ECANCELED).  A request
+ * whose work is already on the device finishes there and is discarded. */
+int eis_cancel(eis_ctx *ctx, uint64_t ticket);
+
+/* Counters since eis_create. */
+int eis_get_stats(eis_ctx *ctx, eis_stats *out);
+
+/* Static text for a status code. */
+const char *eis_strerror(int status);
+
+/* Library ABI version (EIS_ABI_VERSION). */
+int eis_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIS_H */

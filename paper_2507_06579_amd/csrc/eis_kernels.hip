@@ -1,0 +1,359 @@
+// eis_kernels.hip -- gfx950 kernels of the Eisenstein-discriminant search.
+//
+// Pipeline of one pass (at most kPassCandidates candidates d_i = d0 + 8 i):
+//   k_prime_offsets : for every odd prime p <= sqrt(b-1), the first candidate
+//                     index i with p^2 | d0 + 8 i
+//   k_sieve         : squarefree sieve over d = 5 (mod 8) (Section 1, the set
+//                     D), one LDS bitmap per 32768-candidate segment, then
+//                     compaction of the survivors into a work list
+//   k_walk_baby     : one d per lane, reduction steps rho (Appendix A) with the
+//                     generator carried in (O_K/2O_K)^* ~ Z/3 and the
+//                     half-period symmetry exit; persistent, lanes refilled
+//                     from a global queue as their walks end
+//   k_popcount_add  : pi_D and pi_E of the pass
+//
+// Everything on the result path is integer-exact.  The walk keeps its
+// quantities (all integers below 2^22 for d < 10^12) in fp32 registers, where
+// adds, subtracts and fused multiply-adds of such integers are exact, and
+// takes the partial quotient from a reciprocal estimate that is corrected to
+// the exact floor.
+#include "eis_internal.h"
+
+namespace eis {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__global__ void k_zero_u32(u32 *p, u64 n)
+{
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 stride = (u64)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream)
+{
+    if (nwords == 0) return hipSuccess;
+    u64 blocks = (nwords + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_u32, dim3((u32)blocks), dim3(256), 0, stream, p, nwords);
+    return hipGetLastError();
+}
+
+// a * b mod m for a, b < m < 2^42: the quotient estimate from fp64 is off by
+// at most one, and the wrapped 64-bit difference a*b - q*m is then exact.
+__device__ __forceinline__ u64 mulmod_small(u64 a, u64 b, u64 m)
+{
+    double q = ((double)a * (double)b) / (double)m;
+    u64 qi = (u64)q;
+    long long r = (long long)(a * b - qi * m);
+    while (r < 0) r += (long long)m;
+    while (r >= (long long)m) r -= (long long)m;
+    return (u64)r;
+}
+
+// ---------------------------------------------------------------------------
+// k_prime_offsets: roff[k] = i_k, the least i >= 0 with m_k | d0 + 8 i, i.e.
+// i = (-d0) * 8^{-1} (mod m_k).
+// ---------------------------------------------------------------------------
+__global__ void k_prime_offsets(const PrimeEntry *__restrict__ primes, u32 nprimes, u64 d0,
+                                u64 *__restrict__ roff)
+{
+    u32 k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nprimes) return;
+    u64 m = primes[k].m;
+    u64 r = d0 % m;
+    u64 neg = r ? m - r : 0;
+    roff[k] = mulmod_small(neg, primes[k].inv8, m);
+}
+
+hipError_t launch_prime_offsets(const PrimeEntry *primes, u32 nprimes, u64 d0, u64 *roff,
+                                hipStream_t stream)
+{
+    if (nprimes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prime_offsets, dim3((nprimes + 255) / 256), dim3(256), 0, stream,
+                       primes, nprimes, d0, roff);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_sieve: one workgroup per segment of kSegCandidates candidates.
+//   1. LDS bitmap <- all candidates of the segment that lie below n
+//   2. strike i = roff (mod m) for every prime square m.  The first `nsmall`
+//      primes (m < 4096, many strikes per segment) are spread over all
+//      threads; each larger prime belongs to one thread.
+//   3. write the bitmap words, and append the surviving indices to the work
+//      list (block-wide prefix sum, one global atomic per segment).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ primes,
+                                               const u64 *__restrict__ roff, u32 nprimes,
+                                               u32 nsmall, u32 n, u32 *__restrict__ sq_words,
+                                               u32 *__restrict__ list,
+                                               PassCounters *__restrict__ ctr)
+{
+    __shared__ u32 bits[kSegWords];
+    __shared__ u32 scan[256];
+    __shared__ u32 base_sh;
+    const u32 tid = threadIdx.x;
+    const u32 seg0 = blockIdx.x * kSegCandidates;  // first candidate index of the segment
+    const u32 segn = min(kSegCandidates, n - seg0);
+
+    for (u32 w = tid; w < kSegWords; w += 256) {
+        u32 lo = w * 32;
+        u32 v;
+        if (lo + 32 <= segn) v = 0xffffffffu;
+        else if (lo >= segn) v = 0u;
+        else v = (1u << (segn - lo)) - 1u;
+        bits[w] = v;
+    }
+    __syncthreads();
+
+    // small prime squares: all threads share each prime's strikes
+    for (u32 k = 0; k < nsmall; k++) {
+        u32 m = (u32)primes[k].m;
+        u32 r = (u32)roff[k];
+        u32 off = seg0 % m;
+        u32 first = (r >= off) ? r - off : r + m - off;  // (r - seg0) mod m
+        for (u32 i = first + tid * m; i < segn; i += 256 * m)
+            atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+    }
+    // larger prime squares: one prime per thread
+    for (u32 k = nsmall + tid; k < nprimes; k += 256) {
+        const u64 m = primes[k].m;
+        const u64 r = roff[k];
+        if (m >= (u64)n) {
+            // at most one strike in the whole pass: index r itself
+            if (r >= seg0 && r < (u64)seg0 + segn) {
+                u32 i = (u32)r - seg0;
+                atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+            }
+            continue;
+        }
+        // here m < n < 2^31, so 32-bit arithmetic is exact
+        const u32 m32 = (u32)m, r32 = (u32)r;
+        const u32 off = seg0 % m32;
+        u32 first = (r32 >= off) ? r32 - off : r32 + m32 - off;  // (r - seg0) mod m
+        for (u32 i = first; i < segn; i += m32)
+            atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
+    }
+    __syncthreads();
+
+    // write bitmap words and compact the survivors
+    const u32 wbase = seg0 / 32;
+    u32 cnt = 0;
+    u32 wv[kSegWords / 256];
+#pragma unroll
+    for (u32 t = 0; t < kSegWords / 256; t++) {
+        u32 w = tid * (kSegWords / 256) + t;
+        wv[t] = bits[w];
+        cnt += __popc(wv[t]);
+    }
+    for (u32 w = tid; w < kSegWords; w += 256) {
+        if (w * 32 < segn) sq_words[wbase + w] = bits[w];
+    }
+    scan[tid] = cnt;
+    __syncthreads();
+    for (u32 off = 1; off < 256; off <<= 1) {
+        u32 v = (tid >= off) ? scan[tid - off] : 0u;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    if (tid == 255) base_sh = atomicAdd(&ctr->list_len, scan[255]);
+    __syncthreads();
+    u32 pos = base_sh + scan[tid] - cnt;
+#pragma unroll
+    for (u32 t = 0; t < kSegWords / 256; t++) {
+        u32 v = wv[t];
+        u32 ibase = seg0 + (tid * (kSegWords / 256) + t) * 32;
+        while (v) {
+            u32 b = __ffs(v) - 1;
+            v &= v - 1;
+            list[pos++] = ibase + b;
+        }
+    }
+}
+
+hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, u32 nprimes, u32 nsmall,
+                        u32 n, u32 *sq_words, u32 *list, PassCounters *ctr, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    u32 nseg = (n + kSegCandidates - 1) / kSegCandidates;
+    hipLaunchKernelGGL(k_sieve, dim3(nseg), dim3(256), 0, stream, primes, roff, nprimes, nsmall,
+                       n, sq_words, list, ctr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Baby-step walk.
+//
+// Ideal (theta_{j+1}) = [Q_j/2, (P_j + sqrt d)/2], (P_0, Q_0) = (1, 2), and rho:
+//   q = floor((P + sqrt d)/Q) = floor((P + s)/Q),  s = floor(sqrt d)
+//   P' = q Q - P,   Q' = Q_prev + q (P - P')        (= (d - P'^2)/Q)
+// The relative generator (P' + sqrt d)/Q has residue log 1 in F_4^* ~ Z/3
+// when P' = 1 (mod 4) and log 2 when P' = 3 (mod 4) (Q/2 is odd and 2 is
+// inert), so S_j = sum_{i<=j} (1 + bit1(P_i)) is log theta_{j+1} (mod 3).
+// Half-period exit (the symmetry of the cycle under conjugation, which acts
+// on F_4 as the Frobenius, log -> -log):
+//   Q_j = Q_{j-1}          -> log eps = S_j + S_{j-1}
+//   P_j = P_{j-1}, j >= 2  -> log eps = 2 S_{j-1}
+// and d is Eisenstein iff log eps = 0 (mod 3).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ u64 isqrt_u64(u64 d)
+{
+    u64 s = (u64)sqrt((double)d);
+    while (s * s > d) s--;
+    while ((s + 1) * (s + 1) <= d) s++;
+    return s;
+}
+
+__device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
+{
+    if (eis) atomicOr(&eis_words[idx >> 5], 1u << (idx & 31));
+}
+
+// Iterations of the inner loop between two checks of the step budget.
+constexpr u32 kInnerChunk = 1u << 14;
+
+__global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
+{
+    const u32 n = p.ctr->list_len;
+    // inner-loop length between budget checks; a walk that has not ended
+    // after max_steps (rounded up to a multiple of K) is abandoned and counted
+    const u32 K = min(kInnerChunk, max(p.max_steps, 1u));
+    float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
+    u32 S = 0, j = 0, idx = 0;
+    bool active = false, exhausted = false;
+    u64 my_steps = 0, my_refills = 0;
+
+    for (;;) {
+        // ---- refill lanes without a walk --------------------------------
+        for (;;) {
+            bool want = !active && !exhausted;
+            if (!__any(want)) break;
+            if (want) {
+                u32 k = atomicAdd(&p.ctr->work_next, 1u);
+                if (k >= n) {
+                    exhausted = true;
+                } else {
+                    idx = p.list[k];
+                    my_refills++;
+                    u64 d = p.d0 + 8ull * idx;
+                    u64 si = isqrt_u64(d);
+                    // first step from (P_0, Q_0) = (1, 2), in 64-bit integers
+                    u64 P1 = ((si + 1) >> 1) * 2 - 1;
+                    u64 Q1 = (d - P1 * P1) >> 1;
+                    u32 S1 = 1u + (u32)((P1 >> 1) & 1);
+                    my_steps += 1;
+                    if (Q1 == 2) {
+                        // Q_1 = Q_0: log eps = S_1 + S_0 = S_1
+                        emit_flag(p.eis_words, idx, S1 % 3u == 0u);
+                    } else {
+                        s = (float)si;
+                        P = (float)P1;
+                        Q = (float)Q1;
+                        Qp = 2.f;
+                        S = S1;
+                        j = 1;
+                        active = true;
+                    }
+                }
+            }
+        }
+        if (!__any(active)) break;
+
+        if (active) {
+            bool ex;
+            u32 k = 0;
+            do {
+                const float t = P + s;
+                const float rq = __builtin_amdgcn_rcpf(Q);
+                // floor(t/Q) - 1 <= q0 <= floor(t/Q): the estimate t*rq is
+                // within 0.16 of t/Q for t/Q < 2^20
+                const float q0 = floorf(fmaf(t, rq, -0.5f));
+                const float r = fmaf(-q0, Q, t);
+                const float q = (r >= Q) ? q0 + 1.f : q0;
+                const float Pn = fmaf(q, Q, -P);
+                const float Qn = fmaf(q, P - Pn, Qp);
+                S += 1u + (((u32)Pn >> 1) & 1u);
+                ex = (Qn == Q) | (Pn == P);
+                Qp = Q;
+                Q = Qn;
+                P = Pn;
+                ++k;
+            } while (!__any(ex) && k < K);
+            j += k;
+            if (ex) {
+                const u32 rj = 1u + (((u32)P >> 1) & 1u);
+                // Q-rule first (it also covers the tie at the period's end)
+                const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
+                emit_flag(p.eis_words, idx, v % 3u == 0u);
+                my_steps += j - 1;
+                active = false;
+            } else if (j > p.max_steps) {
+                atomicAdd(&p.ctr->err_count, 1u);
+                my_steps += j - 1;
+                active = false;
+            }
+        }
+    }
+    // wave-level reduction of the counters, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        my_steps += __shfl_down(my_steps, off, 64);
+        my_refills += __shfl_down(my_refills, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
+        atomicAdd(&p.ctr->refills, (unsigned long long)my_refills);
+    }
+}
+
+hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream)
+{
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk_baby, dim3(grid), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+int walk_baby_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_baby, 256, 0) != hipSuccess)
+        return 4;
+    return nb > 0 ? nb : 1;
+}
+
+// ---------------------------------------------------------------------------
+// k_popcount_add: *out += number of set bits in words[0 .. nwords)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_popcount_add(const u32 *__restrict__ words, u64 nwords,
+                                                      unsigned long long *out)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long c = 0;
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 stride = (u64)gridDim.x * blockDim.x;
+    for (; i < nwords; i += stride) c += __popc(words[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(out, t);
+    }
+}
+
+hipError_t launch_popcount_add(const u32 *words, u64 nwords, unsigned long long *out,
+                               hipStream_t stream)
+{
+    if (nwords == 0) return hipSuccess;
+    u64 blocks = (nwords + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_popcount_add, dim3((u32)blocks), dim3(256), 0, stream, words, nwords,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace eis

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Flags are integers, so every comparison is exact (tolerance 0).  Small
+ranges are compared bit for bit over the whole range; full-size ranges are
+compared on sampled candidates (the oracle classifies each one by itself)
+and by their counts against the paper's Table 1 and the Moebius count.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_06579_amd as eis
+from paper_2507_06579_amd import workloads
+from _bits import bit, unpack
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+METHODS = [eis.Method.BABY]
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", params=METHODS, ids=lambda m: eis.Method(m).name)
+def ctx(request):
+    c = eis.Context(method=request.param)
+    yield c
+    c.close()
+
+
+def _compare_full(ctx, a, b):
+    _say(f"full compare [{a}, {b}) method={ctx_method(ctx)}")
+    sq, eb, ns, ne = ctx.eis_classify(a, b)
+    ref = oracle.classify_range(a, b)
+    n = eis.eis_num_candidates(a, b)
+    nb = (n + 7) // 8
+    assert ns == ref["n_sqfree"]
+    assert ne == ref["n_eis"]
+    if n:
+        np.testing.assert_array_equal(unpack(sq, n), unpack(ref["sq_bits"], n))
+        np.testing.assert_array_equal(unpack(eb, n), unpack(ref["eis_bits"], n))
+        # unused high bits of the last byte are zero
+        assert sq[nb - 1] >> (n - 8 * (nb - 1)) == 0 if n % 8 else True
+        assert eb[nb - 1] >> (n - 8 * (nb - 1)) == 0 if n % 8 else True
+
+
+def ctx_method(ctx):
+    return getattr(ctx, "_method_name", "?")
+
+
+def _compare_sampled(ctx, a, b, k, seed):
+    _say(f"sampled compare [{a}, {b}) k={k}")
+    sq, eb, ns, ne = ctx.eis_classify(a, b)
+    n = eis.eis_num_candidates(a, b)
+    d0 = eis.eis_first_candidate(a)
+    idx = workloads.sample_indices(n, k, seed)
+    ds = [d0 + 8 * int(i) for i in idx]
+    insq = [oracle.is_squarefree_trial(d) for d in ds]
+    for i, s in zip(idx, insq):
+        assert bit(sq, int(i)) == int(s), d0 + 8 * int(i)
+    members = [d for d, s in zip(ds, insq) if s]
+    flags, _ = oracle.classify_list(members)
+    j = 0
+    for i, s in zip(idx, insq):
+        if s:
+            assert bit(eb, int(i)) == int(flags[j]), d0 + 8 * int(i)
+            j += 1
+        else:
+            assert bit(eb, int(i)) == 0
+    assert ns == oracle.mobius_count(a, b)
+    # eis is a subset of sqfree
+    assert not np.any(eb & ~sq)
+    return ns, ne
+
+
+def test_small_config_full_bitmap(ctx):
+    a, b = workloads.SMALL
+    _compare_full(ctx, a, b)
+
+
+@pytest.mark.parametrize("a,b", [(5, 6), (13, 14), (21, 22), (0, 5), (6, 13), (5, 5), (7, 3),
+                                 (0, 1000), (1901, 1902), (7053, 7054), (1234567, 1239999),
+                                 (999_999_000, 1_000_001_001)])
+def test_edges_and_ragged(ctx, a, b):
+    _compare_full(ctx, a, b)
+
+
+def test_mid_prefix_full_bitmap(ctx):
+    a = workloads.MID[0]
+    _compare_full(ctx, a, a + 400_000)
+
+
+def test_mid_config_sampled(ctx):
+    a, b = workloads.MID
+    _compare_sampled(ctx, a, b, 3000, seed=11)
+
+
+def test_large_config_table1_and_sampled(ctx):
+    # Table 1: #E in [10^11 - 10^8, 10^11] = 3,345,503
+    with open(os.path.join(GOLDEN, "paper_pins.json")) as f:
+        w = json.load(f)["table1_windows"][3]
+    a, b = workloads.LARGE
+    ns, ne = _compare_sampled(ctx, a, b, 600, seed=12)
+    assert ne == w["count"]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_table1_windows(ctx, k):
+    with open(os.path.join(GOLDEN, "paper_pins.json")) as f:
+        w = json.load(f)["table1_windows"][k]
+    _say(f"table-1 window {k}: [{w['a']}, {w['b']})")
+    ns, ne = ctx.eis_count(w["a"], w["b"])
+    assert ne == w["count"]
+    assert ns == oracle.mobius_count(w["a"], w["b"])
+
+
+def test_max_height_sampled(ctx):
+    b = eis.EIS_MAX_D
+    _compare_sampled(ctx, b - 200_000, b, 60, seed=13)
+
+
+def test_counts_match_classify_and_are_deterministic(ctx):
+    a, b = 10**10, 10**10 + 3_000_000
+    _say("determinism")
+    r1 = ctx.eis_classify(a, b)
+    r2 = ctx.eis_classify(a, b)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    assert ctx.eis_count(a, b) == (r1[2], r1[3])
+
+
+def test_multi_pass_range(ctx):
+    # more candidates than one pass (2^24): the pass boundary must be seamless
+    a = 3 * 10**9
+    b = a + 8 * (1 << 24) + 8 * 1000 + 3
+    _say("multi-pass")
+    sq, eb, ns, ne = ctx.eis_classify(a, b)
+    assert ns == oracle.mobius_count(a, b)
+    n = eis.eis_num_candidates(a, b)
+    lo = (1 << 24) - 500
+    d0 = eis.eis_first_candidate(a)
+    ref = oracle.classify_range(d0 + 8 * lo, d0 + 8 * (lo + 1000))
+    np.testing.assert_array_equal(unpack(sq, n)[lo:lo + 1000], unpack(ref["sq_bits"], 1000))
+    np.testing.assert_array_equal(unpack(eb, n)[lo:lo + 1000], unpack(ref["eis_bits"], 1000))
+
+
+def test_async_device_buffers(ctx):
+    import torch
+    a, b = 10**8, 10**8 + 2_000_000
+    n = eis.eis_num_candidates(a, b)
+    nb = (n + 7) // 8
+    _say("async device buffers")
+    sq = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    eb = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    cnt = torch.full((2,), 7, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx.eis_classify_async(a, b, sq.data_ptr(), eb.data_ptr(), cnt.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    assert ctx.eis_last_error() == 0
+    hsq, heb, ns, ne = ctx.eis_classify(a, b)
+    assert np.array_equal(sq.cpu().numpy(), hsq)
+    assert np.array_equal(eb.cpu().numpy(), heb)
+    assert cnt.cpu().tolist() == [ns, ne]
+
+
+def test_errors():
+    with eis.Context(method=eis.Method.BABY) as c:
+        with pytest.raises(eis.EisError) as ei:
+            c.eis_count(5, eis.EIS_MAX_D + 1)
+        assert ei.value.status == eis.Status.ERANGE
+        assert c.eis_count(100, 100) == (0, 0)
+        assert c.eis_count(100, 50) == (0, 0)
+
+
+def test_step_budget_overrun_is_an_error_not_a_wrong_bit():
+    # the budget is forced from the host; every lane still exits normally
+    with eis.Context(method=eis.Method.BABY, max_steps_per_d=64) as c:
+        _say("step budget")
+        with pytest.raises(eis.EisError) as ei:
+            c.eis_count(10**9, 10**9 + 100_000)
+        assert ei.value.status == eis.Status.EINTERNAL
+        # a range whose walks all fit in the budget still works
+        assert c.eis_count(5, 200) == (oracle.mobius_count(5, 200),
+                                       oracle.classify_range(5, 200)["n_eis"])
