@@ -94,6 +94,13 @@ def lib():
     if not os.path.exists(_LIB_PATH):
         raise OSError(f"{_LIB_PATH} is missing: build it with "
                       "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # PyTorch ships its own HIP runtime (same soname).  Load it first so that
+    # libeis.so binds to that copy and the process has ONE HIP runtime,
+    # whose device memory and streams both sides then share.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(_LIB_PATH)
     u64, c_int, vp, sz = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
     P = ctypes.POINTER

@@ -14,6 +14,9 @@ SOURCES = ["eis_api.cpp", "eis_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
+    # code object v5: loadable by every HIP runtime in use here (the system
+    # one and the one bundled with PyTorch)
+    "-mcode-object-version=5",
     "-O3",
     "-std=c++17",
     "-fPIC",

@@ -214,6 +214,23 @@ __device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
     if (eis) atomicOr(&eis_words[idx >> 5], 1u << (idx & 31));
 }
 
+// One reduction step from (P, Q) with predecessor Qp to (Pn, Qn); S gains the
+// residue of the relative generator (Pn + sqrt d)/Q.
+__device__ __forceinline__ void baby_step(float s, float P, float Q, float Qp, float &Pn,
+                                          float &Qn, u32 &S)
+{
+    const float t = P + s;
+    const float rq = __builtin_amdgcn_rcpf(Q);
+    // floor(t/Q) - 1 <= q0 <= floor(t/Q): the estimate t*rq is within 0.16
+    // of t/Q for t/Q < 2^20, and the bias -0.5 keeps it on the low side
+    const float q0 = floorf(fmaf(t, rq, -0.5f));
+    const float r = fmaf(-q0, Q, t);
+    const float q = (r >= Q) ? q0 + 1.f : q0;
+    Pn = fmaf(q, Q, -P);
+    Qn = fmaf(q, P - Pn, Qp);
+    S += 1u + (((u32)Pn >> 1) & 1u);
+}
+
 // Iterations of the inner loop between two checks of the step budget.
 constexpr u32 kInnerChunk = 1u << 14;
 
@@ -222,7 +239,7 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
     const u32 n = p.ctr->list_len;
     // inner-loop length between budget checks; a walk that has not ended
     // after max_steps (rounded up to a multiple of K) is abandoned and counted
-    const u32 K = min(kInnerChunk, max(p.max_steps, 1u));
+    const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
     float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
     u32 S = 0, j = 0, idx = 0;
     bool active = false, exhausted = false;
@@ -265,26 +282,37 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
         if (!__any(active)) break;
 
         if (active) {
-            bool ex;
+            // Up to K steps, leaving as soon as any lane of the wave reaches
+            // its exit; the loop control is wave-uniform (scalar branches).
+            // Two steps per iteration, so that the state never needs moves.
             u32 k = 0;
-            do {
-                const float t = P + s;
-                const float rq = __builtin_amdgcn_rcpf(Q);
-                // floor(t/Q) - 1 <= q0 <= floor(t/Q): the estimate t*rq is
-                // within 0.16 of t/Q for t/Q < 2^20
-                const float q0 = floorf(fmaf(t, rq, -0.5f));
-                const float r = fmaf(-q0, Q, t);
-                const float q = (r >= Q) ? q0 + 1.f : q0;
-                const float Pn = fmaf(q, Q, -P);
-                const float Qn = fmaf(q, P - Pn, Qp);
-                S += 1u + (((u32)Pn >> 1) & 1u);
-                ex = (Qn == Q) | (Pn == P);
+            u64 em = 0;
+            bool first_half = false;
+            float P1 = 0.f, Q1 = 0.f;
+            for (;;) {
+                float P2, Q2;
+                baby_step(s, P, Q, Qp, P1, Q1, S);
+                em = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
+                if (em) {
+                    first_half = true;
+                    break;
+                }
+                baby_step(s, P1, Q1, Q, P2, Q2, S);
+                em = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
+                Qp = Q1;
+                Q = Q2;
+                P = P2;
+                k += 2;
+                if (em || k >= K) break;
+            }
+            if (first_half) {
                 Qp = Q;
-                Q = Qn;
-                P = Pn;
-                ++k;
-            } while (!__any(ex) && k < K);
+                Q = Q1;
+                P = P1;
+                k += 1;
+            }
             j += k;
+            const bool ex = (em >> __lane_id()) & 1ull;
             if (ex) {
                 const u32 rj = 1u + (((u32)P >> 1) & 1u);
                 // Q-rule first (it also covers the tie at the period's end)
