@@ -152,6 +152,7 @@ def main():
                    "candidates": n, "members_of_D": n_sq, "pi_E": n_e,
                    "method": args.method},
         "baby_steps_per_s": round(baby / elapsed, 1),
+        "fallbacks_per_step": (st["fallbacks"] - base["fallbacks"]) // args.steps,
         "giant_steps_per_s": round(giant / elapsed, 1),
         "roofline": roofline,
     }

@@ -94,6 +94,7 @@ typedef struct {
     uint64_t baby_steps;       /* rho steps executed on the device */
     uint64_t giant_steps;      /* giant steps (NUCOMP / NUDUPL) executed */
     uint64_t refills;          /* lane refills in the walk kernels */
+    uint64_t fallbacks;        /* d's the giant-step method handed to the plain walk */
     uint64_t requests_done;    /* serving requests completed */
     double last_walk_ms;       /* device time of the last walk launch(es) */
     double last_total_ms;      /* device time of the last whole classify */

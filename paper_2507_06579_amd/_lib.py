@@ -60,6 +60,7 @@ class EisStats(ctypes.Structure):
         ("baby_steps", ctypes.c_uint64),
         ("giant_steps", ctypes.c_uint64),
         ("refills", ctypes.c_uint64),
+        ("fallbacks", ctypes.c_uint64),
         ("requests_done", ctypes.c_uint64),
         ("last_walk_ms", ctypes.c_double),
         ("last_total_ms", ctypes.c_double),

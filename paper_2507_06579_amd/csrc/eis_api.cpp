@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -28,6 +29,13 @@ using namespace eis;
 namespace {
 
 constexpr u64 kDefaultMaxSteps = u64(1) << 28;
+// mu_1 is the distinguished ideal number window_scale * d^(1/4) / 16, about
+// window_scale * d^(1/4) reduction steps from (1).
+constexpr double kDefaultWindowScale = 3.5;
+// Below this height the plain walk is as fast as the giant steps (AUTO).
+constexpr u64 kDefaultInfraMinHeight = 100000000ull;
+// d's per infrastructure batch (dictionaries of one batch are resident).
+constexpr u64 kInfraBatch = u64(1) << 21;
 constexpr u64 kPrimeLimit = 1000000;  // isqrt(EIS_MAX_D - 1) = 999999
 
 // odd primes p <= lim (plain Eratosthenes on the host)
@@ -87,6 +95,22 @@ struct eis_ctx {
     PassCounters *d_ctr = nullptr;
     unsigned long long *d_counts = nullptr;  // {n_sqfree, n_eis}
     u64 bytes_held = 0;
+
+    // infrastructure-method scratch
+    WindowState *d_state = nullptr;
+    unsigned long long *d_lists = nullptr;
+    unsigned long long *d_tables = nullptr;
+    u32 *d_glist = nullptr;
+    u32 *d_q = nullptr;             // per-batch queue heads (3 cache lines)
+    u32 *d_fb_list = nullptr;
+    PassCounters *d_fb_ctr = nullptr;
+    u32 *h_pinned = nullptr;        // pinned host word for the list length
+    u64 infra_batch_cap = 0;        // d's per batch the scratch holds
+    u64 infra_stride_cap = 0;       // dictionary words per d the scratch holds
+    u32 infra_emax_cap = 0;
+    u32 infra_tsize_cap = 0;
+    int window_blocks_per_cu = 1;
+    int giant_blocks_per_cu = 1;
 
     std::mutex stats_mu;
     eis_stats stats{};
@@ -149,8 +173,21 @@ extern "C" void eis_config_default(eis_config *cfg)
     cfg->method = EIS_METHOD_AUTO;
 }
 
+static void free_infra(eis_ctx *c)
+{
+    (void)hipFree(c->d_state);
+    (void)hipFree(c->d_lists);
+    (void)hipFree(c->d_tables);
+    (void)hipFree(c->d_glist);
+    c->d_state = nullptr;
+    c->d_lists = c->d_tables = nullptr;
+    c->d_glist = nullptr;
+    c->infra_batch_cap = c->infra_stride_cap = 0;
+}
+
 static void free_scratch(eis_ctx *c)
 {
+    free_infra(c);
     (void)hipFree(c->d_roff);
     (void)hipFree(c->d_sq_words);
     (void)hipFree(c->d_eis_words);
@@ -168,6 +205,10 @@ extern "C" void eis_destroy(eis_ctx *c)
     (void)hipFree(c->d_primes);
     (void)hipFree(c->d_ctr);
     (void)hipFree(c->d_counts);
+    (void)hipFree(c->d_q);
+    (void)hipFree(c->d_fb_list);
+    (void)hipFree(c->d_fb_ctr);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->ev_walk0) (void)hipEventDestroy(c->ev_walk0);
     if (c->ev_walk1) (void)hipEventDestroy(c->ev_walk1);
     if (c->ev_all0) (void)hipEventDestroy(c->ev_all0);
@@ -198,6 +239,7 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     c->cfg = *cfg;
     c->cfg.tune_cache_path = nullptr;  // not retained beyond the call
     if (c->cfg.max_steps_per_d == 0) c->cfg.max_steps_per_d = kDefaultMaxSteps;
+    if (c->cfg.window_scale == 0.0) c->cfg.window_scale = kDefaultWindowScale;
     if (c->cfg.max_steps_per_d > 0xffff0000ull) c->cfg.max_steps_per_d = 0xffff0000ull;
     c->device = cfg->device;
     c->num_cu = prop.multiProcessorCount;
@@ -237,7 +279,19 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
             rc = EIS_ENOMEM;
             break;
         }
+        if (hipMalloc(&c->d_q, 3 * 64) != hipSuccess ||
+            hipMalloc(&c->d_fb_ctr, sizeof(PassCounters)) != hipSuccess ||
+            hipMalloc(&c->d_fb_list, kPassCandidates * sizeof(u32)) != hipSuccess) {
+            rc = EIS_ENOMEM;
+            break;
+        }
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64, hipHostMallocDefault) != hipSuccess) {
+            rc = EIS_ENOMEM;
+            break;
+        }
         c->walk_blocks_per_cu = walk_baby_blocks_per_cu();
+        c->window_blocks_per_cu = walk_window_blocks_per_cu();
+        c->giant_blocks_per_cu = walk_giant_blocks_per_cu();
     } while (0);
     if (rc != EIS_OK) {
         eis_destroy(c);
@@ -274,43 +328,157 @@ static u32 primes_needed(const eis_ctx *c, u64 dmax)
                  c->primes_host.begin());
 }
 
+static bool use_infra(const eis_ctx *c, u64 d0)
+{
+    if (c->cfg.method == EIS_METHOD_INFRA) return true;
+    if (c->cfg.method == EIS_METHOD_BABY) return false;
+    return d0 >= kDefaultInfraMinHeight;
+}
+
+// Dictionary geometry for heights up to dmax.
+static void infra_geometry(const eis_ctx *c, u64 dmax, u32 &emax, u32 &tsize)
+{
+    double n = c->cfg.window_scale * std::pow((double)dmax, 0.25) / 16.0;
+    u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
+    emain = std::max<u32>(emain, 16);
+    emax = emain + 16;
+    if (emax > 496) emax = 496;
+    // load factor at most 0.5 for the usual count (mu_1 plus a few)
+    tsize = 32;
+    while (tsize < 2 * (emain + 4)) tsize <<= 1;
+}
+
+// Scratch of one infrastructure batch: `batch` d's (rounded up to whole
+// tiles of 64), `emax` list entries and `tsize` table slots each.
+static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
+{
+    const u64 tiles = (batch + 63) / 64;
+    const u64 stride = (u64)emax + tsize;
+    if (c->d_lists && c->infra_batch_cap >= tiles * 64 && c->infra_stride_cap >= stride &&
+        c->infra_emax_cap >= emax && c->infra_tsize_cap >= tsize)
+        return EIS_OK;
+    free_infra(c);
+    const u64 bytes = tiles * 64 * (stride * 8 + sizeof(WindowState) + sizeof(u32));
+    if (c->cfg.mem_budget_bytes && c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
+    if (hipMalloc(&c->d_lists, tiles * 64 * emax * 8) != hipSuccess ||
+        hipMalloc(&c->d_tables, tiles * 64 * tsize * 8) != hipSuccess ||
+        hipMalloc(&c->d_state, tiles * 64 * sizeof(WindowState)) != hipSuccess ||
+        hipMalloc(&c->d_glist, tiles * 64 * sizeof(u32)) != hipSuccess) {
+        free_infra(c);
+        return EIS_ENOMEM;
+    }
+    c->infra_batch_cap = tiles * 64;
+    c->infra_stride_cap = stride;
+    c->infra_emax_cap = emax;
+    c->infra_tsize_cap = tsize;
+    return EIS_OK;
+}
+
+// Walk of the compacted list with the plain method (grid sized to n when n
+// is known on the host, else to the whole device).
+static int enqueue_walk_baby(eis_ctx *c, u64 d0, const u32 *list, PassCounters *ctr, u64 n_hint,
+                             hipStream_t st)
+{
+    WalkParams wp;
+    wp.d0 = d0;
+    wp.list = list;
+    wp.ctr = ctr;
+    wp.eis_words = c->d_eis_words;
+    wp.max_steps = (u32)c->cfg.max_steps_per_d;
+    u64 want_blocks = (n_hint + 255) / 256;
+    u64 max_blocks = (u64)c->num_cu * (u64)c->walk_blocks_per_cu;
+    u32 grid = (u32)std::max<u64>(1, std::min(want_blocks, max_blocks));
+    HIP_TRY(launch_walk_baby(wp, grid, st));
+    return EIS_OK;
+}
+
 // Enqueue one pass: candidates d0 + 8 i, i < n (n <= kPassCandidates).
 // Bitmaps land in c->d_sq_words / c->d_eis_words; counts are added to
-// counts[0..1].
+// counts[0..1].  The infrastructure method reads the list length back to
+// the host once per pass, to size its batches.
 static int enqueue_pass(eis_ctx *c, u64 d0, u32 n, unsigned long long *counts, hipStream_t st)
 {
     const u64 nwords = (n + 31) / 32;
     const u64 dmax = d0 + 8ull * (n - 1);
     const u32 np = primes_needed(c, dmax);
     HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctr), sizeof(PassCounters) / 4, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_fb_ctr), sizeof(PassCounters) / 4, st));
     HIP_TRY(launch_zero_u32(c->d_eis_words, nwords, st));
     HIP_TRY(launch_prime_offsets(c->d_primes, np, d0, c->d_roff, st));
     HIP_TRY(launch_sieve(c->d_primes, c->d_roff, np, std::min(c->nsmall, np), n, c->d_sq_words,
                          c->d_list, c->d_ctr, st));
-    WalkParams wp;
-    wp.d0 = d0;
-    wp.list = c->d_list;
-    wp.ctr = c->d_ctr;
-    wp.eis_words = c->d_eis_words;
-    wp.max_steps = (u32)c->cfg.max_steps_per_d;
-    u64 want_blocks = ((u64)n + 255) / 256;
-    u64 max_blocks = (u64)c->num_cu * (u64)c->walk_blocks_per_cu;
-    u32 grid = (u32)std::max<u64>(1, std::min(want_blocks, max_blocks));
+    u64 launches = 6;
     HIP_TRY(hipEventRecord(c->ev_walk0, st));
-    HIP_TRY(launch_walk_baby(wp, grid, st));
+    if (!use_infra(c, d0)) {
+        int rc = enqueue_walk_baby(c, d0, c->d_list, c->d_ctr, n, st);
+        if (rc != EIS_OK) return rc;
+        launches += 1;
+    } else {
+        HIP_TRY(hipMemcpyAsync(c->h_pinned, &c->d_ctr->list_len, sizeof(u32), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const u64 nd = *c->h_pinned;
+        u32 emax, tsize;
+        infra_geometry(c, dmax, emax, tsize);
+        const u64 batch = std::min<u64>(std::max<u64>(nd, 1), kInfraBatch);
+        int rc = ensure_infra(c, batch, emax, tsize);
+        if (rc != EIS_OK) return rc;
+        InfraParams ip;
+        ip.d0 = d0;
+        ip.list = c->d_list;
+        ip.ctr = c->d_ctr;
+        ip.win_next = c->d_q;
+        ip.giant_len = c->d_q + 16;
+        ip.giant_next = c->d_q + 32;
+        ip.giant_list = c->d_glist;
+        ip.fb_list = c->d_fb_list;
+        ip.fb_ctr = c->d_fb_ctr;
+        ip.state = c->d_state;
+        ip.lists = c->d_lists;
+        ip.tables = c->d_tables;
+        ip.emax = emax;
+        ip.tsize = tsize;
+        ip.window_scale = (float)c->cfg.window_scale;
+        ip.max_steps = (u32)c->cfg.max_steps_per_d;
+        ip.max_giants = 1u << 20;
+        ip.eis_words = c->d_eis_words;
+        const u64 max_win = (u64)c->num_cu * (u64)c->window_blocks_per_cu;
+        const u64 max_giant = (u64)c->num_cu * (u64)c->giant_blocks_per_cu;
+        for (u64 k0 = 0; k0 < nd; k0 += batch) {
+            const u64 k1 = std::min<u64>(nd, k0 + batch);
+            ip.k0 = (u32)k0;
+            ip.k1 = (u32)k1;
+            const u64 nb = k1 - k0;
+            HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
+            const u32 gw = (u32)std::max<u64>(1, std::min((nb + 255) / 256, max_win));
+            // window waves take tiles of 64 d's
+            HIP_TRY(launch_walk_window(ip, gw, st));
+            HIP_TRY(launch_build_tables(ip, (u32)nb, st));
+            const u32 gg = (u32)std::max<u64>(1, std::min((nb + 255) / 256, max_giant));
+            HIP_TRY(launch_walk_giant(ip, gg, st));
+            launches += 4;
+        }
+        // d's that left the giant-step method: the plain walk, exact for all d
+        rc = enqueue_walk_baby(c, d0, c->d_fb_list, c->d_fb_ctr, 256ull * (u64)c->num_cu, st);
+        if (rc != EIS_OK) return rc;
+        launches += 1;
+    }
     HIP_TRY(hipEventRecord(c->ev_walk1, st));
     HIP_TRY(launch_popcount_add(c->d_sq_words, nwords, counts + 0, st));
     HIP_TRY(launch_popcount_add(c->d_eis_words, nwords, counts + 1, st));
     std::lock_guard<std::mutex> lk(c->stats_mu);
-    c->stats.launches += 7;
+    c->stats.launches += launches + 2;
     return EIS_OK;
 }
 
 // Read the per-pass counters after the stream has finished the pass.
 static int collect_pass(eis_ctx *c)
 {
-    PassCounters h;
+    PassCounters h, f;
     if (hipMemcpy(&h, c->d_ctr, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
+    if (hipMemcpy(&f, c->d_fb_ctr, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
+    h.baby_steps += f.baby_steps;
+    h.refills += f.refills;
+    h.err_count += f.err_count;
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
     std::lock_guard<std::mutex> lk(c->stats_mu);
@@ -319,6 +487,7 @@ static int collect_pass(eis_ctx *c)
     c->stats.baby_steps += h.baby_steps;
     c->stats.giant_steps += h.giant_steps;
     c->stats.refills += h.refills;
+    c->stats.fallbacks += f.list_len;
     return h.err_count ? EIS_EINTERNAL : EIS_OK;
 }
 

@@ -1,0 +1,402 @@
+// eis_giant.h -- device arithmetic of the infrastructure giant step
+// (Appendix A: Algorithms NUCOMP, NUDUPL and NUCOMPchoose, the reduction map
+// rho on non-reduced ideals, and the residue of gamma in (O_K/2O_K)^*).
+//
+// Number representation.  Form coefficients and every intermediate of
+// NUCOMP/NUDUPL are integers carried in fp64, where +, -, * and fma are
+// exact while the exact result stays below 2^53 in magnitude.  Every product
+// and every multi-term sum is checked against 2^52 (so that sums of two
+// checked values are exact too), and every division the algorithms declare
+// exact is checked for a zero remainder.  Any failed check sets `bad`; the
+// caller then discards the giant-step result for that d and classifies it
+// with the plain reduction walk instead.  The reduction after the
+// composition uses the division-free form of rho, so it never needs P^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eis_internal.h"
+
+namespace eis {
+
+typedef long long i64;
+
+constexpr double kExactLimit = 4503599627370496.0;  // 2^52
+
+__device__ __forceinline__ void chk(double x, bool &bad) { bad |= !(fabs(x) < kExactLimit); }
+
+// 1/b to nearly full fp64 precision: hardware estimate + one Newton step.
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    return fma(fma(-b, r, 1.0), r, r);
+}
+
+// floor(a / b) for integers |a| < 2^52, 0 < b < 2^52.
+__device__ __forceinline__ double fl_div(double a, double b)
+{
+    double q = floor(a * rcp_nr(b));
+    double r = fma(-q, b, a);  // exact: |r| < 2b
+    if (r < 0.0) q -= 1.0;
+    else if (r >= b) q += 1.0;
+    return q;
+}
+
+// a mod m in [0, m) for integers |a| < 2^52, 0 < m < 2^52.
+__device__ __forceinline__ double nn_mod(double a, double m)
+{
+    double q = fl_div(a, m);
+    return fma(-q, m, a);
+}
+
+// a / b where the quotient is an exact integer of magnitude < 2^50; the
+// remainder is checked.
+__device__ __forceinline__ double ex_div(double a, double b, bool &bad)
+{
+    double q = rint(a * rcp_nr(b));
+    bad |= (fma(-q, b, a) != 0.0);
+    return q;
+}
+
+// Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for |a|, |b| < 2^52.
+__device__ __forceinline__ void xgcd(double a, double b, double &x, double &y, double &g)
+{
+    const double sa = a < 0.0 ? -1.0 : 1.0, sb = b < 0.0 ? -1.0 : 1.0;
+    a = fabs(a);
+    b = fabs(b);
+    double x0 = 1.0, x1 = 0.0, y0 = 0.0, y1 = 1.0;
+    while (b != 0.0) {
+        const double q = fl_div(a, b);
+        const double r = fma(-q, b, a);
+        a = b;
+        b = r;
+        double t = fma(-q, x1, x0);
+        x0 = x1;
+        x1 = t;
+        t = fma(-q, y1, y0);
+        y0 = y1;
+        y1 = t;
+    }
+    g = a;
+    x = x0 * sa;
+    y = y0 * sb;
+}
+
+struct Form {
+    double u, v, w;
+};
+
+// gamma = (A + B sqrt d) / C
+struct Gamma {
+    double A, B, C;
+};
+
+// Partial Euclid shared by NUCOMP and NUDUPL: run while |b_y| > L and b_x != 0
+// (both stay non-negative), then flip the signs of b_y and y when the number
+// of steps z is odd.
+__device__ __forceinline__ void partial_euclid(double &bx, double &by, double &x, double &y,
+                                               int &z, double L)
+{
+    x = 1.0;
+    y = 0.0;
+    z = 0;
+    while (fabs(by) > L && bx != 0.0) {
+        const double q = fl_div(by, bx);
+        const double t = fma(-q, bx, by);
+        by = bx;
+        bx = t;
+        const double t2 = fma(-q, x, y);
+        y = x;
+        x = t2;
+        z++;
+    }
+    if (z & 1) {
+        by = -by;
+        y = -y;
+    }
+}
+
+// Algorithm NUCOMP: phi3 = (1/gamma) phi1 phi2, partially reduced with bound L.
+__device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gamma &g,
+                                       bool &bad)
+{
+    if (f1.w < f2.w) {
+        const Form t = f1;
+        f1 = f2;
+        f2 = t;
+    }
+    const double s = ex_div(f1.v + f2.v, 2.0, bad);
+    const double m = f2.v - s;
+    double b, c, F;
+    xgcd(f2.u, f1.u, b, c, F);  // b u2 + c u1 = F
+    double G, Bx, By, Cy, Dy;
+    if (nn_mod(s, F) == 0.0) {
+        G = F;
+        Bx = m * b;
+        chk(Bx, bad);
+        By = ex_div(f1.u, G, bad);
+        Cy = ex_div(f2.u, G, bad);
+        Dy = ex_div(s, G, bad);
+    } else {
+        double x2, y2;
+        xgcd(F, s, x2, y2, G);  // x2 F + y2 s = G
+        const double H = ex_div(F, G, bad);
+        By = ex_div(f1.u, G, bad);
+        Cy = ex_div(f2.u, G, bad);
+        Dy = ex_div(s, G, bad);
+        // l = y2 (b w1 + c w2) mod H, reduced term by term to keep it small
+        const double t1 = nn_mod(b, H) * nn_mod(f1.w, H);
+        const double t2 = nn_mod(c, H) * nn_mod(f2.w, H);
+        const double l = nn_mod(nn_mod(y2, H) * nn_mod(t1 + t2, H), H);
+        const double num = fma(l, By, b * m);
+        chk(b * m, bad);
+        chk(l * By, bad);
+        chk(num, bad);
+        Bx = ex_div(num, H, bad);
+    }
+    double bx = nn_mod(Bx, By), by = By, x, y;
+    int z;
+    partial_euclid(bx, by, x, y, z, L);
+    const double ax = G * x, ay = G * y;
+    double u3, v3, w3;
+    if (z != 0) {
+        const double n1 = fma(Cy, bx, -m * x);
+        chk(Cy * bx, bad);
+        chk(m * x, bad);
+        const double cx = ex_div(n1, By, bad);
+        const double Q1 = by * cx;
+        chk(Q1, bad);
+        const double Q2 = Q1 + m;
+        const double n2 = fma(Dy, bx, -f2.w * x);
+        chk(Dy * bx, bad);
+        chk(f2.w * x, bad);
+        const double dx = ex_div(n2, By, bad);
+        const double Q3 = y * dx;
+        chk(Q3, bad);
+        const double Q4 = Q3 + Dy;
+        const double dy = ex_div(Q4, x, bad);
+        double cy;
+        if (bx != 0.0) {
+            cy = ex_div(Q2, bx, bad);
+        } else {
+            const double n3 = fma(cx, dy, -f1.w);
+            chk(cx * dy, bad);
+            cy = ex_div(n3, dx, bad);
+        }
+        chk(by * cy, bad);
+        chk(ay * dy, bad);
+        chk(bx * cx, bad);
+        chk(ax * dx, bad);
+        u3 = fma(by, cy, -ay * dy);
+        w3 = fma(bx, cx, -ax * dx);
+        v3 = G * (Q3 + Q4) - Q1 - Q2;
+        chk(G * (Q3 + Q4), bad);
+    } else {
+        const double Q1 = Cy * bx;
+        chk(Q1, bad);
+        const double cx = ex_div(Q1 - m, By, bad);
+        const double n2 = fma(bx, Dy, -f2.w);
+        chk(bx * Dy, bad);
+        const double dx = ex_div(n2, By, bad);
+        u3 = by * Cy;
+        chk(bx * cx, bad);
+        chk(G * dx, bad);
+        w3 = fma(bx, cx, -G * dx);
+        v3 = f2.v - 2.0 * Q1;
+    }
+    chk(u3, bad);
+    chk(v3, bad);
+    chk(w3, bad);
+    const double t = 2.0 * u3;
+    chk(x * t, bad);
+    chk(y * v3, bad);
+    g.A = G * fma(x, t, y * v3);
+    g.B = G * y;
+    g.C = t;
+    chk(g.A, bad);
+    f3.u = u3;
+    f3.v = v3;
+    f3.w = w3;
+}
+
+// Algorithm NUDUPL: phi3 = (1/gamma) phi^2, partially reduced with bound L.
+__device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, bool &bad)
+{
+    double x0, y0, G;
+    xgcd(f.u, f.v, x0, y0, G);  // x0 u + y0 v = G
+    const double By = ex_div(f.u, G, bad);
+    const double Dy = ex_div(f.v, G, bad);
+    // B_x = y0 w mod B_y, reduced factor by factor
+    const double Bx = nn_mod(nn_mod(y0, By) * nn_mod(f.w, By), By);
+    double bx = Bx, by = By, x, y;
+    int z;
+    partial_euclid(bx, by, x, y, z, L);
+    const double ax = G * x, ay = G * y;
+    double u3, v3, w3;
+    if (z == 0) {
+        const double n = fma(bx, Dy, -f.w);
+        chk(bx * Dy, bad);
+        const double dx = ex_div(n, By, bad);
+        u3 = by * by;
+        w3 = bx * bx;
+        const double sq = (bx + by) * (bx + by);
+        chk(u3, bad);
+        chk(w3, bad);
+        chk(sq, bad);
+        v3 = f.v - sq + u3 + w3;
+        chk(G * dx, bad);
+        w3 = w3 - G * dx;
+    } else {
+        const double n = fma(bx, Dy, -f.w * x);
+        chk(bx * Dy, bad);
+        chk(f.w * x, bad);
+        const double dx = ex_div(n, By, bad);
+        const double Q1 = dx * y;
+        chk(Q1, bad);
+        double dy = Q1 + Dy;
+        v3 = G * (dy + Q1);
+        chk(v3, bad);
+        dy = ex_div(dy, x, bad);
+        u3 = by * by;
+        w3 = bx * bx;
+        const double sq = (bx + by) * (bx + by);
+        chk(u3, bad);
+        chk(w3, bad);
+        chk(sq, bad);
+        v3 = v3 - sq + u3 + w3;
+        chk(ay * dy, bad);
+        chk(ax * dx, bad);
+        u3 = u3 - ay * dy;
+        w3 = w3 - ax * dx;
+    }
+    chk(u3, bad);
+    chk(v3, bad);
+    chk(w3, bad);
+    const double t = 2.0 * u3;
+    chk(x * t, bad);
+    chk(y * v3, bad);
+    g.A = G * fma(x, t, y * v3);
+    g.B = G * y;
+    g.C = t;
+    chk(g.A, bad);
+    f3.u = u3;
+    f3.v = v3;
+    f3.w = w3;
+}
+
+// Residue of gamma = (A + B sqrt d)/C in F_4^* ~ Z/3 (the localisation of
+// Appendix A: 1/gamma lies in O_{K,2}).  Common factors 2 of A and B are
+// stripped; (A + B sqrt d)/2 with A, B odd reduces to omega (log 1) when
+// A = B (mod 4) and to omega^2 (log 2) otherwise; A + B sqrt d with A, B of
+// mixed parity is odd (log 0).  The power of 2 stripped must equal that of C
+// (gamma is a 2-unit), else `bad`.  Only A, B mod 2^64 matter, and |A|, |B|
+// < 2^52 here, so the int64 images are exact.
+__device__ __forceinline__ u32 gamma_log(const Gamma &g, bool &bad)
+{
+    unsigned long long A = (unsigned long long)(i64)g.A;
+    unsigned long long B = (unsigned long long)(i64)g.B;
+    unsigned long long C = (unsigned long long)(i64)fabs(g.C);
+    if (C == 0 || (A | B) == 0) {
+        bad = true;
+        return 0;
+    }
+    const int vA = __builtin_ctzll(A | B);  // common power of 2
+    A >>= vA;
+    B >>= vA;
+    int v = vA;
+    u32 lg = 0;
+    if ((A & 1) && (B & 1)) {
+        v += 1;
+        lg = (((A - B) & 3) == 0) ? 1u : 2u;
+    }
+    const int vC = __builtin_ctzll(C);
+    bad |= (v != vC);
+    return lg;
+}
+
+// NUCOMPchoose without the small-norm branch: ideals I_k = [u_k/2, (v_k +
+// sqrt d)/2] (u_k = Q, v_k = P) in; the form (u3, v3, w3) and gamma out, with
+// [|2 u3|/2, (-v3 + sqrt d)/2] = (1/gamma) I_1 I_2.  The inputs are reduced
+// ideals: u_k < 2^21 and 0 < v_k < 2^21 for d < 2^40.
+__device__ __forceinline__ void nucomp_choose(double u1, double v1, double u2, double v2,
+                                              double d, double L, Form &f3, Gamma &g,
+                                              bool &bad)
+{
+    u1 = fabs(u1);
+    u2 = fabs(u2);
+    v1 = nn_mod(v1, u1);
+    v2 = nn_mod(v2, u2);
+    const double w1 = ex_div(fma(v1, v1, -d), 2.0 * u1, bad);
+    if (u1 == u2 && v1 == v2) {
+        Form f = {0.5 * u1, -v1, w1};
+        nudupl(f, L, f3, g, bad);
+    } else {
+        const double w2 = ex_div(fma(v2, v2, -d), 2.0 * u2, bad);
+        Form a = {0.5 * u1, -v1, w1};
+        Form b = {0.5 * u2, -v2, w2};
+        nucomp(a, b, L, f3, g, bad);
+    }
+    bad |= (f3.u == 0.0);
+}
+
+// Reduction of the composed ideal.  The ideal of the form (u3, v3, w3) is
+// [Q/2, (P + sqrt d)/2] with Q = |2 u3|, P = -v3 (P matters only mod Q, and
+// the paper's normalisation v = -v3 mod u is not needed here), and its rho
+// predecessor is Qp = (d - P^2)/Q = -2 sgn(u3) w3, which needs no big
+// product.  rho then runs with the division-free recurrence
+//   q = floor((P + sqrt d)/Q),  P' = q Q - P,  Q' = Qp + q (P - P')
+// (Q may be negative on the way: then q = floor((-P - s - 1)/(-Q))), until
+// Q > 0, 0 < P <= s and s - P < Q <= s + P.  Values stay exact fp64
+// integers (checked).  Returns the residue sum of the relative generators
+// (P' + sqrt d)/Q; on return Qp is the predecessor of the reduced (Q, P),
+// and Q Qp = d - P^2 is checked.
+constexpr int kMaxReduce = 128;
+
+__device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, double &Q,
+                                           double &P, double &Qp, bool &bad)
+{
+    Q = fabs(2.0 * f.u);
+    P = -f.v;
+    Qp = (f.u > 0.0) ? -2.0 * f.w : 2.0 * f.w;
+    u32 S = 0;
+    int it = 0;
+    while (!(Q > 0.0 && P > 0.0 && P <= s && s - P < Q && Q <= s + P)) {
+        if (++it > kMaxReduce || Q == 0.0) {
+            bad = true;
+            break;
+        }
+        const double q = (Q > 0.0) ? fl_div(P + s, Q) : fl_div(-P - s - 1.0, -Q);
+        const double qQ = q * Q;
+        chk(qQ, bad);
+        const double Pn = qQ - P;
+        const double t = q * (P - Pn);
+        chk(t, bad);
+        const double Qn = Qp + t;
+        chk(Qn, bad);
+        if (bad) break;
+        S += 1u + (u32)(((long long)Pn >> 1) & 1);
+        Qp = Q;
+        Q = Qn;
+        P = Pn;
+    }
+    bad |= (fma(Q, Qp, P * P) != d);
+    return S;
+}
+
+// Dictionary keys and slots (shared by the table build and the lookups).
+__device__ __forceinline__ unsigned long long dict_key(u32 Q, u32 P)
+{
+    return ((unsigned long long)Q << 32) | ((unsigned long long)P << 2);
+}
+
+__device__ __forceinline__ u32 dict_slot(u32 Q, u32 P, u32 mask)
+{
+    u32 h = (Q * 0x9E3779B1u) ^ (P * 0x85EBCA77u);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 13;
+    return h & mask;
+}
+
+}  // namespace eis

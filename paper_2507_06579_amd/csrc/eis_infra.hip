@@ -1,0 +1,384 @@
+// eis_infra.hip -- the infrastructure method of Appendix A on gfx950.
+//
+// Algorithm "Infrastructure" with the generators carried in
+// (O_K/2O_K)^* ~ Z/3, split into three kernels so that every lane of a wave
+// runs the same phase:
+//
+//   k_walk_window  one d per lane: reduction steps from (1), with the
+//                  half-period symmetry exit; the "distinguished" ideals of
+//                  the walk (Q = 2 mod 64, about one in 16) are appended to
+//                  the d's dictionary list.  mu_1 is the n-th distinguished
+//                  ideal (n = window_scale * d^(1/4) / 16, at least 16); the
+//                  window ends at the first distinguished ideal at least six
+//                  steps after mu_1 (the two extra ideals of the algorithm,
+//                  with margin), and that extension must stay within a
+//                  quarter of mu_1's step count.
+//   k_build_tables one wave per d: the list becomes an open-addressed hash
+//                  table, built in LDS and written out whole.
+//   k_walk_giant   one d per lane, lanes refilled from a queue: mu_k =
+//                  reduce(mu_1 * mu_{k-1}) (NUDUPL for k = 2, then NUCOMP),
+//                  the residue updated with log mu_1 + log mu_{k-1} - log gamma
+//                  + the residues of the reduction steps; then reduction steps
+//                  forward to the first distinguished ideal, which is looked
+//                  up.  A hit gives log eps = log(ideal) - log(stored ideal).
+//
+// Why the distinguished ideals: a dictionary with every window ideal would
+// cost one scattered 8-byte store per reduction step.  With only every 16th
+// ideal stored, the stores are rare and the tables small, at the price of a
+// short walk after every giant step.  Correctness is unchanged: giant steps
+// advance by at most the distance of mu_1 plus the few reduction steps of
+// the composition, so the first giant ideal past a full period lies at most
+// (position of mu_1 + 6) ideals past (1), and the first distinguished ideal
+// at or after it is in the dictionary.  A hit at k = 2 is skipped: when the
+// window is short, mu_2 can land inside the window itself, which reads as a
+// "unit" of distance 0.  From k = 3 on, the giant ideals lie beyond the
+// window's short extension, so a hit is at one regulator, or at two when the
+// skipped k = 2 hit was a true one; log eps^2 = 2 log eps is 0 in Z/3 exactly
+// when log eps is, so the flag is the same.
+//
+// Any arithmetic check that fails (fp64 exactness, exact divisions, step or
+// walk budgets, table overflow) sends the d to the plain walk, which is exact
+// for every d below 10^12.
+#include "eis_giant.h"
+#include "eis_internal.h"
+#include "eis_walk.h"
+
+namespace eis {
+
+// Q = 2 (mod 64): fract(Q / 64) = 1/32 exactly for integer-valued Q < 2^24.
+constexpr float kDpScale = 1.0f / 64.0f;
+constexpr float kDpHit = 2.0f / 64.0f;
+__device__ __forceinline__ bool is_dp(float Q) { return __builtin_amdgcn_fractf(Q * kDpScale) == kDpHit; }
+
+constexpr u32 kTableMax = 1024;     // largest table (slots) per d
+constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
+constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
+constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
+
+__device__ __forceinline__ unsigned long long entry_of(float Q, float P, u32 S)
+{
+    return ((unsigned long long)__float_as_uint(Q) << 32) | (unsigned long long)(__float_as_uint(P) | (S % 3u));
+}
+
+// ---------------------------------------------------------------------------
+// k_walk_window: a wave takes a tile of 64 consecutive batch positions, one d
+// per lane, and keeps it until every lane's window has ended, so that the
+// 64 lanes append to one tile of the list array (tile-interleaved layout:
+// the writes of a wave stay within one small region of memory).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
+{
+    const u32 lane = __lane_id();
+    const u32 nb = p.k1 - p.k0;
+    const u32 ntiles = (nb + 63) / 64;
+    u64 my_steps = 0, my_refills = 0;
+
+    for (;;) {
+        u32 t = 0;
+        if (lane == 0) t = atomicAdd(p.win_next, 1u);
+        t = __shfl(t, 0, 64);
+        if (t >= ntiles) break;
+        const u32 pos = t * 64 + lane;
+        unsigned long long *lst = p.lists + (u64)t * p.emax * 64 + lane;  // entry e at lst[64 e]
+        float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
+        u32 S = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1 = 0, m1q = 0, m1p = 0;
+        bool active = false, to_giant = false, to_plain = false;
+        if (pos < nb) {
+            idx = p.list[p.k0 + pos];
+            my_refills++;
+            const u64 d = p.d0 + 8ull * idx;
+            const u64 si = isqrt_u64(d);
+            const u64 P1 = ((si + 1) >> 1) * 2 - 1;
+            const u64 Q1 = (d - P1 * P1) >> 1;
+            const u32 S1 = 1u + (u32)((P1 >> 1) & 1);
+            j = 1;
+            if (Q1 == 2) {
+                emit_flag(p.eis_words, idx, S1 % 3u == 0u);
+            } else {
+                s = (float)si;
+                P = (float)P1;
+                Q = (float)Q1;
+                S = S1;
+                // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
+                lst[0] = entry_of(2.f, P, 0u);
+                cnt = 1;
+                const float n = p.window_scale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
+                emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
+                if (is_dp(Q)) {
+                    lst[64] = entry_of(Q, P, S);
+                    cnt = 2;
+                }
+                active = true;
+            }
+        }
+        while (active) {
+            float Pn, Qn;
+            baby_step(s, P, Q, Qp, Pn, Qn, S);
+            j++;
+            if (Qn == Q || Pn == P) {
+                // half-period symmetry: the unit is found without giant steps
+                const u32 rj = 1u + (((u32)Pn >> 1) & 1u);
+                const u32 v = (Qn == Q) ? (2u * S - rj) : (2u * (S - rj));
+                emit_flag(p.eis_words, idx, v % 3u == 0u);
+                active = false;
+            } else {
+                Qp = Q;
+                Q = Qn;
+                P = Pn;
+                if (is_dp(Q)) {
+                    lst[(u64)cnt * 64] = entry_of(Q, P, S);
+                    cnt++;
+                    if (cnt == emain) {
+                        m1q = __float_as_uint(Q);
+                        m1p = __float_as_uint(P) | (S % 3u);
+                        j1 = j;
+                    } else if (j1 != 0 && j >= j1 + kExtraSteps) {
+                        // end of the window; its extension past mu_1 must be
+                        // short next to mu_1's own distance (see above)
+                        if (j - j1 <= j1 / 4 && cnt < p.emax) {
+                            WindowState st;
+                            st.q_bits = m1q;
+                            st.p_bits = m1p;
+                            st.count = cnt;
+                            st.idx = idx;
+                            p.state[pos] = st;
+                            to_giant = true;
+                        } else {
+                            to_plain = true;
+                        }
+                        active = false;
+                    }
+                    if (active && (cnt >= p.emax || j > p.max_steps)) {
+                        to_plain = true;
+                        active = false;
+                    }
+                }
+            }
+        }
+        // hand the tile's d's on, one atomic per wave and list
+        if (to_giant) {
+            const u32 gslot = atomicAdd(p.giant_len, 1u);
+            p.giant_list[gslot] = pos;
+        }
+        if (to_plain) {
+            const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+            p.fb_list[f] = idx;
+        }
+        my_steps += j;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        my_steps += __shfl_down(my_steps, off, 64);
+        my_refills += __shfl_down(my_refills, off, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
+        atomicAdd(&p.ctr->refills, (unsigned long long)my_refills);
+    }
+}
+
+hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream)
+{
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk_window, dim3(grid), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+int walk_window_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_window, 256, 0) != hipSuccess)
+        return 4;
+    return nb > 0 ? nb : 1;
+}
+
+// ---------------------------------------------------------------------------
+// k_build_tables: one wave per d that needs giant steps.  Workgroups are
+// numbered so that consecutive ones (d's of the same list tile) run on the
+// same XCD and share its L2: hardware block b goes to XCD b % 8.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
+{
+    __shared__ unsigned long long tab[4][kTableMax];
+    const u32 nblk = gridDim.x, b = blockIdx.x;
+    const u32 xcd = b % 8, q = nblk / 8, r = nblk % 8;
+    const u32 lb = xcd * q + min(xcd, r) + b / 8;  // logical block
+    const u32 wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const u32 w = lb * 4 + wv;
+    const u32 n = *p.giant_len;
+    const bool valid = w < n;
+    const u32 mask = p.tsize - 1;
+    for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0ull;
+    __syncthreads();
+    u32 pos = 0;
+    if (valid) {
+        pos = p.giant_list[w];
+        const unsigned long long *lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
+        const u32 cnt = p.state[pos].count;
+        for (u32 e = lane; e < cnt; e += 64) {
+            const unsigned long long ent = lst[(u64)e * 64];
+            const u32 qb = (u32)(ent >> 32), pb = (u32)ent & ~3u;
+            u32 slot = dict_slot(qb, pb, mask);
+            for (u32 probe = 0; probe < p.tsize; probe++) {
+                const unsigned long long prev = atomicCAS(&tab[wv][slot], 0ull, ent);
+                if (prev == 0ull) break;
+                slot = (slot + 1) & mask;
+            }
+        }
+    }
+    __syncthreads();
+    if (valid) {
+        unsigned long long *tbl = p.tables + (u64)pos * p.tsize;
+        for (u32 t = lane; t < p.tsize; t += 64) tbl[t] = tab[wv][t];
+    }
+}
+
+hipError_t launch_build_tables(const InfraParams &p, u32 nmax, hipStream_t stream)
+{
+    if (nmax == 0) return hipSuccess;
+    if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_tables, dim3((nmax + 3) / 4), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_walk_giant
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
+{
+    const u32 n = *p.giant_len;
+    const u32 mask = p.tsize - 1;
+    // per-lane state
+    u32 idx = 0, ng = 0;
+    double dd = 0.0, sd = 0.0, L = 0.0;
+    float sf = 0.f;
+    double m1Q = 0.0, m1P = 0.0, cQ = 0.0, cP = 0.0;
+    u32 m1S = 0, cS = 0;
+    const unsigned long long *tbl = nullptr;
+    u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
+    bool active = false, exhausted = false;
+    u64 my_giants = 0, my_steps = 0;
+
+    for (;;) {
+        for (;;) {
+            bool want = !active && !exhausted;
+            if (!__any(want)) break;
+            u32 g = n;
+            wave_take(p.giant_next, n, want, g, cbase, cend);
+            if (want) {
+                if (g >= n) {
+                    exhausted = true;
+                } else {
+                    const u32 pos = p.giant_list[g];
+                    const WindowState st = p.state[pos];
+                    idx = st.idx;
+                    const u64 d = p.d0 + 8ull * idx;
+                    const u64 s64 = isqrt_u64(d);
+                    dd = (double)d;
+                    sd = (double)s64;
+                    sf = (float)s64;
+                    L = (double)isqrt_u64(s64);
+                    m1Q = (double)__uint_as_float(st.q_bits);
+                    m1P = (double)__uint_as_float(st.p_bits & ~3u);
+                    m1S = st.p_bits & 3u;
+                    cQ = m1Q;
+                    cP = m1P;
+                    cS = m1S;
+                    tbl = p.tables + (u64)pos * p.tsize;
+                    ng = 0;
+                    active = true;
+                }
+            }
+        }
+        if (!__any(active)) break;
+
+        if (active) {
+            bool bad = false;
+            Form f3;
+            Gamma gm;
+            nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, bad);
+            const u32 lg = gamma_log(gm, bad);
+            double Qk, Pk, Qpk;
+            const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, bad);
+            const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
+            ng++;
+            bool done = false, flag = false;
+            if (!bad) {
+                cQ = Qk;
+                cP = Pk;
+                cS = Sk;
+                // forward to the first distinguished ideal
+                float Qw = (float)Qk, Pw = (float)Pk, Qpw = (float)Qpk;
+                u32 Sw = Sk;
+                u32 w = 0;
+                while (!is_dp(Qw) && w < kWalkLimit) {
+                    float Pn, Qn;
+                    baby_step(sf, Pw, Qw, Qpw, Pn, Qn, Sw);
+                    Qpw = Qw;
+                    Qw = Qn;
+                    Pw = Pn;
+                    w++;
+                }
+                my_steps += w;
+                if (!is_dp(Qw)) {
+                    bad = true;
+                } else if (!bad) {
+                    const u32 qb = __float_as_uint(Qw), pb = __float_as_uint(Pw);
+                    const unsigned long long key = ((unsigned long long)qb << 32) | pb;
+                    u32 slot = dict_slot(qb, pb, mask);
+                    for (u32 probe = 0; probe < p.tsize; probe++) {
+                        const unsigned long long e = tbl[slot];
+                        if (e == 0ull) break;
+                        if ((e & ~3ull) == key) {
+                            // a hit at k = 2 is skipped: mu_2 may lie inside
+                            // the window (a "unit" of distance 0); if it was a
+                            // true hit, the next one is at eps or eps^2, whose
+                            // residues are both 0 or both not
+                            if (ng > 1) {
+                                const u32 St = (u32)e & 3u;
+                                flag = ((Sw + 3u - St) % 3u) == 0u;
+                                done = true;
+                            }
+                            break;
+                        }
+                        slot = (slot + 1) & mask;
+                    }
+                }
+            }
+            if (done) {
+                emit_flag(p.eis_words, idx, flag);
+                my_giants += ng;
+                active = false;
+            } else if (bad || ng >= p.max_giants) {
+                const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                p.fb_list[f] = idx;
+                my_giants += ng;
+                active = false;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        my_steps += __shfl_down(my_steps, off, 64);
+        my_giants += __shfl_down(my_giants, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
+        atomicAdd(&p.ctr->giant_steps, (unsigned long long)my_giants);
+    }
+}
+
+hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream)
+{
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+int walk_giant_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_giant, 256, 0) != hipSuccess)
+        return 2;
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace eis

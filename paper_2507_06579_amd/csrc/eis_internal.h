@@ -48,6 +48,39 @@ struct WalkParams {
     u32 max_steps;                // per-d step budget
 };
 
+// ---- infrastructure method ------------------------------------------------
+// Per-d record written by the window walk for the giant-step walk.
+struct WindowState {
+    u32 q_bits;   // fp32 bit pattern of Q of mu_1 (the giant step)
+    u32 p_bits;   // fp32 bit pattern of P of mu_1, OR its residue (2 bits)
+    u32 count;    // dictionary entries written
+    u32 idx;      // candidate index of d in the pass
+};
+
+struct InfraParams {
+    u64 d0;                     // first candidate of the pass
+    const u32 *list;            // compacted squarefree candidate indices of the pass
+    u32 k0, k1;                 // batch: list positions [k0, k1)
+    PassCounters *ctr;          // pass counters: err_count and step statistics
+    u32 *win_next;              // window-walk queue head (per batch)
+    u32 *giant_list;            // batch-relative positions that need giant steps
+    u32 *giant_len;             // their number
+    u32 *giant_next;            // giant-walk queue head
+    u32 *fb_list;               // candidate indices handed to the plain walk
+    PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
+    WindowState *state;         // per batch position
+    unsigned long long *lists;  // window lists, tile-interleaved: entry e of batch
+                                // position k at ((k / 64) * emax + e) * 64 + k % 64
+    unsigned long long *tables; // hash tables, tsize slots per batch position
+    u32 emax;                   // list capacity per d
+    u32 tsize;                  // table slots per d (power of two)
+    float window_scale;         // mu_1 is the distinguished ideal number
+                                // round(window_scale * d^(1/4) / 16)
+    u32 max_steps;              // per-d budget of reduction steps (window)
+    u32 max_giants;             // per-d budget of giant steps
+    u32 *eis_words;             // output bitmap of the pass
+};
+
 // Launchers (all enqueue on `stream`, never synchronise).
 hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream);
 hipError_t launch_prime_offsets(const PrimeEntry *primes, u32 nprimes, u64 d0, u64 *roff,
@@ -57,6 +90,12 @@ hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, u32 nprimes, 
 hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream);
 hipError_t launch_popcount_add(const u32 *words, u64 nwords, unsigned long long *out,
                                hipStream_t stream);
+
+hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream);
+hipError_t launch_build_tables(const InfraParams &p, u32 nmax, hipStream_t stream);
+hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream);
+int walk_window_blocks_per_cu();
+int walk_giant_blocks_per_cu();
 
 // Occupancy helper: resident 256-thread blocks per CU of the baby walk.
 int walk_baby_blocks_per_cu();

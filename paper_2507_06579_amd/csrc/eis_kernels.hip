@@ -18,6 +18,7 @@
 // takes the partial quotient from a reciprocal estimate that is corrected to
 // the exact floor.
 #include "eis_internal.h"
+#include "eis_walk.h"
 
 namespace eis {
 
@@ -201,39 +202,6 @@ hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, u32 nprimes, 
 // and d is Eisenstein iff log eps = 0 (mod 3).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ u64 isqrt_u64(u64 d)
-{
-    u64 s = (u64)sqrt((double)d);
-    while (s * s > d) s--;
-    while ((s + 1) * (s + 1) <= d) s++;
-    return s;
-}
-
-__device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
-{
-    if (eis) atomicOr(&eis_words[idx >> 5], 1u << (idx & 31));
-}
-
-// One reduction step from (P, Q) with predecessor Qp to (Pn, Qn); S gains the
-// residue of the relative generator (Pn + sqrt d)/Q.
-__device__ __forceinline__ void baby_step(float s, float P, float Q, float Qp, float &Pn,
-                                          float &Qn, u32 &S)
-{
-    const float t = P + s;
-    const float rq = __builtin_amdgcn_rcpf(Q);
-    // floor(t/Q) - 1 <= q0 <= floor(t/Q): the estimate t*rq is within 0.16
-    // of t/Q for t/Q < 2^20, and the bias -0.5 keeps it on the low side
-    const float q0 = floorf(fmaf(t, rq, -0.5f));
-    const float r = fmaf(-q0, Q, t);
-    const float q = (r >= Q) ? q0 + 1.f : q0;
-    Pn = fmaf(q, Q, -P);
-    Qn = fmaf(q, P - Pn, Qp);
-    S += 1u + (((u32)Pn >> 1) & 1u);
-}
-
-// Iterations of the inner loop between two checks of the step budget.
-constexpr u32 kInnerChunk = 1u << 14;
-
 __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
 {
     const u32 n = p.ctr->list_len;
@@ -242,6 +210,7 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
     float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
     u32 S = 0, j = 0, idx = 0;
+    u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool active = false, exhausted = false;
     u64 my_steps = 0, my_refills = 0;
 
@@ -250,8 +219,9 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
         for (;;) {
             bool want = !active && !exhausted;
             if (!__any(want)) break;
+            u32 k = n;
+            wave_take(&p.ctr->work_next, n, want, k, cbase, cend);
             if (want) {
-                u32 k = atomicAdd(&p.ctr->work_next, 1u);
                 if (k >= n) {
                     exhausted = true;
                 } else {

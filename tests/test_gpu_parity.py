@@ -20,7 +20,7 @@ from _bits import bit, unpack
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-METHODS = [eis.Method.BABY]
+METHODS = [eis.Method.BABY, eis.Method.INFRA]
 
 
 def _say(msg):
@@ -31,6 +31,7 @@ def _say(msg):
 @pytest.fixture(scope="module", params=METHODS, ids=lambda m: eis.Method(m).name)
 def ctx(request):
     c = eis.Context(method=request.param)
+    c._method_name = eis.Method(request.param).name
     yield c
     c.close()
 
@@ -188,3 +189,29 @@ def test_step_budget_overrun_is_an_error_not_a_wrong_bit():
         # a range whose walks all fit in the budget still works
         assert c.eis_count(5, 200) == (oracle.mobius_count(5, 200),
                                        oracle.classify_range(5, 200)["n_eis"])
+
+
+def test_methods_agree_on_mid_config():
+    # the plain walk and the giant-step method on the same GPU, whole range
+    a, b = workloads.MID
+    with eis.Context(method=eis.Method.BABY) as cb, eis.Context(method=eis.Method.INFRA) as ci:
+        _say("baby vs infra, mid config")
+        rb = cb.eis_classify(a, b)
+        ri = ci.eis_classify(a, b)
+        st = ci.eis_get_stats()
+    assert np.array_equal(rb[0], ri[0]) and np.array_equal(rb[1], ri[1])
+    assert rb[2:] == ri[2:]
+    assert st["giant_steps"] > 0
+
+
+@pytest.mark.parametrize("scale", [0.5, 1.0, 2.0, 6.0, 12.0])
+def test_window_scale_does_not_change_bits(scale):
+    a, b = 4 * 10**10, 4 * 10**10 + 2_000_000
+    with eis.Context(method=eis.Method.BABY) as cb:
+        ref = cb.eis_classify(a, b)
+    with eis.Context(method=eis.Method.INFRA, window_scale=scale) as ci:
+        _say(f"window scale {scale}")
+        got = ci.eis_classify(a, b)
+        st = ci.eis_get_stats()
+    assert np.array_equal(ref[1], got[1]) and ref[3] == got[3]
+    _say(f"scale {scale}: giant steps {st['giant_steps']} fallbacks {st['fallbacks']}")
