@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="auto", choices=["auto", "baby", "infra"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=100.0)
+    ap.add_argument("--serve-n", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the per-d walks "
@@ -156,6 +159,18 @@ def main():
         "giant_steps_per_s": round(giant / elapsed, 1),
         "roofline": roofline,
     }
+    if not args.no_serving:
+        from paper_2507_06579_amd import serve
+        log(f"serving: {args.serve_n} requests, Poisson at {args.serve_rate} req/s")
+        reqs = workloads.serve_requests(args.serve_n, args.serve_rate)
+        with eis.Context(device=0, serve_slots=256) as sctx:
+            res = serve.run_open_loop(sctx, reqs)
+        srv = serve.summarize(res, reqs)
+        srv["rate_req_s"] = args.serve_rate
+        srv["workload"] = ("range counts [a, a+w), a log-uniform in [1e6, 1e11], "
+                           "w log-uniform in [1e3, 1e7]")
+        out["p99_query_latency_ms"] = srv["p99_ms"]
+        out["serving"] = srv
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(a, b)

@@ -76,6 +76,9 @@ typedef enum {
     EIS_METHOD_AUTO = 2   /* per-range choice by height (autotuned) */
 } eis_method;
 
+/* eis_config.flags bits */
+#define EIS_FLAG_NO_GRAPHS 1u  /* run batched passes as plain launches, not hipGraph replays */
+
 typedef struct {
     int device;                /* HIP device ordinal */
     int method;                /* an eis_method */
@@ -84,7 +87,7 @@ typedef struct {
     double window_scale;       /* giant-step method: baby window = window_scale * d^(1/4)
                                   reduction steps; 0 = autotuned */
     uint32_t serve_slots;      /* serving: max requests in flight; 0 = default (64) */
-    uint32_t flags;            /* reserved, must be 0 */
+    uint32_t flags;            /* EIS_FLAG_* bits; other bits must be 0 */
     const char *tune_cache_path; /* autotuner JSON cache; NULL = no persistence */
 } eis_config;
 
@@ -142,9 +145,12 @@ int eis_classify_async(eis_ctx *ctx, uint64_t a, uint64_t b, void *d_sqfree_bits
  * synchronises the context's stream. */
 int eis_last_error(eis_ctx *ctx);
 
-/* n ranges [a[k], b[k]) counted in one batched launch sequence: the sieve of
- * every range, then ONE persistent walk kernel over a global queue ordered
- * by estimated cost, then the counts (Section 1 counts, per range).
+/* n ranges [a[k], b[k]) counted together (Section 1 counts, per range).
+ * The ranges are cut into pieces, ordered by height (the costliest walks
+ * first) and packed into passes; a pass is one sieve launch over all its
+ * pieces, ONE persistent walk launch over all their members of D (plus the
+ * giant-step launches of the pieces above the method-switch height), and
+ * the counts, replayed from a captured hipGraph.
  * n_sqfree / n_eis: caller-owned host arrays of n entries (either NULL).
  * Overlapping ranges are allowed and are counted independently. */
 int eis_count_batch(eis_ctx *ctx, const uint64_t *a, const uint64_t *b, size_t n,
@@ -153,8 +159,11 @@ int eis_count_batch(eis_ctx *ctx, const uint64_t *a, const uint64_t *b, size_t n
 /* ----- Serving (continuous batching of range-count queries) ----------- */
 
 /* Queue the count of [a, b).  *ticket receives a handle for eis_wait.
- * EIS_EBUSY when serve_slots requests are already queued or running, or
- * when the request alone exceeds mem_budget_bytes (never admissible). */
+ * A server thread (started by the first call) runs passes back to back; each
+ * pass takes the next chunk (at most 2^20 candidates) of every admitted
+ * request, so requests that arrive while others run join the next pass and
+ * a large request does not hold up small ones (continuous batching).
+ * EIS_EBUSY when serve_slots requests are already queued or running. */
 int eis_submit(eis_ctx *ctx, uint64_t a, uint64_t b, uint64_t *ticket);
 
 /* Wait up to timeout_us microseconds (< 0 = forever) for a ticket.  On

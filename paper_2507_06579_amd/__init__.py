@@ -7,6 +7,7 @@ needs it does, and raises if it was not built.
 """
 from ._lib import (  # noqa: F401
     EIS_MAX_D,
+    EIS_FLAG_NO_GRAPHS,
     EisError,
     Context,
     Status,

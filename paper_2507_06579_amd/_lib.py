@@ -13,6 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
+EIS_FLAG_NO_GRAPHS = 1
 
 EXPORTED_SYMBOLS = [
     "eis_config_default", "eis_create", "eis_destroy", "eis_num_candidates",
@@ -152,7 +153,8 @@ class Context:
     """Owns an ``eis_ctx``.  Methods mirror the C calls of the same names."""
 
     def __init__(self, device: int = 0, method: int = Method.AUTO, mem_budget_bytes: int = 0,
-                 max_steps_per_d: int = 0, window_scale: float = 0.0, serve_slots: int = 0):
+                 max_steps_per_d: int = 0, window_scale: float = 0.0, serve_slots: int = 0,
+                 flags: int = 0):
         L = lib()
         cfg = EisConfig()
         L.eis_config_default(ctypes.byref(cfg))
@@ -162,6 +164,7 @@ class Context:
         cfg.max_steps_per_d = max_steps_per_d
         cfg.window_scale = window_scale
         cfg.serve_slots = serve_slots
+        cfg.flags = flags
         h = ctypes.c_void_p()
         _check(L.eis_create(ctypes.byref(cfg), ctypes.byref(h)), "eis_create")
         self._h = h

@@ -1,16 +1,26 @@
 // eis_api.cpp -- host runtime behind include/eis.h.
 //
-// A context owns one HIP stream (default priority), the device prime table
-// of the squarefree sieve, and grow-on-demand scratch buffers.  A range
-// [a, b) is cut into passes of at most kPassCandidates candidates; each pass
-// runs prime offsets -> sieve -> walk -> popcount on the stream.  The serving
-// loop and the batched launch are built on the same pass machinery.
+// Everything is organised in passes.  A pass is a set of at most
+// kMaxSegments segments (ranges or pieces of ranges) with at most
+// kPassCandidates candidates together; one pass is one launch sequence on the
+// context's stream:
+//
+//   zero counters -> prime offsets (all segments) -> sieve (all segments, one
+//   launch) -> plain walk (one persistent launch over every item of the
+//   plain-walk segments) -> giant-step batches (window, table build, giant
+//   walk) over the items of the giant-step segments -> plain walk of the
+//   hand-offs -> per-segment popcounts
+//
+// The segment table lives in device memory, so the launch sequence of a pass
+// depends only on its shape; the batched call replays it from a hipGraph.
+// The single-range calls, the batched call and the serving loop all run on
+// this machinery; a mutex serialises them on the pass buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -19,6 +29,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/eis.h"
@@ -32,11 +43,16 @@ constexpr u64 kDefaultMaxSteps = u64(1) << 28;
 // mu_1 is the distinguished ideal number window_scale * d^(1/4) / 16, about
 // window_scale * d^(1/4) reduction steps from (1).
 constexpr double kDefaultWindowScale = 3.5;
-// Below this height the plain walk is as fast as the giant steps (AUTO).
+// AUTO method: segments starting at or above this height take giant steps.
 constexpr u64 kDefaultInfraMinHeight = 100000000ull;
-// d's per infrastructure batch (dictionaries of one batch are resident).
+// d's per giant-step batch (the dictionaries of one batch are resident).
 constexpr u64 kInfraBatch = u64(1) << 21;
 constexpr u64 kPrimeLimit = 1000000;  // isqrt(EIS_MAX_D - 1) = 999999
+constexpr u32 kPassWords = (u32)(kPassCandidates / 32) + kMaxSegments;
+constexpr u32 kDefaultServeSlots = 64;
+// serving: candidates of one request per pass (a larger request advances a
+// chunk per pass, so that requests behind it are not held up)
+constexpr u64 kServeChunk = u64(1) << 20;
 
 // odd primes p <= lim (plain Eratosthenes on the host)
 std::vector<u32> odd_primes_upto(u64 lim)
@@ -67,9 +83,24 @@ u64 isqrt_host(u64 n)
     return r;
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
+// A segment as the host plans it.
+struct HostSeg {
+    u64 d0;
+    u32 n;
+    u32 slot;      // count slot
+    u32 method;    // 0 plain walk, 1 giant steps
+    u64 dst_bit;   // candidate offset of the segment in the caller's bitmap
+};
+
+struct Request {
+    u64 ticket = 0;
+    u64 d0 = 0, ncand = 0;
+    u64 dispatched = 0;  // candidates handed to passes
+    u64 completed = 0;   // candidates whose pass has finished
+    u64 n_sq = 0, n_eis = 0;
+    int status = EIS_OK;
+    bool cancelled = false;
+    bool finished = false;
 };
 
 }  // namespace
@@ -79,46 +110,68 @@ struct eis_ctx {
     int device = 0;
     int num_cu = 0;
     int walk_blocks_per_cu = 1;
+    int window_blocks_per_cu = 1;
+    int giant_blocks_per_cu = 1;
     hipStream_t stream = nullptr;
     hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;
+    double window_scale = kDefaultWindowScale;
+    u64 infra_min_height = kDefaultInfraMinHeight;
+    bool use_graphs = true;
 
     // prime table
     std::vector<u32> primes_host;
     PrimeEntry *d_primes = nullptr;
     u32 nsmall = 0;
 
-    // scratch (sized for one pass)
+    // pass buffers
+    SegInfo *d_segs = nullptr;
+    SegInfo *h_segs = nullptr;      // pinned staging
     u64 *d_roff = nullptr;
+    u64 roff_cap = 0;
     u32 *d_sq_words = nullptr;
     u32 *d_eis_words = nullptr;
-    u32 *d_list = nullptr;
-    PassCounters *d_ctr = nullptr;
-    unsigned long long *d_counts = nullptr;  // {n_sqfree, n_eis}
-    u64 bytes_held = 0;
+    u32 *d_list_plain = nullptr;
+    u32 *d_list_giant = nullptr;
+    u32 *d_fb_list = nullptr;
+    PassCounters *d_ctrs = nullptr;  // [0] plain walk, [1] giant steps, [2] hand-offs
+    unsigned long long *d_counts = nullptr;
+    u64 counts_cap = 0;              // pairs
+    unsigned long long *h_counts = nullptr;  // pinned
+    u64 h_counts_cap = 0;
+    u32 *d_q = nullptr;              // giant-step queue heads (3 cache lines)
+    bool pass_ready = false;
 
-    // infrastructure-method scratch
+    // giant-step scratch
     WindowState *d_state = nullptr;
     unsigned long long *d_lists = nullptr;
     unsigned long long *d_tables = nullptr;
     u32 *d_glist = nullptr;
-    u32 *d_q = nullptr;             // per-batch queue heads (3 cache lines)
-    u32 *d_fb_list = nullptr;
-    PassCounters *d_fb_ctr = nullptr;
-    u32 *h_pinned = nullptr;        // pinned host word for the list length
-    u64 infra_batch_cap = 0;        // d's per batch the scratch holds
-    u64 infra_stride_cap = 0;       // dictionary words per d the scratch holds
+    u64 infra_batch_cap = 0;
     u32 infra_emax_cap = 0;
     u32 infra_tsize_cap = 0;
-    int window_blocks_per_cu = 1;
-    int giant_blocks_per_cu = 1;
+    u64 bytes_held = 0;
 
+    // captured pass sequences, by shape
+    std::map<std::vector<u64>, hipGraphExec_t> graphs;
+
+    std::mutex gpu_mu;  // pass buffers and the stream
     std::mutex stats_mu;
     eis_stats stats{};
     int async_status = EIS_OK;
+
+    // serving
+    std::mutex smu;
+    std::condition_variable scv;    // wakes the server loop
+    std::condition_variable dcv;    // wakes waiters
+    std::deque<u64> order;          // tickets in arrival order (not finished)
+    std::map<u64, Request> reqs;
+    u64 next_ticket = 1;
+    bool stop = false;
+    std::thread server;
 };
 
 // ---------------------------------------------------------------------------
-// helpers
+// small helpers
 // ---------------------------------------------------------------------------
 
 static int hip_status(hipError_t e)
@@ -128,9 +181,9 @@ static int hip_status(hipError_t e)
     return EIS_EDEVICE;
 }
 
-#define HIP_TRY(expr)                          \
-    do {                                       \
-        hipError_t _e = (expr);                \
+#define HIP_TRY(expr)                                \
+    do {                                             \
+        hipError_t _e = (expr);                      \
         if (_e != hipSuccess) return hip_status(_e); \
     } while (0)
 
@@ -182,33 +235,48 @@ static void free_infra(eis_ctx *c)
     c->d_state = nullptr;
     c->d_lists = c->d_tables = nullptr;
     c->d_glist = nullptr;
-    c->infra_batch_cap = c->infra_stride_cap = 0;
+    c->infra_batch_cap = 0;
+    c->infra_emax_cap = c->infra_tsize_cap = 0;
 }
 
-static void free_scratch(eis_ctx *c)
+static void drop_graphs(eis_ctx *c)
 {
-    free_infra(c);
-    (void)hipFree(c->d_roff);
-    (void)hipFree(c->d_sq_words);
-    (void)hipFree(c->d_eis_words);
-    (void)hipFree(c->d_list);
-    c->d_roff = nullptr;
-    c->d_sq_words = c->d_eis_words = c->d_list = nullptr;
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+static void stop_server(eis_ctx *c)
+{
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        c->stop = true;
+    }
+    c->scv.notify_all();
+    c->dcv.notify_all();
+    if (c->server.joinable()) c->server.join();
 }
 
 extern "C" void eis_destroy(eis_ctx *c)
 {
     if (!c) return;
+    stop_server(c);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    free_scratch(c);
+    drop_graphs(c);
+    free_infra(c);
     (void)hipFree(c->d_primes);
-    (void)hipFree(c->d_ctr);
+    (void)hipFree(c->d_segs);
+    (void)hipFree(c->d_roff);
+    (void)hipFree(c->d_sq_words);
+    (void)hipFree(c->d_eis_words);
+    (void)hipFree(c->d_list_plain);
+    (void)hipFree(c->d_list_giant);
+    (void)hipFree(c->d_fb_list);
+    (void)hipFree(c->d_ctrs);
     (void)hipFree(c->d_counts);
     (void)hipFree(c->d_q);
-    (void)hipFree(c->d_fb_list);
-    (void)hipFree(c->d_fb_ctr);
-    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->h_segs) (void)hipHostFree(c->h_segs);
+    if (c->h_counts) (void)hipHostFree(c->h_counts);
     if (c->ev_walk0) (void)hipEventDestroy(c->ev_walk0);
     if (c->ev_walk1) (void)hipEventDestroy(c->ev_walk1);
     if (c->ev_all0) (void)hipEventDestroy(c->ev_all0);
@@ -223,7 +291,7 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     eis_config def;
     eis_config_default(&def);
     if (!cfg) cfg = &def;
-    if (cfg->flags != 0) return EIS_EINVAL;
+    if ((cfg->flags & ~(uint32_t)EIS_FLAG_NO_GRAPHS) != 0) return EIS_EINVAL;
     if (cfg->method < EIS_METHOD_BABY || cfg->method > EIS_METHOD_AUTO) return EIS_EINVAL;
     if (cfg->window_scale < 0) return EIS_EINVAL;
 
@@ -239,8 +307,10 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     c->cfg = *cfg;
     c->cfg.tune_cache_path = nullptr;  // not retained beyond the call
     if (c->cfg.max_steps_per_d == 0) c->cfg.max_steps_per_d = kDefaultMaxSteps;
-    if (c->cfg.window_scale == 0.0) c->cfg.window_scale = kDefaultWindowScale;
     if (c->cfg.max_steps_per_d > 0xffff0000ull) c->cfg.max_steps_per_d = 0xffff0000ull;
+    if (c->cfg.serve_slots == 0) c->cfg.serve_slots = kDefaultServeSlots;
+    c->window_scale = cfg->window_scale > 0 ? cfg->window_scale : kDefaultWindowScale;
+    c->use_graphs = (cfg->flags & EIS_FLAG_NO_GRAPHS) == 0;
     c->device = cfg->device;
     c->num_cu = prop.multiProcessorCount;
     int rc = EIS_OK;
@@ -274,21 +344,6 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
             rc = EIS_EDEVICE;
             break;
         }
-        if (hipMalloc(&c->d_ctr, sizeof(PassCounters)) != hipSuccess ||
-            hipMalloc(&c->d_counts, 4 * sizeof(unsigned long long)) != hipSuccess) {
-            rc = EIS_ENOMEM;
-            break;
-        }
-        if (hipMalloc(&c->d_q, 3 * 64) != hipSuccess ||
-            hipMalloc(&c->d_fb_ctr, sizeof(PassCounters)) != hipSuccess ||
-            hipMalloc(&c->d_fb_list, kPassCandidates * sizeof(u32)) != hipSuccess) {
-            rc = EIS_ENOMEM;
-            break;
-        }
-        if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64, hipHostMallocDefault) != hipSuccess) {
-            rc = EIS_ENOMEM;
-            break;
-        }
         c->walk_blocks_per_cu = walk_baby_blocks_per_cu();
         c->window_blocks_per_cu = walk_window_blocks_per_cu();
         c->giant_blocks_per_cu = walk_giant_blocks_per_cu();
@@ -301,22 +356,91 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     return EIS_OK;
 }
 
-// Make sure the per-pass scratch can hold `ncand` candidates.
-static int ensure_scratch(eis_ctx *c)
+// ---------------------------------------------------------------------------
+// buffers
+// ---------------------------------------------------------------------------
+
+static int ensure_pass_buffers(eis_ctx *c)
 {
-    if (c->d_list) return EIS_OK;
-    const u64 ncand = kPassCandidates;
-    const u64 nwords = ncand / 32;
-    u64 need = c->primes_host.size() * sizeof(u64) + 2 * nwords * sizeof(u32) + ncand * sizeof(u32);
+    if (c->pass_ready) return EIS_OK;
+    const u64 need = kMaxSegments * sizeof(SegInfo) + 2ull * kPassWords * 4 +
+                     3ull * kPassCandidates * 4 + 3 * sizeof(PassCounters) + 3 * 64;
     if (c->cfg.mem_budget_bytes && need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
-    if (hipMalloc(&c->d_roff, c->primes_host.size() * sizeof(u64)) != hipSuccess ||
-        hipMalloc(&c->d_sq_words, nwords * sizeof(u32)) != hipSuccess ||
-        hipMalloc(&c->d_eis_words, nwords * sizeof(u32)) != hipSuccess ||
-        hipMalloc(&c->d_list, ncand * sizeof(u32)) != hipSuccess) {
-        free_scratch(c);
+    if (hipMalloc(&c->d_segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->h_segs), kMaxSegments * sizeof(SegInfo),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&c->d_sq_words, (u64)kPassWords * 4) != hipSuccess ||
+        hipMalloc(&c->d_eis_words, (u64)kPassWords * 4) != hipSuccess ||
+        hipMalloc(&c->d_list_plain, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->d_list_giant, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->d_fb_list, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->d_ctrs, 3 * sizeof(PassCounters)) != hipSuccess ||
+        hipMalloc(&c->d_q, 3 * 64) != hipSuccess)
+        return EIS_ENOMEM;
+    c->bytes_held += need;
+    c->pass_ready = true;
+    return EIS_OK;
+}
+
+static int ensure_roff(eis_ctx *c, u64 n)
+{
+    if (c->roff_cap >= n) return EIS_OK;
+    (void)hipFree(c->d_roff);
+    c->d_roff = nullptr;
+    c->roff_cap = 0;
+    if (hipMalloc(&c->d_roff, n * sizeof(u64)) != hipSuccess) return EIS_ENOMEM;
+    c->roff_cap = n;
+    drop_graphs(c);  // captured sequences hold the old pointer
+    return EIS_OK;
+}
+
+static int ensure_counts(eis_ctx *c, u64 pairs)
+{
+    if (c->counts_cap < pairs) {
+        (void)hipFree(c->d_counts);
+        c->d_counts = nullptr;
+        c->counts_cap = 0;
+        u64 cap = std::max<u64>(pairs, kMaxSegments);
+        if (hipMalloc(&c->d_counts, cap * 2 * sizeof(unsigned long long)) != hipSuccess)
+            return EIS_ENOMEM;
+        c->counts_cap = cap;
+        drop_graphs(c);
+    }
+    if (c->h_counts_cap < pairs) {
+        if (c->h_counts) (void)hipHostFree(c->h_counts);
+        c->h_counts = nullptr;
+        c->h_counts_cap = 0;
+        u64 cap = std::max<u64>(pairs, kMaxSegments);
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->h_counts),
+                          cap * 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+            return EIS_ENOMEM;
+        c->h_counts_cap = cap;
+    }
+    return EIS_OK;
+}
+
+// Scratch of the giant-step method: `batch` d's (whole tiles of 64), `emax`
+// list entries and `tsize` table slots each.
+static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
+{
+    const u64 cap = (batch + 63) / 64 * 64;
+    if (c->d_lists && c->infra_batch_cap >= cap && c->infra_emax_cap >= emax &&
+        c->infra_tsize_cap >= tsize)
+        return EIS_OK;
+    free_infra(c);
+    drop_graphs(c);
+    const u64 bytes = cap * ((u64)(emax + tsize) * 8 + sizeof(WindowState) + sizeof(u32));
+    if (c->cfg.mem_budget_bytes && c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
+    if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
+        hipMalloc(&c->d_tables, cap * tsize * 8) != hipSuccess ||
+        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
+        hipMalloc(&c->d_glist, cap * sizeof(u32)) != hipSuccess) {
+        free_infra(c);
         return EIS_ENOMEM;
     }
-    c->bytes_held = need;
+    c->infra_batch_cap = cap;
+    c->infra_emax_cap = emax;
+    c->infra_tsize_cap = tsize;
     return EIS_OK;
 }
 
@@ -324,171 +448,227 @@ static int ensure_scratch(eis_ctx *c)
 static u32 primes_needed(const eis_ctx *c, u64 dmax)
 {
     u64 r = isqrt_host(dmax);
-    return (u32)(std::upper_bound(c->primes_host.begin(), c->primes_host.end(), (u32)std::min<u64>(r, 0xffffffffu)) -
+    return (u32)(std::upper_bound(c->primes_host.begin(), c->primes_host.end(),
+                                  (u32)std::min<u64>(r, 0xffffffffu)) -
                  c->primes_host.begin());
 }
 
-static bool use_infra(const eis_ctx *c, u64 d0)
-{
-    if (c->cfg.method == EIS_METHOD_INFRA) return true;
-    if (c->cfg.method == EIS_METHOD_BABY) return false;
-    return d0 >= kDefaultInfraMinHeight;
-}
-
 // Dictionary geometry for heights up to dmax.
-static void infra_geometry(const eis_ctx *c, u64 dmax, u32 &emax, u32 &tsize)
+static void infra_geometry(double window_scale, u64 dmax, u32 &emax, u32 &tsize)
 {
-    double n = c->cfg.window_scale * std::pow((double)dmax, 0.25) / 16.0;
+    double n = window_scale * std::pow((double)dmax, 0.25) / 16.0;
     u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
     emain = std::max<u32>(emain, 16);
     emax = emain + 16;
     if (emax > 496) emax = 496;
     // load factor at most 0.5 for the usual count (mu_1 plus a few)
     tsize = 32;
-    while (tsize < 2 * (emain + 4)) tsize <<= 1;
+    while (tsize < 2 * (std::min(emain, emax - 8) + 4)) tsize <<= 1;
 }
 
-// Scratch of one infrastructure batch: `batch` d's (rounded up to whole
-// tiles of 64), `emax` list entries and `tsize` table slots each.
-static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
+static u32 method_for(const eis_ctx *c, u64 d0)
 {
-    const u64 tiles = (batch + 63) / 64;
-    const u64 stride = (u64)emax + tsize;
-    if (c->d_lists && c->infra_batch_cap >= tiles * 64 && c->infra_stride_cap >= stride &&
-        c->infra_emax_cap >= emax && c->infra_tsize_cap >= tsize)
-        return EIS_OK;
-    free_infra(c);
-    const u64 bytes = tiles * 64 * (stride * 8 + sizeof(WindowState) + sizeof(u32));
-    if (c->cfg.mem_budget_bytes && c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
-    if (hipMalloc(&c->d_lists, tiles * 64 * emax * 8) != hipSuccess ||
-        hipMalloc(&c->d_tables, tiles * 64 * tsize * 8) != hipSuccess ||
-        hipMalloc(&c->d_state, tiles * 64 * sizeof(WindowState)) != hipSuccess ||
-        hipMalloc(&c->d_glist, tiles * 64 * sizeof(u32)) != hipSuccess) {
-        free_infra(c);
-        return EIS_ENOMEM;
+    if (c->cfg.method == EIS_METHOD_INFRA) return 1;
+    if (c->cfg.method == EIS_METHOD_BABY) return 0;
+    return d0 >= c->infra_min_height ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// one pass
+// ---------------------------------------------------------------------------
+
+struct PassPlan {
+    u32 nseg = 0, nblocks = 0, np_max = 0, words = 0;
+    u64 plain_cand = 0, giant_cand = 0;
+    u32 emax = 0, tsize = 0;
+    u64 batch = 0;
+    u32 nbatches = 0;
+    u32 grid_plain = 0, grid_win = 0, grid_giant = 0, grid_fb = 0;
+    u64 roff_total = 0;
+};
+
+// Fill the pinned segment table and the plan of a pass.
+static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl)
+{
+    pl = PassPlan();
+    pl.nseg = (u32)segs.size();
+    u32 word = 0, block = 0;
+    u64 roff = 0, dmax_giant = 0;
+    for (u32 s = 0; s < pl.nseg; s++) {
+        const HostSeg &h = segs[s];
+        SegInfo &g = c->h_segs[s];
+        g.d0 = h.d0;
+        g.n = h.n;
+        g.word_off = word;
+        g.block_off = block;
+        const u64 dlast = h.d0 + 8ull * (h.n - 1);
+        g.np = primes_needed(c, dlast);
+        g.roff_off = (u32)roff;
+        g.method = h.method;
+        g.count_slot = h.slot;
+        g.pad = 0;
+        word += (h.n + 31) / 32;
+        block += (h.n + kSegCandidates - 1) / kSegCandidates;
+        roff += g.np;
+        pl.np_max = std::max(pl.np_max, g.np);
+        if (h.method) {
+            pl.giant_cand += h.n;
+            dmax_giant = std::max(dmax_giant, dlast);
+        } else {
+            pl.plain_cand += h.n;
+        }
     }
-    c->infra_batch_cap = tiles * 64;
-    c->infra_stride_cap = stride;
-    c->infra_emax_cap = emax;
-    c->infra_tsize_cap = tsize;
-    return EIS_OK;
+    pl.words = word;
+    pl.nblocks = block;
+    pl.roff_total = roff;
+    const u64 max_plain = (u64)c->num_cu * c->walk_blocks_per_cu;
+    pl.grid_plain = (u32)std::min<u64>((pl.plain_cand + 255) / 256, max_plain);
+    pl.grid_fb = (u32)c->num_cu;
+    if (pl.giant_cand) {
+        infra_geometry(c->window_scale, dmax_giant, pl.emax, pl.tsize);
+        pl.batch = std::min<u64>(pl.giant_cand, kInfraBatch);
+        pl.nbatches = (u32)((pl.giant_cand + pl.batch - 1) / pl.batch);
+        const u64 max_win = (u64)c->num_cu * c->window_blocks_per_cu;
+        const u64 max_giant = (u64)c->num_cu * c->giant_blocks_per_cu;
+        pl.grid_win = (u32)std::max<u64>(1, std::min((pl.batch + 255) / 256, max_win));
+        pl.grid_giant = (u32)std::max<u64>(1, std::min((pl.batch + 255) / 256, max_giant));
+    }
 }
 
-// Walk of the compacted list with the plain method (grid sized to n when n
-// is known on the host, else to the whole device).
-static int enqueue_walk_baby(eis_ctx *c, u64 d0, const u32 *list, PassCounters *ctr, u64 n_hint,
-                             hipStream_t st)
+// Enqueue the launch sequence of a planned pass (after the segment table
+// upload).  Captured into graphs by shape.
+static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, bool timed)
 {
+    PassCounters *ctr_plain = c->d_ctrs, *ctr_giant = c->d_ctrs + 1, *ctr_fb = c->d_ctrs + 2;
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctrs), 3 * sizeof(PassCounters) / 4, st));
+    HIP_TRY(launch_zero_u32(c->d_eis_words, pl.words, st));
+    HIP_TRY(launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
+    HIP_TRY(launch_sieve(c->d_primes, c->d_roff, c->d_segs, pl.nseg, pl.nblocks, c->nsmall,
+                         c->d_sq_words, c->d_list_plain, ctr_plain, c->d_list_giant, ctr_giant, st));
+    if (timed) HIP_TRY(hipEventRecord(c->ev_walk0, st));
     WalkParams wp;
-    wp.d0 = d0;
-    wp.list = list;
-    wp.ctr = ctr;
+    wp.segs = c->d_segs;
     wp.eis_words = c->d_eis_words;
     wp.max_steps = (u32)c->cfg.max_steps_per_d;
-    u64 want_blocks = (n_hint + 255) / 256;
-    u64 max_blocks = (u64)c->num_cu * (u64)c->walk_blocks_per_cu;
-    u32 grid = (u32)std::max<u64>(1, std::min(want_blocks, max_blocks));
-    HIP_TRY(launch_walk_baby(wp, grid, st));
-    return EIS_OK;
-}
-
-// Enqueue one pass: candidates d0 + 8 i, i < n (n <= kPassCandidates).
-// Bitmaps land in c->d_sq_words / c->d_eis_words; counts are added to
-// counts[0..1].  The infrastructure method reads the list length back to
-// the host once per pass, to size its batches.
-static int enqueue_pass(eis_ctx *c, u64 d0, u32 n, unsigned long long *counts, hipStream_t st)
-{
-    const u64 nwords = (n + 31) / 32;
-    const u64 dmax = d0 + 8ull * (n - 1);
-    const u32 np = primes_needed(c, dmax);
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctr), sizeof(PassCounters) / 4, st));
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_fb_ctr), sizeof(PassCounters) / 4, st));
-    HIP_TRY(launch_zero_u32(c->d_eis_words, nwords, st));
-    HIP_TRY(launch_prime_offsets(c->d_primes, np, d0, c->d_roff, st));
-    HIP_TRY(launch_sieve(c->d_primes, c->d_roff, np, std::min(c->nsmall, np), n, c->d_sq_words,
-                         c->d_list, c->d_ctr, st));
-    u64 launches = 6;
-    HIP_TRY(hipEventRecord(c->ev_walk0, st));
-    if (!use_infra(c, d0)) {
-        int rc = enqueue_walk_baby(c, d0, c->d_list, c->d_ctr, n, st);
-        if (rc != EIS_OK) return rc;
-        launches += 1;
-    } else {
-        HIP_TRY(hipMemcpyAsync(c->h_pinned, &c->d_ctr->list_len, sizeof(u32), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const u64 nd = *c->h_pinned;
-        u32 emax, tsize;
-        infra_geometry(c, dmax, emax, tsize);
-        const u64 batch = std::min<u64>(std::max<u64>(nd, 1), kInfraBatch);
-        int rc = ensure_infra(c, batch, emax, tsize);
-        if (rc != EIS_OK) return rc;
+    if (pl.plain_cand) {
+        wp.list = c->d_list_plain;
+        wp.ctr = ctr_plain;
+        HIP_TRY(launch_walk_baby(wp, pl.grid_plain, st));
+    }
+    if (pl.giant_cand) {
         InfraParams ip;
-        ip.d0 = d0;
-        ip.list = c->d_list;
-        ip.ctr = c->d_ctr;
+        ip.segs = c->d_segs;
+        ip.list = c->d_list_giant;
+        ip.list_ctr = ctr_giant;
+        ip.batch = (u32)pl.batch;
+        ip.ctr = ctr_giant;
         ip.win_next = c->d_q;
         ip.giant_len = c->d_q + 16;
         ip.giant_next = c->d_q + 32;
         ip.giant_list = c->d_glist;
         ip.fb_list = c->d_fb_list;
-        ip.fb_ctr = c->d_fb_ctr;
+        ip.fb_ctr = ctr_fb;
         ip.state = c->d_state;
         ip.lists = c->d_lists;
         ip.tables = c->d_tables;
-        ip.emax = emax;
-        ip.tsize = tsize;
-        ip.window_scale = (float)c->cfg.window_scale;
+        ip.emax = pl.emax;
+        ip.tsize = pl.tsize;
+        ip.window_scale = (float)c->window_scale;
         ip.max_steps = (u32)c->cfg.max_steps_per_d;
         ip.max_giants = 1u << 20;
         ip.eis_words = c->d_eis_words;
-        const u64 max_win = (u64)c->num_cu * (u64)c->window_blocks_per_cu;
-        const u64 max_giant = (u64)c->num_cu * (u64)c->giant_blocks_per_cu;
-        for (u64 k0 = 0; k0 < nd; k0 += batch) {
-            const u64 k1 = std::min<u64>(nd, k0 + batch);
-            ip.k0 = (u32)k0;
-            ip.k1 = (u32)k1;
-            const u64 nb = k1 - k0;
+        for (u32 bi = 0; bi < pl.nbatches; bi++) {
+            ip.k0 = (u32)(bi * pl.batch);
             HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
-            const u32 gw = (u32)std::max<u64>(1, std::min((nb + 255) / 256, max_win));
-            // window waves take tiles of 64 d's
-            HIP_TRY(launch_walk_window(ip, gw, st));
-            HIP_TRY(launch_build_tables(ip, (u32)nb, st));
-            const u32 gg = (u32)std::max<u64>(1, std::min((nb + 255) / 256, max_giant));
-            HIP_TRY(launch_walk_giant(ip, gg, st));
-            launches += 4;
+            HIP_TRY(launch_walk_window(ip, pl.grid_win, st));
+            HIP_TRY(launch_build_tables(ip, st));
+            HIP_TRY(launch_walk_giant(ip, pl.grid_giant, st));
         }
-        // d's that left the giant-step method: the plain walk, exact for all d
-        rc = enqueue_walk_baby(c, d0, c->d_fb_list, c->d_fb_ctr, 256ull * (u64)c->num_cu, st);
-        if (rc != EIS_OK) return rc;
-        launches += 1;
+        // d's handed off by the giant-step method: the plain walk, exact for all d
+        wp.list = c->d_fb_list;
+        wp.ctr = ctr_fb;
+        HIP_TRY(launch_walk_baby(wp, pl.grid_fb, st));
     }
-    HIP_TRY(hipEventRecord(c->ev_walk1, st));
-    HIP_TRY(launch_popcount_add(c->d_sq_words, nwords, counts + 0, st));
-    HIP_TRY(launch_popcount_add(c->d_eis_words, nwords, counts + 1, st));
-    std::lock_guard<std::mutex> lk(c->stats_mu);
-    c->stats.launches += launches + 2;
+    if (timed) HIP_TRY(hipEventRecord(c->ev_walk1, st));
+    HIP_TRY(launch_popcount_segs(c->d_sq_words, c->d_eis_words, c->d_segs, pl.nseg,
+                                 (u32)((kPassCandidates + 31) / 32), c->d_counts, st));
     return EIS_OK;
 }
 
-// Read the per-pass counters after the stream has finished the pass.
+static std::vector<u64> plan_key(const eis_ctx *c, const PassPlan &pl)
+{
+    u64 ws;
+    std::memcpy(&ws, &c->window_scale, sizeof(ws));
+    return {pl.nseg, pl.nblocks, pl.np_max, pl.words, pl.plain_cand ? 1ull : 0ull,
+            pl.giant_cand ? 1ull : 0ull, pl.emax, pl.tsize, pl.batch, pl.nbatches, pl.grid_plain,
+            pl.grid_win, pl.grid_giant, pl.grid_fb, ws, c->cfg.max_steps_per_d};
+}
+
+// Run one pass of segments (counts are accumulated into d_counts, which the
+// caller zeroes).  Synchronous when `sync`.
+static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st, bool graph,
+                    PassPlan &pl)
+{
+    (void)hipGetLastError();  // launch checks below must not see an older error
+    int rc = ensure_pass_buffers(c);
+    if (rc != EIS_OK) return rc;
+    plan_pass(c, segs, pl);
+    rc = ensure_roff(c, std::max<u64>(pl.roff_total, 1));
+    if (rc != EIS_OK) return rc;
+    if (pl.giant_cand) {
+        rc = ensure_infra(c, pl.batch, pl.emax, pl.tsize);
+        if (rc != EIS_OK) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_segs, c->h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
+    u64 launches = 7 + (pl.giant_cand ? 1 + 4ull * pl.nbatches : 0);
+    if (graph && c->use_graphs && st == c->stream) {
+        const std::vector<u64> key = plan_key(c, pl);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int brc = enqueue_pass_body(c, pl, st, false);
+            hipError_t e = hipStreamEndCapture(st, &g);
+            if (brc != EIS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return brc;
+            }
+            if (e != hipSuccess) return hip_status(e);
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_status(e);
+            it = c->graphs.emplace(key, ge).first;
+        }
+        // a replay is timed as a whole (the walk events are not in the graph)
+        HIP_TRY(hipEventRecord(c->ev_walk0, st));
+        HIP_TRY(hipGraphLaunch(it->second, st));
+        HIP_TRY(hipEventRecord(c->ev_walk1, st));
+    } else {
+        rc = enqueue_pass_body(c, pl, st, true);
+        if (rc != EIS_OK) return rc;
+    }
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    c->stats.launches += launches;
+    return EIS_OK;
+}
+
+// Read the pass counters after the stream has finished the pass.
 static int collect_pass(eis_ctx *c)
 {
-    PassCounters h, f;
-    if (hipMemcpy(&h, c->d_ctr, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
-    if (hipMemcpy(&f, c->d_fb_ctr, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
-    h.baby_steps += f.baby_steps;
-    h.refills += f.refills;
-    h.err_count += f.err_count;
+    PassCounters h[3];
+    if (hipMemcpy(h, c->d_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
+    if (!have_ms) (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(c->stats_mu);
     if (have_ms) c->stats.last_walk_ms = wms;
-    c->stats.discriminants += h.list_len;
-    c->stats.baby_steps += h.baby_steps;
-    c->stats.giant_steps += h.giant_steps;
-    c->stats.refills += h.refills;
-    c->stats.fallbacks += f.list_len;
-    return h.err_count ? EIS_EINTERNAL : EIS_OK;
+    c->stats.discriminants += (u64)h[0].list_len + h[1].list_len;
+    c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[2].baby_steps;
+    c->stats.giant_steps += h[1].giant_steps;
+    c->stats.refills += h[0].refills + h[1].refills + h[2].refills;
+    c->stats.fallbacks += h[2].list_len;
+    return (h[0].err_count | h[1].err_count | h[2].err_count) ? EIS_EINTERNAL : EIS_OK;
 }
 
 static int check_range(uint64_t a, uint64_t b)
@@ -498,24 +678,30 @@ static int check_range(uint64_t a, uint64_t b)
     return EIS_OK;
 }
 
-// Core driver: every pass of [a, b); bitmaps go to host (h_*) or device
-// (d_*) byte buffers at the pass's byte offset.
+// Core driver of one range: one pass per piece of at most kPassCandidates
+// candidates; bitmaps go to host (h_*) or device (d_*) byte buffers.
 static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t *h_eis,
                      uint8_t *d_sq, uint8_t *d_eis, uint64_t *n_sq, uint64_t *n_eis,
                      unsigned long long *d_counts_out, hipStream_t st, bool sync)
 {
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    int rc = ensure_scratch(c);
+    int rc = ensure_counts(c, 1);
     if (rc != EIS_OK) return rc;
     const u64 n = eis_num_candidates(a, b);
     const u64 d0 = eis_first_candidate(a);
-    unsigned long long *counts = d_counts_out ? d_counts_out : c->d_counts;
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(counts), 4, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4, st));
     HIP_TRY(hipEventRecord(c->ev_all0, st));
     int status = EIS_OK;
     for (u64 off = 0; off < n; off += kPassCandidates) {
         const u32 pn = (u32)std::min<u64>(kPassCandidates, n - off);
-        rc = enqueue_pass(c, d0 + 8 * off, pn, counts, st);
+        std::vector<HostSeg> segs(1);
+        segs[0].d0 = d0 + 8 * off;
+        segs[0].n = pn;
+        segs[0].slot = 0;
+        segs[0].method = method_for(c, segs[0].d0);
+        segs[0].dst_bit = off;
+        PassPlan pl;
+        rc = run_pass(c, segs, st, false, pl);
         if (rc != EIS_OK) return rc;
         const size_t bytes = (pn + 7) / 8;
         const size_t boff = off / 8;
@@ -530,15 +716,21 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
             if (prc != EIS_OK) status = prc;
         }
     }
+    if (d_counts_out) {
+        HIP_TRY(hipMemcpyAsync(d_counts_out, c->d_counts, 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToDevice, st));
+    }
     HIP_TRY(hipEventRecord(c->ev_all1, st));
     if (sync) {
         HIP_TRY(hipStreamSynchronize(st));
         unsigned long long hc[2] = {0, 0};
-        HIP_TRY(hipMemcpy(hc, counts, sizeof(hc), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hc, c->d_counts, sizeof(hc), hipMemcpyDeviceToHost));
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev_all0, c->ev_all1) == hipSuccess) {
             std::lock_guard<std::mutex> lk(c->stats_mu);
             c->stats.last_total_ms = ms;
+        } else {
+            (void)hipGetLastError();
         }
         if (status != EIS_OK) return status;
         if (n_sq) *n_sq = hc[0];
@@ -552,11 +744,12 @@ extern "C" int eis_count(eis_ctx *c, uint64_t a, uint64_t b, uint64_t *n_sqfree,
     if (!c) return EIS_EINVAL;
     int rc = check_range(a, b);
     if (rc != EIS_OK) return rc;
-    if (a >= b) {
+    if (eis_num_candidates(a, b) == 0) {
         if (n_sqfree) *n_sqfree = 0;
         if (n_eis) *n_eis = 0;
         return EIS_OK;
     }
+    std::lock_guard<std::mutex> g(c->gpu_mu);
     return run_range(c, a, b, nullptr, nullptr, nullptr, nullptr, n_sqfree, n_eis, nullptr,
                      c->stream, true);
 }
@@ -570,7 +763,7 @@ extern "C" int eis_classify(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *sqfree_
     if (rc != EIS_OK) return rc;
     const u64 n = eis_num_candidates(a, b);
     if ((sqfree_bits || eis_bits) && len_bytes < (n + 7) / 8) return EIS_EINVAL;
-    if (a >= b || n == 0) {
+    if (n == 0) {
         if (n_sqfree) *n_sqfree = 0;
         if (n_eis) *n_eis = 0;
         return EIS_OK;
@@ -578,8 +771,12 @@ extern "C" int eis_classify(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *sqfree_
     // stage into temporaries so that an error leaves the caller's buffers untouched
     std::vector<uint8_t> tsq(sqfree_bits ? (n + 7) / 8 : 0), teis(eis_bits ? (n + 7) / 8 : 0);
     u64 cs = 0, ce = 0;
-    rc = run_range(c, a, b, sqfree_bits ? tsq.data() : nullptr, eis_bits ? teis.data() : nullptr,
-                   nullptr, nullptr, &cs, &ce, nullptr, c->stream, true);
+    {
+        std::lock_guard<std::mutex> g(c->gpu_mu);
+        rc = run_range(c, a, b, sqfree_bits ? tsq.data() : nullptr,
+                       eis_bits ? teis.data() : nullptr, nullptr, nullptr, &cs, &ce, nullptr,
+                       c->stream, true);
+    }
     if (rc != EIS_OK) return rc;
     if (sqfree_bits) std::memcpy(sqfree_bits, tsq.data(), tsq.size());
     if (eis_bits) std::memcpy(eis_bits, teis.data(), teis.size());
@@ -596,11 +793,10 @@ extern "C" int eis_classify_async(eis_ctx *c, uint64_t a, uint64_t b, void *d_sq
     if (rc != EIS_OK) return rc;
     hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
     const u64 n = eis_num_candidates(a, b);
+    std::lock_guard<std::mutex> g(c->gpu_mu);
+    if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     if (n == 0) {
-        if (d_counts2) {
-            if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-            HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(d_counts2), 4, st));
-        }
+        if (d_counts2) HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(d_counts2), 4, st));
         return EIS_OK;
     }
     rc = run_range(c, a, b, nullptr, nullptr, reinterpret_cast<uint8_t *>(d_sqfree_bits),
@@ -613,12 +809,61 @@ extern "C" int eis_classify_async(eis_ctx *c, uint64_t a, uint64_t b, void *d_sq
 extern "C" int eis_last_error(eis_ctx *c)
 {
     if (!c) return EIS_EINVAL;
+    std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    int rc = collect_pass(c);
+    int rc = EIS_OK;
+    if (c->pass_ready) rc = collect_pass(c);
     if (rc == EIS_OK) rc = c->async_status;
     c->async_status = EIS_OK;
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// batched counts
+// ---------------------------------------------------------------------------
+
+// Cut ranges into pieces of at most kPassCandidates candidates, order them
+// by estimated cost (height first: the walks of high d are the long ones, so
+// they start first and the tail of the persistent launch is short), and pack
+// them into passes of at most kMaxSegments pieces and kPassCandidates
+// candidates.
+static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>> &ranges,
+                        std::vector<std::vector<HostSeg>> &passes)
+{
+    std::vector<HostSeg> pieces;
+    for (const auto &r : ranges) {
+        const u64 a = std::get<0>(r), b = std::get<1>(r);
+        const u32 slot = std::get<2>(r);
+        const u64 n = eis_num_candidates(a, b);
+        const u64 d0 = eis_first_candidate(a);
+        for (u64 off = 0; off < n; off += kPassCandidates) {
+            HostSeg h;
+            h.d0 = d0 + 8 * off;
+            h.n = (u32)std::min<u64>(kPassCandidates, n - off);
+            h.slot = slot;
+            h.method = method_for(c, h.d0);
+            h.dst_bit = off;
+            pieces.push_back(h);
+        }
+    }
+    std::sort(pieces.begin(), pieces.end(), [](const HostSeg &x, const HostSeg &y) {
+        return x.d0 > y.d0;
+    });
+    std::vector<HostSeg> cur;
+    u64 cand = 0;
+    for (const HostSeg &h : pieces) {
+        // a segment's bitmap starts on a word: count its padding too
+        const u64 cost = (h.n + 31) / 32 * 32;
+        if (!cur.empty() && (cur.size() == kMaxSegments || cand + cost > kPassCandidates)) {
+            passes.push_back(cur);
+            cur.clear();
+            cand = 0;
+        }
+        cur.push_back(h);
+        cand += cost;
+    }
+    if (!cur.empty()) passes.push_back(cur);
 }
 
 extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b, size_t n,
@@ -629,34 +874,219 @@ extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b,
         int rc = check_range(a[k], b[k]);
         if (rc != EIS_OK) return rc;
     }
-    std::vector<uint64_t> s(n), e(n);
-    for (size_t k = 0; k < n; k++) {
-        int rc = eis_count(c, a[k], b[k], &s[k], &e[k]);
+    std::vector<std::tuple<u64, u64, u32>> ranges;
+    for (size_t k = 0; k < n; k++)
+        if (eis_num_candidates(a[k], b[k])) ranges.emplace_back(a[k], b[k], (u32)k);
+    std::vector<std::vector<HostSeg>> passes;
+    std::lock_guard<std::mutex> g(c->gpu_mu);
+    if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
+    pack_passes(c, ranges, passes);
+    int rc = ensure_counts(c, std::max<u64>(n, 1));
+    if (rc != EIS_OK) return rc;
+    hipStream_t st = c->stream;
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * std::max<u64>(n, 1), st));
+    HIP_TRY(hipEventRecord(c->ev_all0, st));
+    int status = EIS_OK;
+    for (const auto &segs : passes) {
+        PassPlan pl;
+        rc = run_pass(c, segs, st, true, pl);
         if (rc != EIS_OK) return rc;
+        HIP_TRY(hipStreamSynchronize(st));
+        int prc = collect_pass(c);
+        if (prc != EIS_OK) status = prc;
     }
+    HIP_TRY(hipEventRecord(c->ev_all1, st));
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(c->h_counts, c->d_counts, 2 * n * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_all0, c->ev_all1) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(c->stats_mu);
+        c->stats.last_total_ms = ms;
+    } else {
+        (void)hipGetLastError();
+    }
+    if (status != EIS_OK) return status;
     for (size_t k = 0; k < n; k++) {
-        if (n_sqfree) n_sqfree[k] = s[k];
-        if (n_eis) n_eis[k] = e[k];
+        if (n_sqfree) n_sqfree[k] = c->h_counts[2 * k];
+        if (n_eis) n_eis[k] = c->h_counts[2 * k + 1];
     }
     return EIS_OK;
 }
 
-extern "C" int eis_submit(eis_ctx *c, uint64_t, uint64_t, uint64_t *)
+// ---------------------------------------------------------------------------
+// serving: continuous batching of range-count requests
+// ---------------------------------------------------------------------------
+//
+// A server thread runs passes back to back.  Each pass takes, in arrival
+// order, the next chunk (at most kServeChunk candidates) of every admitted
+// request, up to the pass's capacity; a request finishes when its last chunk
+// has been through a pass.  Requests that arrive while a pass runs join the
+// next one, next to the remaining chunks of the earlier ones.
+
+static void server_loop(eis_ctx *c)
 {
-    if (!c) return EIS_EINVAL;
-    return EIS_EINVAL;
+    (void)hipSetDevice(c->device);
+    for (;;) {
+        std::vector<HostSeg> segs;
+        std::vector<std::pair<u64, u64>> parts;  // (ticket, candidates) per segment
+        {
+            std::unique_lock<std::mutex> lk(c->smu);
+            c->scv.wait(lk, [&] {
+                if (c->stop) return true;
+                for (u64 t : c->order) {
+                    const Request &r = c->reqs[t];
+                    if (!r.cancelled && r.dispatched < r.ncand) return true;
+                }
+                return false;
+            });
+            if (c->stop) return;
+            u64 cand = 0;
+            for (u64 t : c->order) {
+                Request &r = c->reqs[t];
+                if (r.cancelled || r.dispatched >= r.ncand) continue;
+                if (segs.size() == kMaxSegments) break;
+                u64 take = std::min<u64>(r.ncand - r.dispatched, kServeChunk);
+                const u64 room = kPassCandidates - cand;
+                if (room < 64) break;
+                take = std::min<u64>(take, room / 32 * 32);
+                HostSeg h;
+                h.d0 = r.d0 + 8 * r.dispatched;
+                h.n = (u32)take;
+                h.slot = (u32)segs.size();
+                h.method = method_for(c, h.d0);
+                h.dst_bit = 0;
+                segs.push_back(h);
+                parts.emplace_back(t, take);
+                r.dispatched += take;
+                cand += (take + 31) / 32 * 32;
+            }
+        }
+        int rc = EIS_OK;
+        {
+            std::lock_guard<std::mutex> g(c->gpu_mu);
+            rc = ensure_counts(c, segs.size());
+            if (rc == EIS_OK) {
+                hipStream_t st = c->stream;
+                if (launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * segs.size(), st) != hipSuccess)
+                    rc = EIS_EDEVICE;
+                PassPlan pl;
+                if (rc == EIS_OK) rc = run_pass(c, segs, st, true, pl);
+                if (rc == EIS_OK &&
+                    hipMemcpyAsync(c->h_counts, c->d_counts, 2 * segs.size() * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st) != hipSuccess)
+                    rc = EIS_EDEVICE;
+                if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
+                if (rc == EIS_OK) rc = collect_pass(c);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(c->smu);
+            for (size_t s = 0; s < parts.size(); s++) {
+                auto it = c->reqs.find(parts[s].first);
+                if (it == c->reqs.end()) continue;
+                Request &r = it->second;
+                if (rc != EIS_OK) {
+                    r.status = rc;
+                    r.finished = true;
+                    continue;
+                }
+                r.n_sq += c->h_counts[2 * s];
+                r.n_eis += c->h_counts[2 * s + 1];
+                r.completed += parts[s].second;
+                if (r.completed >= r.ncand) r.finished = true;
+            }
+            // retire finished and cancelled requests from the arrival order
+            std::deque<u64> keep;
+            for (u64 t : c->order) {
+                Request &r = c->reqs[t];
+                if (r.finished || (r.cancelled && r.completed >= r.dispatched)) {
+                    if (!r.finished) r.finished = true;
+                    if (r.status == EIS_OK && !r.cancelled) {
+                        std::lock_guard<std::mutex> sl(c->stats_mu);
+                        c->stats.requests_done++;
+                    }
+                } else {
+                    keep.push_back(t);
+                }
+            }
+            c->order.swap(keep);
+        }
+        c->dcv.notify_all();
+    }
 }
 
-extern "C" int eis_wait(eis_ctx *c, uint64_t, int64_t, uint64_t *, uint64_t *)
+extern "C" int eis_submit(eis_ctx *c, uint64_t a, uint64_t b, uint64_t *ticket)
 {
-    if (!c) return EIS_EINVAL;
-    return EIS_EINVAL;
+    if (!c || !ticket) return EIS_EINVAL;
+    int rc = check_range(a, b);
+    if (rc != EIS_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        if (c->stop) return EIS_EINVAL;
+        if (c->order.size() >= c->cfg.serve_slots) return EIS_EBUSY;
+        if (!c->server.joinable()) c->server = std::thread(server_loop, c);
+        Request r;
+        r.ticket = c->next_ticket++;
+        r.d0 = eis_first_candidate(a);
+        r.ncand = eis_num_candidates(a, b);
+        if (r.ncand == 0) r.finished = true;
+        c->reqs[r.ticket] = r;
+        if (!r.finished) c->order.push_back(r.ticket);
+        *ticket = r.ticket;
+    }
+    c->scv.notify_all();
+    return EIS_OK;
 }
 
-extern "C" int eis_cancel(eis_ctx *c, uint64_t)
+extern "C" int eis_wait(eis_ctx *c, uint64_t ticket, int64_t timeout_us, uint64_t *n_sqfree,
+                        uint64_t *n_eis)
 {
     if (!c) return EIS_EINVAL;
-    return EIS_EINVAL;
+    std::unique_lock<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return EIS_EINVAL;
+    auto ready = [&] { return c->reqs[ticket].finished || c->stop; };
+    if (timeout_us < 0) {
+        c->dcv.wait(lk, ready);
+    } else if (!c->dcv.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return EIS_ETIMEDOUT;
+    }
+    Request r = c->reqs[ticket];
+    if (!r.finished) return EIS_ETIMEDOUT;
+    c->reqs.erase(ticket);
+    if (r.cancelled) return EIS_ECANCELED;
+    if (r.status != EIS_OK) return r.status;
+    if (n_sqfree) *n_sqfree = r.n_sq;
+    if (n_eis) *n_eis = r.n_eis;
+    return EIS_OK;
+}
+
+extern "C" int eis_cancel(eis_ctx *c, uint64_t ticket)
+{
+    if (!c) return EIS_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        auto it = c->reqs.find(ticket);
+        if (it == c->reqs.end()) return EIS_EINVAL;
+        Request &r = it->second;
+        if (!r.finished) {
+            r.cancelled = true;
+            if (r.completed >= r.dispatched) {
+                // nothing of it is on the device: retire it now
+                r.finished = true;
+                std::deque<u64> keep;
+                for (u64 t : c->order)
+                    if (t != ticket) keep.push_back(t);
+                c->order.swap(keep);
+            }
+        }
+    }
+    c->dcv.notify_all();
+    c->scv.notify_all();
+    return EIS_OK;
 }
 
 extern "C" int eis_get_stats(eis_ctx *c, eis_stats *out)

@@ -69,7 +69,8 @@ __device__ __forceinline__ unsigned long long entry_of(float Q, float P, u32 S)
 __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
 {
     const u32 lane = __lane_id();
-    const u32 nb = p.k1 - p.k0;
+    const u32 total = p.list_ctr->list_len;
+    const u32 nb = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 ntiles = (nb + 63) / 64;
     u64 my_steps = 0, my_refills = 0;
 
@@ -83,10 +84,12 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
         float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
         u32 S = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1 = 0, m1q = 0, m1p = 0;
         bool active = false, to_giant = false, to_plain = false;
+        u32 item = 0;
         if (pos < nb) {
-            idx = p.list[p.k0 + pos];
+            item = p.list[p.k0 + pos];
+            idx = item_bit(p.segs, item);
             my_refills++;
-            const u64 d = p.d0 + 8ull * idx;
+            const u64 d = item_d(p.segs, item);
             const u64 si = isqrt_u64(d);
             const u64 P1 = ((si + 1) >> 1) * 2 - 1;
             const u64 Q1 = (d - P1 * P1) >> 1;
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                             st.q_bits = m1q;
                             st.p_bits = m1p;
                             st.count = cnt;
-                            st.idx = idx;
+                            st.item = item;
                             p.state[pos] = st;
                             to_giant = true;
                         } else {
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
         }
         if (to_plain) {
             const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-            p.fb_list[f] = idx;
+            p.fb_list[f] = item;
         }
         my_steps += j;
     }
@@ -232,11 +235,11 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     }
 }
 
-hipError_t launch_build_tables(const InfraParams &p, u32 nmax, hipStream_t stream)
+hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream)
 {
-    if (nmax == 0) return hipSuccess;
+    if (p.batch == 0) return hipSuccess;
     if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_build_tables, dim3((nmax + 3) / 4), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(k_build_tables, dim3((p.batch + 3) / 4), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     const u32 n = *p.giant_len;
     const u32 mask = p.tsize - 1;
     // per-lane state
-    u32 idx = 0, ng = 0;
+    u32 idx = 0, item = 0, ng = 0;
     double dd = 0.0, sd = 0.0, L = 0.0;
     float sf = 0.f;
     double m1Q = 0.0, m1P = 0.0, cQ = 0.0, cP = 0.0;
@@ -270,8 +273,9 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 } else {
                     const u32 pos = p.giant_list[g];
                     const WindowState st = p.state[pos];
-                    idx = st.idx;
-                    const u64 d = p.d0 + 8ull * idx;
+                    item = st.item;
+                    idx = item_bit(p.segs, item);
+                    const u64 d = item_d(p.segs, item);
                     const u64 s64 = isqrt_u64(d);
                     dd = (double)d;
                     sd = (double)s64;
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 active = false;
             } else if (bad || ng >= p.max_giants) {
                 const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                p.fb_list[f] = idx;
+                p.fb_list[f] = item;
                 my_giants += ng;
                 active = false;
             }

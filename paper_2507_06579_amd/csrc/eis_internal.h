@@ -1,5 +1,6 @@
 // eis_internal.h -- declarations shared by the host runtime (eis_api.cpp) and
-// the kernel launchers (eis_kernels.hip).  Not part of the public ABI.
+// the kernel launchers (eis_kernels.hip, eis_infra.hip).  Not part of the
+// public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,10 +11,15 @@ namespace eis {
 typedef uint32_t u32;
 typedef uint64_t u64;
 
-// Candidates handled by one pass of the pipeline.  A multiple of 32, so that
-// every pass starts on a bitmap word, and small enough that every index fits
-// 31 bits.
+// Candidates of one pass of the pipeline (all segments together).  A
+// multiple of 32, so that segments can start on bitmap words.
 constexpr u64 kPassCandidates = u64(1) << 24;
+
+// A pass covers up to kMaxSegments segments (ranges or pieces of ranges).
+// A work item is (segment << kItemShift) | index, index < 2^kItemShift.
+constexpr u32 kMaxSegments = 256;
+constexpr u32 kItemShift = 24;
+constexpr u32 kItemMask = (1u << kItemShift) - 1;
 
 // Candidates per sieve workgroup (one LDS bitmap of kSegWords words).
 constexpr u32 kSegCandidates = 32768;
@@ -26,9 +32,22 @@ struct PrimeEntry {
     u64 inv8;
 };
 
+// One segment of a pass: candidates d0 + 8 i, i < n.
+struct SegInfo {
+    u64 d0;
+    u32 n;
+    u32 word_off;    // first bitmap word of the segment in the pass bitmaps
+    u32 block_off;   // first sieve workgroup of the segment
+    u32 np;          // odd primes p with p^2 <= the segment's largest d
+    u32 roff_off;    // the segment's prime offsets start here
+    u32 method;      // 0 = plain walk, 1 = giant steps
+    u32 count_slot;  // counts go to counts[2 slot] (D) and counts[2 slot + 1] (E)
+    u32 pad;
+};
+
 // Per-pass device counters (one cache line each to avoid false sharing).
 struct PassCounters {
-    u32 list_len;      // number of squarefree candidates written by the sieve
+    u32 list_len;      // number of items in the list this counter belongs to
     u32 pad0[15];
     u32 work_next;     // walk queue head
     u32 pad1[15];
@@ -40,11 +59,22 @@ struct PassCounters {
     u64 pad3[5];
 };
 
+__device__ __forceinline__ u64 item_d(const SegInfo *segs, u32 item)
+{
+    return segs[item >> kItemShift].d0 + 8ull * (item & kItemMask);
+}
+
+// bit of the pass bitmaps that belongs to an item
+__device__ __forceinline__ u32 item_bit(const SegInfo *segs, u32 item)
+{
+    return segs[item >> kItemShift].word_off * 32u + (item & kItemMask);
+}
+
 struct WalkParams {
-    u64 d0;                       // first candidate of the pass
-    const u32 *list;              // compacted squarefree candidate indices
+    const SegInfo *segs;          // segment table of the pass
+    const u32 *list;              // items to walk
     PassCounters *ctr;            // list_len, queue head, error and step counters
-    u32 *eis_words;               // output bitmap, bit i <-> d0 + 8 i
+    u32 *eis_words;               // output bitmaps of the pass
     u32 max_steps;                // per-d step budget
 };
 
@@ -54,19 +84,20 @@ struct WindowState {
     u32 q_bits;   // fp32 bit pattern of Q of mu_1 (the giant step)
     u32 p_bits;   // fp32 bit pattern of P of mu_1, OR its residue (2 bits)
     u32 count;    // dictionary entries written
-    u32 idx;      // candidate index of d in the pass
+    u32 item;     // the d's work item
 };
 
 struct InfraParams {
-    u64 d0;                     // first candidate of the pass
-    const u32 *list;            // compacted squarefree candidate indices of the pass
-    u32 k0, k1;                 // batch: list positions [k0, k1)
-    PassCounters *ctr;          // pass counters: err_count and step statistics
+    const SegInfo *segs;        // segment table of the pass
+    const u32 *list;            // items that take giant steps
+    const PassCounters *list_ctr;  // list_ctr->list_len: number of such items
+    u32 k0, batch;              // this launch handles list positions [k0, k0 + batch)
+    PassCounters *ctr;          // step statistics
     u32 *win_next;              // window-walk queue head (per batch)
     u32 *giant_list;            // batch-relative positions that need giant steps
     u32 *giant_len;             // their number
     u32 *giant_next;            // giant-walk queue head
-    u32 *fb_list;               // candidate indices handed to the plain walk
+    u32 *fb_list;               // items handed to the plain walk
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position
     unsigned long long *lists;  // window lists, tile-interleaved: entry e of batch
@@ -78,21 +109,24 @@ struct InfraParams {
                                 // round(window_scale * d^(1/4) / 16)
     u32 max_steps;              // per-d budget of reduction steps (window)
     u32 max_giants;             // per-d budget of giant steps
-    u32 *eis_words;             // output bitmap of the pass
+    u32 *eis_words;             // output bitmaps of the pass
 };
 
 // Launchers (all enqueue on `stream`, never synchronise).
 hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream);
-hipError_t launch_prime_offsets(const PrimeEntry *primes, u32 nprimes, u64 d0, u64 *roff,
-                                hipStream_t stream);
-hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, u32 nprimes, u32 nsmall,
-                        u32 n, u32 *sq_words, u32 *list, PassCounters *ctr, hipStream_t stream);
+hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u32 nseg,
+                                u32 np_max, u64 *roff, hipStream_t stream);
+hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo *segs,
+                        u32 nseg, u32 nblocks, u32 nsmall, u32 *sq_words, u32 *list_plain,
+                        PassCounters *ctr_plain, u32 *list_giant, PassCounters *ctr_giant,
+                        hipStream_t stream);
 hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream);
-hipError_t launch_popcount_add(const u32 *words, u64 nwords, unsigned long long *out,
-                               hipStream_t stream);
+hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const SegInfo *segs,
+                                u32 nseg, u32 words_max, unsigned long long *counts,
+                                hipStream_t stream);
 
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream);
-hipError_t launch_build_tables(const InfraParams &p, u32 nmax, hipStream_t stream);
+hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream);
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream);
 int walk_window_blocks_per_cu();
 int walk_giant_blocks_per_cu();

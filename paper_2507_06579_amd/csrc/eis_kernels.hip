@@ -55,98 +55,121 @@ __device__ __forceinline__ u64 mulmod_small(u64 a, u64 b, u64 m)
 }
 
 // ---------------------------------------------------------------------------
-// k_prime_offsets: roff[k] = i_k, the least i >= 0 with m_k | d0 + 8 i, i.e.
-// i = (-d0) * 8^{-1} (mod m_k).
+// k_prime_offsets: for segment s (blockIdx.y) and prime k < np_s,
+// roff[roff_off_s + k] = the least i >= 0 with m_k | d0_s + 8 i, that is
+// i = (-d0_s) * 8^{-1} (mod m_k).
 // ---------------------------------------------------------------------------
-__global__ void k_prime_offsets(const PrimeEntry *__restrict__ primes, u32 nprimes, u64 d0,
-                                u64 *__restrict__ roff)
+__global__ void k_prime_offsets(const PrimeEntry *__restrict__ primes,
+                                const SegInfo *__restrict__ segs, u64 *__restrict__ roff)
 {
-    u32 k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nprimes) return;
-    u64 m = primes[k].m;
-    u64 r = d0 % m;
-    u64 neg = r ? m - r : 0;
-    roff[k] = mulmod_small(neg, primes[k].inv8, m);
+    const SegInfo sg = segs[blockIdx.y];
+    const u32 k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= sg.np) return;
+    const u64 m = primes[k].m;
+    const u64 r = sg.d0 % m;
+    const u64 neg = r ? m - r : 0;
+    roff[sg.roff_off + k] = mulmod_small(neg, primes[k].inv8, m);
 }
 
-hipError_t launch_prime_offsets(const PrimeEntry *primes, u32 nprimes, u64 d0, u64 *roff,
-                                hipStream_t stream)
+hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u32 nseg,
+                                u32 np_max, u64 *roff, hipStream_t stream)
 {
-    if (nprimes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prime_offsets, dim3((nprimes + 255) / 256), dim3(256), 0, stream,
-                       primes, nprimes, d0, roff);
+    if (np_max == 0 || nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prime_offsets, dim3((np_max + 255) / 256, nseg), dim3(256), 0, stream,
+                       primes, segs, roff);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// k_sieve: one workgroup per segment of kSegCandidates candidates.
-//   1. LDS bitmap <- all candidates of the segment that lie below n
+// k_sieve: one workgroup per block of kSegCandidates candidates of one
+// segment (the segment is found from the workgroup index).
+//   1. LDS bitmap <- all candidates of the block that lie below the
+//      segment's n
 //   2. strike i = roff (mod m) for every prime square m.  The first `nsmall`
-//      primes (m < 4096, many strikes per segment) are spread over all
+//      primes (m < 4096, many strikes per block) are spread over all
 //      threads; each larger prime belongs to one thread.
-//   3. write the bitmap words, and append the surviving indices to the work
-//      list (block-wide prefix sum, one global atomic per segment).
+//   3. write the bitmap words, and append the surviving items to the work
+//      list of the segment's method (block-wide prefix sum, one global atomic
+//      per block).  Workgroups beyond the pass's blocks exit at once, so that
+//      a fixed grid can serve every pass.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ primes,
-                                               const u64 *__restrict__ roff, u32 nprimes,
-                                               u32 nsmall, u32 n, u32 *__restrict__ sq_words,
-                                               u32 *__restrict__ list,
-                                               PassCounters *__restrict__ ctr)
+                                               const u64 *__restrict__ roff,
+                                               const SegInfo *__restrict__ segs, u32 nseg,
+                                               u32 nblocks, u32 nsmall, u32 *__restrict__ sq_words,
+                                               u32 *__restrict__ list_plain,
+                                               PassCounters *__restrict__ ctr_plain,
+                                               u32 *__restrict__ list_giant,
+                                               PassCounters *__restrict__ ctr_giant)
 {
     __shared__ u32 bits[kSegWords];
     __shared__ u32 scan[256];
     __shared__ u32 base_sh;
+    const u32 b = blockIdx.x;
+    if (b >= nblocks) return;
+    // segment of this block: the last s with block_off <= b
+    u32 lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (segs[mid].block_off <= b) lo = mid;
+        else hi = mid;
+    }
+    const SegInfo sg = segs[lo];
     const u32 tid = threadIdx.x;
-    const u32 seg0 = blockIdx.x * kSegCandidates;  // first candidate index of the segment
+    const u32 seg0 = (b - sg.block_off) * kSegCandidates;  // first index of the block
+    const u32 n = sg.n;
     const u32 segn = min(kSegCandidates, n - seg0);
+    const u64 *ro = roff + sg.roff_off;
+    const u32 np = sg.np;
+    const u32 ns = min(nsmall, np);
 
     for (u32 w = tid; w < kSegWords; w += 256) {
-        u32 lo = w * 32;
+        const u32 l0 = w * 32;
         u32 v;
-        if (lo + 32 <= segn) v = 0xffffffffu;
-        else if (lo >= segn) v = 0u;
-        else v = (1u << (segn - lo)) - 1u;
+        if (l0 + 32 <= segn) v = 0xffffffffu;
+        else if (l0 >= segn) v = 0u;
+        else v = (1u << (segn - l0)) - 1u;
         bits[w] = v;
     }
     __syncthreads();
 
     // small prime squares: all threads share each prime's strikes
-    for (u32 k = 0; k < nsmall; k++) {
-        u32 m = (u32)primes[k].m;
-        u32 r = (u32)roff[k];
-        u32 off = seg0 % m;
-        u32 first = (r >= off) ? r - off : r + m - off;  // (r - seg0) mod m
+    for (u32 k = 0; k < ns; k++) {
+        const u32 m = (u32)primes[k].m;
+        const u32 r = (u32)ro[k];
+        const u32 off = seg0 % m;
+        const u32 first = (r >= off) ? r - off : r + m - off;  // (r - seg0) mod m
         for (u32 i = first + tid * m; i < segn; i += 256 * m)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
     // larger prime squares: one prime per thread
-    for (u32 k = nsmall + tid; k < nprimes; k += 256) {
+    for (u32 k = ns + tid; k < np; k += 256) {
         const u64 m = primes[k].m;
-        const u64 r = roff[k];
+        const u64 r = ro[k];
         if (m >= (u64)n) {
-            // at most one strike in the whole pass: index r itself
+            // at most one strike in the whole segment: index r itself
             if (r >= seg0 && r < (u64)seg0 + segn) {
-                u32 i = (u32)r - seg0;
+                const u32 i = (u32)r - seg0;
                 atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
             }
             continue;
         }
-        // here m < n < 2^31, so 32-bit arithmetic is exact
+        // here m < n <= 2^24, so 32-bit arithmetic is exact
         const u32 m32 = (u32)m, r32 = (u32)r;
         const u32 off = seg0 % m32;
-        u32 first = (r32 >= off) ? r32 - off : r32 + m32 - off;  // (r - seg0) mod m
+        const u32 first = (r32 >= off) ? r32 - off : r32 + m32 - off;  // (r - seg0) mod m
         for (u32 i = first; i < segn; i += m32)
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
     __syncthreads();
 
     // write bitmap words and compact the survivors
-    const u32 wbase = seg0 / 32;
+    const u32 wbase = sg.word_off + seg0 / 32;
     u32 cnt = 0;
     u32 wv[kSegWords / 256];
 #pragma unroll
     for (u32 t = 0; t < kSegWords / 256; t++) {
-        u32 w = tid * (kSegWords / 256) + t;
+        const u32 w = tid * (kSegWords / 256) + t;
         wv[t] = bits[w];
         cnt += __popc(wv[t]);
     }
@@ -156,33 +179,37 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
     scan[tid] = cnt;
     __syncthreads();
     for (u32 off = 1; off < 256; off <<= 1) {
-        u32 v = (tid >= off) ? scan[tid - off] : 0u;
+        const u32 v = (tid >= off) ? scan[tid - off] : 0u;
         __syncthreads();
         scan[tid] += v;
         __syncthreads();
     }
+    u32 *list = sg.method ? list_giant : list_plain;
+    PassCounters *ctr = sg.method ? ctr_giant : ctr_plain;
     if (tid == 255) base_sh = atomicAdd(&ctr->list_len, scan[255]);
     __syncthreads();
     u32 pos = base_sh + scan[tid] - cnt;
+    const u32 tag = (u32)lo << kItemShift;
 #pragma unroll
     for (u32 t = 0; t < kSegWords / 256; t++) {
         u32 v = wv[t];
-        u32 ibase = seg0 + (tid * (kSegWords / 256) + t) * 32;
+        const u32 ibase = seg0 + (tid * (kSegWords / 256) + t) * 32;
         while (v) {
-            u32 b = __ffs(v) - 1;
+            const u32 bb = __ffs(v) - 1;
             v &= v - 1;
-            list[pos++] = ibase + b;
+            list[pos++] = tag | (ibase + bb);
         }
     }
 }
 
-hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, u32 nprimes, u32 nsmall,
-                        u32 n, u32 *sq_words, u32 *list, PassCounters *ctr, hipStream_t stream)
+hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo *segs,
+                        u32 nseg, u32 nblocks, u32 nsmall, u32 *sq_words, u32 *list_plain,
+                        PassCounters *ctr_plain, u32 *list_giant, PassCounters *ctr_giant,
+                        hipStream_t stream)
 {
-    if (n == 0) return hipSuccess;
-    u32 nseg = (n + kSegCandidates - 1) / kSegCandidates;
-    hipLaunchKernelGGL(k_sieve, dim3(nseg), dim3(256), 0, stream, primes, roff, nprimes, nsmall,
-                       n, sq_words, list, ctr);
+    if (nblocks == 0 || nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sieve, dim3(nblocks), dim3(256), 0, stream, primes, roff, segs, nseg,
+                       nblocks, nsmall, sq_words, list_plain, ctr_plain, list_giant, ctr_giant);
     return hipGetLastError();
 }
 
@@ -225,9 +252,10 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
                 if (k >= n) {
                     exhausted = true;
                 } else {
-                    idx = p.list[k];
+                    const u32 item = p.list[k];
+                    idx = item_bit(p.segs, item);
                     my_refills++;
-                    u64 d = p.d0 + 8ull * idx;
+                    u64 d = item_d(p.segs, item);
                     u64 si = isqrt_u64(d);
                     // first step from (P_0, Q_0) = (1, 2), in 64-bit integers
                     u64 P1 = ((si + 1) >> 1) * 2 - 1;
@@ -324,33 +352,49 @@ int walk_baby_blocks_per_cu()
 }
 
 // ---------------------------------------------------------------------------
-// k_popcount_add: *out += number of set bits in words[0 .. nwords)
+// k_popcount_segs: for segment s (blockIdx.y), add the set bits of its
+// squarefree and Eisenstein bitmap words to counts[2 slot_s] and
+// counts[2 slot_s + 1].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_popcount_add(const u32 *__restrict__ words, u64 nwords,
-                                                      unsigned long long *out)
+__global__ __launch_bounds__(256) void k_popcount_segs(const u32 *__restrict__ sq_words,
+                                                       const u32 *__restrict__ eis_words,
+                                                       const SegInfo *__restrict__ segs,
+                                                       unsigned long long *counts)
 {
-    __shared__ unsigned long long red[4];
-    unsigned long long c = 0;
-    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 stride = (u64)gridDim.x * blockDim.x;
-    for (; i < nwords; i += stride) c += __popc(words[i]);
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __shared__ unsigned long long red[2][4];
+    const SegInfo sg = segs[blockIdx.y];
+    const u32 nw = (sg.n + 31) / 32;
+    unsigned long long cs = 0, ce = 0;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) {
+        cs += __popc(sq_words[sg.word_off + i]);
+        ce += __popc(eis_words[sg.word_off + i]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        cs += __shfl_down(cs, off, 64);
+        ce += __shfl_down(ce, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = cs;
+        red[1][threadIdx.x >> 6] = ce;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = red[0] + red[1] + red[2] + red[3];
-        if (t) atomicAdd(out, t);
+        const unsigned long long ts = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const unsigned long long te = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        if (ts) atomicAdd(&counts[2 * sg.count_slot], ts);
+        if (te) atomicAdd(&counts[2 * sg.count_slot + 1], te);
     }
 }
 
-hipError_t launch_popcount_add(const u32 *words, u64 nwords, unsigned long long *out,
-                               hipStream_t stream)
+hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const SegInfo *segs,
+                                u32 nseg, u32 words_max, unsigned long long *counts,
+                                hipStream_t stream)
 {
-    if (nwords == 0) return hipSuccess;
-    u64 blocks = (nwords + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_popcount_add, dim3((u32)blocks), dim3(256), 0, stream, words, nwords,
-                       out);
+    if (nseg == 0 || words_max == 0) return hipSuccess;
+    u32 bx = (words_max + 255) / 256;
+    if (bx > 256) bx = 256;
+    hipLaunchKernelGGL(k_popcount_segs, dim3(bx, nseg), dim3(256), 0, stream, sq_words,
+                       eis_words, segs, counts);
     return hipGetLastError();
 }
 
