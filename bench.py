@@ -24,12 +24,17 @@ if ROOT not in sys.path:
 METRIC = "discriminants classified/sec and baby-steps/sec at d≈1e11; p99 query latency"
 TABLE1_LARGE = 3345503
 
-# 32-bit VALU lane-operations per second of MI355X: 256 CUs x 4 SIMD x 16
-# lanes x 2.4 GHz.
+# VALU issue rate of MI355X in 32-bit lane-instructions per second: 256 CUs
+# x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction takes 4 cycles).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic lane-operations of one reduction step (partial quotient with
-# exact correction, the P and Q updates, the Z/3 residue, two exit tests).
-OPS_PER_BABY_STEP = 16
+# VALU instructions per rho step of the walk kernels, counted in the gfx950
+# code of the built loops (two steps per iteration, averaged).  The
+# reciprocal estimate issues on the transcendental unit beside them and is
+# not counted.  Plain walk: quotient with one correction (7), P and Q updates
+# (3), Z/3 residue (3), two exit tests (2), plus a register move every other
+# step.  Window walk: the same step plus the distinguished-ideal test (3),
+# the step index, and the end-of-window tests once per two steps.
+VALU_PER_STEP = {"walk_plain": 15.5, "walk_handoff": 15.5, "walk_window": 24.0}
 
 
 def log(msg):
@@ -71,6 +76,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="auto", choices=["auto", "baby", "infra"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="auto method without running the autotuner first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=100.0)
@@ -94,7 +101,13 @@ def main():
     sq = torch.zeros(nb, dtype=torch.uint8, device=dev)
     eb = torch.zeros(nb, dtype=torch.uint8, device=dev)
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
-    ctx = eis.Context(device=0, method=method)
+    ctx = eis.Context(device=0, method=method, flags=eis.EIS_FLAG_KERNEL_TIMES)
+    if method == eis.Method.AUTO and not args.no_tune:
+        t = time.perf_counter()
+        ctx.eis_tune()
+        log(f"autotuner: {time.perf_counter() - t:.1f} s")
+    chosen, wscale = ctx.eis_tuned_choice(a)
+    log(f"method at d={a}: {chosen.name}, window scale {wscale}")
 
     def step():
         ctx.eis_classify_async(a, b, sq.data_ptr(), eb.data_ptr(), counts.data_ptr(), 0)
@@ -124,20 +137,34 @@ def main():
     n_sq, n_e = counts.cpu().tolist()
     if n_e != TABLE1_LARGE:
         raise SystemExit(f"pi_E of the window is {n_e}, Table 1 says {TABLE1_LARGE}")
+    kms = [x - y for x, y in zip(st["kernel_ms"], base["kernel_ms"])]
+    kl = [x - y for x, y in zip(st["kernel_launches"], base["kernel_launches"])]
+    ks = [x - y for x, y in zip(st["kernel_steps"], base["kernel_steps"])]
     discs = st["discriminants"] - base["discriminants"]
     baby = st["baby_steps"] - base["baby_steps"]
     giant = st["giant_steps"] - base["giant_steps"]
     value = discs / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    avg_walk_s = sum(walk_ms) / len(walk_ms) / 1e3
-    ops_per_launch = OPS_PER_BABY_STEP * baby / args.steps
-    achieved = ops_per_launch / avg_walk_s
+    kernels = {}
+    for k, name in enumerate(eis.KERNELS):
+        if kl[k]:
+            kernels[name] = {"ms_per_step": round(kms[k] / args.steps, 3),
+                             "launches_per_step": kl[k] / args.steps,
+                             "rho_steps_per_step": ks[k] // args.steps}
+    # dominant kernel among the walks with an instruction count per step
+    dom = max(VALU_PER_STEP, key=lambda name: kms[eis.KERNELS.index(name)])
+    kd = eis.KERNELS.index(dom)
+    avg_launch_s = kms[kd] / kl[kd] / 1e3
+    units_per_launch = ks[kd] / kl[kd]
+    achieved = VALU_PER_STEP[dom] * units_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-instr/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
-                "kernel": "k_walk_baby",
-                "ops_per_unit": OPS_PER_BABY_STEP, "units_per_launch": int(baby / args.steps),
-                "avg_launch_ms": round(avg_walk_s * 1e3, 3)}
+                "kernel": "k_walk_baby" if dom != "walk_window" else "k_walk_window",
+                "ops_per_unit": VALU_PER_STEP[dom], "unit_of_work": "rho step",
+                "units_per_launch": int(units_per_launch),
+                "avg_launch_ms": round(avg_launch_s * 1e3, 3),
+                "share_of_step_time": round(kms[kd] / (1e3 * elapsed), 3)}
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -153,10 +180,12 @@ def main():
         "data": "synthetic: the integer range itself (no dataset)",
         "config": {"workload": f"large height: all d = 5 mod 8 in [{a}, {b})",
                    "candidates": n, "members_of_D": n_sq, "pi_E": n_e,
-                   "method": args.method},
+                   "method": args.method, "chosen_method": chosen.name.lower(),
+                   "window_scale": wscale},
         "baby_steps_per_s": round(baby / elapsed, 1),
         "fallbacks_per_step": (st["fallbacks"] - base["fallbacks"]) // args.steps,
         "giant_steps_per_s": round(giant / elapsed, 1),
+        "kernels": kernels,
         "roofline": roofline,
     }
     if not args.no_serving:

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 1
+#define EIS_ABI_VERSION 2
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -77,7 +77,22 @@ typedef enum {
 } eis_method;
 
 /* eis_config.flags bits */
-#define EIS_FLAG_NO_GRAPHS 1u  /* run batched passes as plain launches, not hipGraph replays */
+#define EIS_FLAG_NO_GRAPHS 1u    /* run batched passes as plain launches, not hipGraph replays */
+#define EIS_FLAG_KERNEL_TIMES 2u /* time every kernel launch of plain (non-graph) passes with
+                                    events on the launch stream; totals in eis_stats */
+
+/* Kernels of a pass, for the per-kernel entries of eis_stats. */
+typedef enum {
+    EIS_K_PRIME_OFFSETS = 0, /* first multiple of every p^2 in each segment */
+    EIS_K_SIEVE = 1,         /* squarefree sieve and work-list compaction */
+    EIS_K_WALK_PLAIN = 2,    /* rho walk to the half-period exit (Section 3.1) */
+    EIS_K_WALK_WINDOW = 3,   /* giant-step method: baby window and dictionary */
+    EIS_K_BUILD_TABLES = 4,  /* giant-step method: dictionary hash tables */
+    EIS_K_WALK_GIANT = 5,    /* giant-step method: giant steps with lookups */
+    EIS_K_WALK_HANDOFF = 6,  /* plain walk of the d's the giant-step method handed off */
+    EIS_K_POPCOUNT = 7,      /* per-segment counts */
+    EIS_K_COUNT = 8
+} eis_kernel;
 
 typedef struct {
     int device;                /* HIP device ordinal */
@@ -101,6 +116,12 @@ typedef struct {
     uint64_t requests_done;    /* serving requests completed */
     double last_walk_ms;       /* device time of the last walk launch(es) */
     double last_total_ms;      /* device time of the last whole classify */
+    /* per eis_kernel: rho steps executed by that kernel (walk kernels only) */
+    uint64_t kernel_steps[EIS_K_COUNT];
+    /* per eis_kernel, only with EIS_FLAG_KERNEL_TIMES: timed launches and
+     * their summed device time */
+    uint64_t kernel_launches[EIS_K_COUNT];
+    double kernel_ms[EIS_K_COUNT];
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */
@@ -136,13 +157,17 @@ int eis_classify(eis_ctx *ctx, uint64_t a, uint64_t b, uint8_t *sqfree_bits,
  * d_sqfree_bits / d_eis_bits: device buffers of ceil(n/8) bytes or NULL.
  * d_counts2: device uint64_t[2] receiving {n_sqfree, n_eis}, or NULL.
  * Returns after enqueueing; results are valid once the stream reaches them.
- * Step-budget overruns are reported by the next synchronous call on this
- * context, or by eis_last_error. */
+ * Ranges of more than 2^24 candidates wait on the host between passes (the
+ * pass buffers are reused); the last pass is left running.  The next call on
+ * the context that runs a pass waits for it first.  Step-budget overruns
+ * (EIS_EINTERNAL) are reported by eis_last_error. */
 int eis_classify_async(eis_ctx *ctx, uint64_t a, uint64_t b, void *d_sqfree_bits,
                        void *d_eis_bits, uint64_t *d_counts2, void *hip_stream);
 
-/* Status of the last completed asynchronous call (EIS_OK or EIS_EINTERNAL);
- * synchronises the context's stream. */
+/* Status of the asynchronous calls since the last eis_last_error (EIS_OK,
+ * or EIS_EINTERNAL if a walk of theirs overran its step budget).  Waits for
+ * the last pass they left running, on the stream it was enqueued on (which
+ * must still exist). */
 int eis_last_error(eis_ctx *ctx);
 
 /* n ranges [a[k], b[k]) counted together (Section 1 counts, per range).
@@ -175,6 +200,24 @@ int eis_wait(eis_ctx *ctx, uint64_t ticket, int64_t timeout_us, uint64_t *n_sqfr
 /* Cancel a pending ticket (its eis_wait returns EIS_ECANCELED).  A request
  * whose work is already on the device finishes there and is discarded. */
 int eis_cancel(eis_ctx *ctx, uint64_t ticket);
+
+/* ----- Autotuner ----------------------------------------------------- */
+
+/* Time the plain walk and the giant-step method (window scales 1 to 7) on
+ * sample ranges of 2^21 candidates starting at 10^6.5, 10^7.5, ..., 10^11.5
+ * and keep, per height decade 10^k <= d < 10^(k+1), the faster method and its
+ * best window scale (below 10^6: the plain walk).  The AUTO method then
+ * follows these choices (an explicit method or window scale in the config
+ * still wins).  With cfg.tune_cache_path set at eis_create, the choices are
+ * loaded from that file when it exists and holds every decade, and eis_tune
+ * writes them there (EIS_EINVAL if the file cannot be written; the choices
+ * are in force anyway).  Every choice gives the same bits; only the time
+ * differs.  Takes a few seconds.  Thread-safe against the other calls. */
+int eis_tune(eis_ctx *ctx);
+
+/* The choice in force for height d: *method (an eis_method, BABY or INFRA)
+ * and *window_scale. */
+int eis_tuned_choice(eis_ctx *ctx, uint64_t d, int *method, double *window_scale);
 
 /* Counters since eis_create. */
 int eis_get_stats(eis_ctx *ctx, eis_stats *out);

@@ -8,6 +8,9 @@ needs it does, and raises if it was not built.
 from ._lib import (  # noqa: F401
     EIS_MAX_D,
     EIS_FLAG_NO_GRAPHS,
+    EIS_FLAG_KERNEL_TIMES,
+    KERNELS,
+    ABI_VERSION,
     EisError,
     Context,
     Status,

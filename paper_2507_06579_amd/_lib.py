@@ -13,13 +13,18 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
+ABI_VERSION = 2  # must match EIS_ABI_VERSION of include/eis.h
 EIS_FLAG_NO_GRAPHS = 1
+EIS_FLAG_KERNEL_TIMES = 2
+# eis_kernel: index of the per-kernel entries of the stats
+KERNELS = ["prime_offsets", "sieve", "walk_plain", "walk_window", "build_tables", "walk_giant",
+           "walk_handoff", "popcount"]
 
 EXPORTED_SYMBOLS = [
     "eis_config_default", "eis_create", "eis_destroy", "eis_num_candidates",
     "eis_first_candidate", "eis_count", "eis_classify", "eis_classify_async",
     "eis_last_error", "eis_count_batch", "eis_submit", "eis_wait", "eis_cancel",
-    "eis_get_stats", "eis_strerror", "eis_abi_version",
+    "eis_get_stats", "eis_strerror", "eis_abi_version", "eis_tune", "eis_tuned_choice",
 ]
 
 
@@ -65,10 +70,17 @@ class EisStats(ctypes.Structure):
         ("requests_done", ctypes.c_uint64),
         ("last_walk_ms", ctypes.c_double),
         ("last_total_ms", ctypes.c_double),
+        ("kernel_steps", ctypes.c_uint64 * 8),
+        ("kernel_launches", ctypes.c_uint64 * 8),
+        ("kernel_ms", ctypes.c_double * 8),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name.startswith("kernel_") else v
+        return out
 
 
 class EisError(RuntimeError):
@@ -124,6 +136,12 @@ def lib():
     L.eis_get_stats.argtypes = [vp, P(EisStats)]; L.eis_get_stats.restype = c_int
     L.eis_strerror.argtypes = [c_int]; L.eis_strerror.restype = ctypes.c_char_p
     L.eis_abi_version.argtypes = []; L.eis_abi_version.restype = c_int
+    L.eis_tune.argtypes = [vp]; L.eis_tune.restype = c_int
+    L.eis_tuned_choice.argtypes = [vp, u64, P(c_int), P(ctypes.c_double)]
+    L.eis_tuned_choice.restype = c_int
+    if L.eis_abi_version() != ABI_VERSION:
+        raise OSError(f"{_LIB_PATH} has ABI version {L.eis_abi_version()}, this binding "
+                      f"expects {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 
@@ -154,7 +172,7 @@ class Context:
 
     def __init__(self, device: int = 0, method: int = Method.AUTO, mem_budget_bytes: int = 0,
                  max_steps_per_d: int = 0, window_scale: float = 0.0, serve_slots: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, tune_cache_path: str | None = None):
         L = lib()
         cfg = EisConfig()
         L.eis_config_default(ctypes.byref(cfg))
@@ -165,6 +183,8 @@ class Context:
         cfg.window_scale = window_scale
         cfg.serve_slots = serve_slots
         cfg.flags = flags
+        path = tune_cache_path.encode() if tune_cache_path else None
+        cfg.tune_cache_path = path
         h = ctypes.c_void_p()
         _check(L.eis_create(ctypes.byref(cfg), ctypes.byref(h)), "eis_create")
         self._h = h
@@ -246,6 +266,16 @@ class Context:
 
     def eis_cancel(self, ticket: int):
         _check(lib().eis_cancel(self._h, ticket), "eis_cancel")
+
+    def eis_tune(self):
+        _check(lib().eis_tune(self._h), "eis_tune")
+
+    def eis_tuned_choice(self, d: int):
+        """(method, window_scale) in force for height d."""
+        m, w = ctypes.c_int(0), ctypes.c_double(0.0)
+        _check(lib().eis_tuned_choice(self._h, d, ctypes.byref(m), ctypes.byref(w)),
+               "eis_tuned_choice")
+        return Method(m.value), float(w.value)
 
     def eis_get_stats(self):
         st = EisStats()

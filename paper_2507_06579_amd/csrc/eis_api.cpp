@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -89,6 +90,7 @@ struct HostSeg {
     u32 n;
     u32 slot;      // count slot
     u32 method;    // 0 plain walk, 1 giant steps
+    float wscale;  // giant steps: window scale of the segment
     u64 dst_bit;   // candidate offset of the segment in the caller's bitmap
 };
 
@@ -117,6 +119,11 @@ struct eis_ctx {
     double window_scale = kDefaultWindowScale;
     u64 infra_min_height = kDefaultInfraMinHeight;
     bool use_graphs = true;
+    // autotuner choices per height decade 10^k, k = 0..12
+    bool tuned = false;
+    int tuned_method[13] = {};
+    double tuned_ws[13] = {};
+    std::string tune_path;
 
     // prime table
     std::vector<u32> primes_host;
@@ -140,11 +147,19 @@ struct eis_ctx {
     u64 h_counts_cap = 0;
     u32 *d_q = nullptr;              // giant-step queue heads (3 cache lines)
     bool pass_ready = false;
+    bool uncollected = false;            // a pass whose counters nobody has read yet
+    hipStream_t pending_stream = nullptr;  // the stream it runs on
+
+    // per-kernel timing (EIS_FLAG_KERNEL_TIMES): event pairs of this pass
+    bool kernel_times = false;
+    std::vector<hipEvent_t> kev;
+    std::vector<int> kev_kind;
+    u32 kev_used = 0;
 
     // giant-step scratch
     WindowState *d_state = nullptr;
     unsigned long long *d_lists = nullptr;
-    unsigned long long *d_tables = nullptr;
+    u32 *d_tables = nullptr;
     u32 *d_glist = nullptr;
     u64 infra_batch_cap = 0;
     u32 infra_emax_cap = 0;
@@ -226,6 +241,37 @@ extern "C" void eis_config_default(eis_config *cfg)
     cfg->method = EIS_METHOD_AUTO;
 }
 
+// Autotuner cache: a small JSON object written by eis_tune,
+//   {"arch": "gfx950", "decades": [{"k": 6, "method": 0, "window_scale": 3.5, ...}, ...]}
+// read back by scanning for the three keys of every decade.
+static void load_tune_cache(eis_ctx *c)
+{
+    FILE *f = std::fopen(c->tune_path.c_str(), "r");
+    if (!f) return;
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    if (txt.find("\"gfx950\"") == std::string::npos) return;
+    int seen = 0;
+    size_t at = 0;
+    while ((at = txt.find("\"k\":", at)) != std::string::npos) {
+        int k = -1, m = -1;
+        double ws = 0.0;
+        const char *q = txt.c_str() + at;
+        if (std::sscanf(q, "\"k\": %d, \"method\": %d, \"window_scale\": %lf", &k, &m, &ws) == 3 &&
+            k >= 0 && k <= 12 && (m == 0 || m == 1) && ws > 0.0 && ws < 100.0) {
+            c->tuned_method[k] = m;
+            c->tuned_ws[k] = ws;
+            seen |= 1 << k;
+        }
+        at += 4;
+    }
+    // every decade must be present
+    if (seen == (1 << 13) - 1) c->tuned = true;
+}
+
 static void free_infra(eis_ctx *c)
 {
     (void)hipFree(c->d_state);
@@ -233,7 +279,8 @@ static void free_infra(eis_ctx *c)
     (void)hipFree(c->d_tables);
     (void)hipFree(c->d_glist);
     c->d_state = nullptr;
-    c->d_lists = c->d_tables = nullptr;
+    c->d_lists = nullptr;
+    c->d_tables = nullptr;
     c->d_glist = nullptr;
     c->infra_batch_cap = 0;
     c->infra_emax_cap = c->infra_tsize_cap = 0;
@@ -279,6 +326,7 @@ extern "C" void eis_destroy(eis_ctx *c)
     if (c->h_counts) (void)hipHostFree(c->h_counts);
     if (c->ev_walk0) (void)hipEventDestroy(c->ev_walk0);
     if (c->ev_walk1) (void)hipEventDestroy(c->ev_walk1);
+    for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
     if (c->ev_all0) (void)hipEventDestroy(c->ev_all0);
     if (c->ev_all1) (void)hipEventDestroy(c->ev_all1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -291,7 +339,7 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     eis_config def;
     eis_config_default(&def);
     if (!cfg) cfg = &def;
-    if ((cfg->flags & ~(uint32_t)EIS_FLAG_NO_GRAPHS) != 0) return EIS_EINVAL;
+    if ((cfg->flags & ~(uint32_t)(EIS_FLAG_NO_GRAPHS | EIS_FLAG_KERNEL_TIMES)) != 0) return EIS_EINVAL;
     if (cfg->method < EIS_METHOD_BABY || cfg->method > EIS_METHOD_AUTO) return EIS_EINVAL;
     if (cfg->window_scale < 0) return EIS_EINVAL;
 
@@ -305,12 +353,14 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     eis_ctx *c = new (std::nothrow) eis_ctx();
     if (!c) return EIS_ENOMEM;
     c->cfg = *cfg;
-    c->cfg.tune_cache_path = nullptr;  // not retained beyond the call
+    if (cfg->tune_cache_path) c->tune_path = cfg->tune_cache_path;
+    c->cfg.tune_cache_path = nullptr;  // the context keeps its own copy
     if (c->cfg.max_steps_per_d == 0) c->cfg.max_steps_per_d = kDefaultMaxSteps;
     if (c->cfg.max_steps_per_d > 0xffff0000ull) c->cfg.max_steps_per_d = 0xffff0000ull;
     if (c->cfg.serve_slots == 0) c->cfg.serve_slots = kDefaultServeSlots;
     c->window_scale = cfg->window_scale > 0 ? cfg->window_scale : kDefaultWindowScale;
     c->use_graphs = (cfg->flags & EIS_FLAG_NO_GRAPHS) == 0;
+    c->kernel_times = (cfg->flags & EIS_FLAG_KERNEL_TIMES) != 0;
     c->device = cfg->device;
     c->num_cu = prop.multiProcessorCount;
     int rc = EIS_OK;
@@ -347,6 +397,7 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
         c->walk_blocks_per_cu = walk_baby_blocks_per_cu();
         c->window_blocks_per_cu = walk_window_blocks_per_cu();
         c->giant_blocks_per_cu = walk_giant_blocks_per_cu();
+        if (!c->tune_path.empty()) load_tune_cache(c);
     } while (0);
     if (rc != EIS_OK) {
         eis_destroy(c);
@@ -429,10 +480,10 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)(emax + tsize) * 8 + sizeof(WindowState) + sizeof(u32));
+    const u64 bytes = cap * ((u64)emax * 8 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(u32));
     if (c->cfg.mem_budget_bytes && c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
-        hipMalloc(&c->d_tables, cap * tsize * 8) != hipSuccess ||
+        hipMalloc(&c->d_tables, cap * tsize * 4) != hipSuccess ||
         hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
         hipMalloc(&c->d_glist, cap * sizeof(u32)) != hipSuccess) {
         free_infra(c);
@@ -454,9 +505,9 @@ static u32 primes_needed(const eis_ctx *c, u64 dmax)
 }
 
 // Dictionary geometry for heights up to dmax.
-static void infra_geometry(double window_scale, u64 dmax, u32 &emax, u32 &tsize)
+static void infra_geometry(double scaled_root, u32 &emax, u32 &tsize)
 {
-    double n = window_scale * std::pow((double)dmax, 0.25) / 16.0;
+    double n = scaled_root / 16.0;
     u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
     emain = std::max<u32>(emain, 16);
     emax = emain + 16;
@@ -466,11 +517,27 @@ static void infra_geometry(double window_scale, u64 dmax, u32 &emax, u32 &tsize)
     while (tsize < 2 * (std::min(emain, emax - 8) + 4)) tsize <<= 1;
 }
 
+// k with 10^k <= d < 10^(k+1), at most 12
+static int decade_of(u64 d)
+{
+    int k = 0;
+    for (u64 p = 10; k < 12 && d >= p; p *= 10) k++;
+    return k;
+}
+
 static u32 method_for(const eis_ctx *c, u64 d0)
 {
     if (c->cfg.method == EIS_METHOD_INFRA) return 1;
     if (c->cfg.method == EIS_METHOD_BABY) return 0;
+    if (c->tuned) return (u32)c->tuned_method[decade_of(d0)];
     return d0 >= c->infra_min_height ? 1 : 0;
+}
+
+static double scale_for(const eis_ctx *c, u64 d0)
+{
+    if (c->cfg.window_scale > 0) return c->cfg.window_scale;
+    if (c->tuned) return c->tuned_ws[decade_of(d0)];
+    return c->window_scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -493,7 +560,8 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     pl = PassPlan();
     pl.nseg = (u32)segs.size();
     u32 word = 0, block = 0;
-    u64 roff = 0, dmax_giant = 0;
+    u64 roff = 0;
+    double nmax_giant = 0.0;  // largest wscale * d^(1/4) of the giant-step segments
     for (u32 s = 0; s < pl.nseg; s++) {
         const HostSeg &h = segs[s];
         SegInfo &g = c->h_segs[s];
@@ -506,14 +574,14 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
         g.roff_off = (u32)roff;
         g.method = h.method;
         g.count_slot = h.slot;
-        g.pad = 0;
+        g.wscale = h.wscale;
         word += (h.n + 31) / 32;
         block += (h.n + kSegCandidates - 1) / kSegCandidates;
         roff += g.np;
         pl.np_max = std::max(pl.np_max, g.np);
         if (h.method) {
             pl.giant_cand += h.n;
-            dmax_giant = std::max(dmax_giant, dlast);
+            nmax_giant = std::max(nmax_giant, (double)g.wscale * std::pow((double)dlast, 0.25));
         } else {
             pl.plain_cand += h.n;
         }
@@ -525,7 +593,7 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     pl.grid_plain = (u32)std::min<u64>((pl.plain_cand + 255) / 256, max_plain);
     pl.grid_fb = (u32)c->num_cu;
     if (pl.giant_cand) {
-        infra_geometry(c->window_scale, dmax_giant, pl.emax, pl.tsize);
+        infra_geometry(nmax_giant, pl.emax, pl.tsize);
         pl.batch = std::min<u64>(pl.giant_cand, kInfraBatch);
         pl.nbatches = (u32)((pl.giant_cand + pl.batch - 1) / pl.batch);
         const u64 max_win = (u64)c->num_cu * c->window_blocks_per_cu;
@@ -535,16 +603,57 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     }
 }
 
+static int collect_pass(eis_ctx *c);
+
+// Per-kernel timing: an event pair around one launch, read by collect_pass.
+static int kt_begin(eis_ctx *c, hipStream_t st, int kind)
+{
+    const u32 i = c->kev_used;
+    while (c->kev.size() < 2 * (size_t)(i + 1)) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreate(&e));
+        c->kev.push_back(e);
+    }
+    if (c->kev_kind.size() <= i) c->kev_kind.resize(i + 1);
+    c->kev_kind[i] = kind;
+    HIP_TRY(hipEventRecord(c->kev[2 * i], st));
+    return EIS_OK;
+}
+
+static int kt_end(eis_ctx *c, hipStream_t st)
+{
+    HIP_TRY(hipEventRecord(c->kev[2 * c->kev_used + 1], st));
+    c->kev_used++;
+    return EIS_OK;
+}
+
+// one launch, timed when kt
+#define KLAUNCH(kind, expr)                        \
+    do {                                           \
+        if (kt) {                                  \
+            int _r = kt_begin(c, st, (kind));      \
+            if (_r != EIS_OK) return _r;           \
+        }                                          \
+        HIP_TRY(expr);                             \
+        if (kt) {                                  \
+            int _r = kt_end(c, st);                \
+            if (_r != EIS_OK) return _r;           \
+        }                                          \
+    } while (0)
+
 // Enqueue the launch sequence of a planned pass (after the segment table
 // upload).  Captured into graphs by shape.
 static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, bool timed)
 {
     PassCounters *ctr_plain = c->d_ctrs, *ctr_giant = c->d_ctrs + 1, *ctr_fb = c->d_ctrs + 2;
+    const bool kt = timed && c->kernel_times;
     HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctrs), 3 * sizeof(PassCounters) / 4, st));
     HIP_TRY(launch_zero_u32(c->d_eis_words, pl.words, st));
-    HIP_TRY(launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
-    HIP_TRY(launch_sieve(c->d_primes, c->d_roff, c->d_segs, pl.nseg, pl.nblocks, c->nsmall,
-                         c->d_sq_words, c->d_list_plain, ctr_plain, c->d_list_giant, ctr_giant, st));
+    KLAUNCH(EIS_K_PRIME_OFFSETS,
+            launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
+    KLAUNCH(EIS_K_SIEVE, launch_sieve(c->d_primes, c->d_roff, c->d_segs, pl.nseg, pl.nblocks,
+                                      c->nsmall, c->d_sq_words, c->d_list_plain, ctr_plain,
+                                      c->d_list_giant, ctr_giant, st));
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk0, st));
     WalkParams wp;
     wp.segs = c->d_segs;
@@ -553,7 +662,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
     if (pl.plain_cand) {
         wp.list = c->d_list_plain;
         wp.ctr = ctr_plain;
-        HIP_TRY(launch_walk_baby(wp, pl.grid_plain, st));
+        KLAUNCH(EIS_K_WALK_PLAIN, launch_walk_baby(wp, pl.grid_plain, st));
     }
     if (pl.giant_cand) {
         InfraParams ip;
@@ -573,35 +682,33 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.tables = c->d_tables;
         ip.emax = pl.emax;
         ip.tsize = pl.tsize;
-        ip.window_scale = (float)c->window_scale;
         ip.max_steps = (u32)c->cfg.max_steps_per_d;
         ip.max_giants = 1u << 20;
         ip.eis_words = c->d_eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
             HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
-            HIP_TRY(launch_walk_window(ip, pl.grid_win, st));
-            HIP_TRY(launch_build_tables(ip, st));
-            HIP_TRY(launch_walk_giant(ip, pl.grid_giant, st));
+            KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, st));
+            KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, st));
+            KLAUNCH(EIS_K_WALK_GIANT, launch_walk_giant(ip, pl.grid_giant, st));
         }
         // d's handed off by the giant-step method: the plain walk, exact for all d
         wp.list = c->d_fb_list;
         wp.ctr = ctr_fb;
-        HIP_TRY(launch_walk_baby(wp, pl.grid_fb, st));
+        KLAUNCH(EIS_K_WALK_HANDOFF, launch_walk_baby(wp, pl.grid_fb, st));
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk1, st));
-    HIP_TRY(launch_popcount_segs(c->d_sq_words, c->d_eis_words, c->d_segs, pl.nseg,
+    KLAUNCH(EIS_K_POPCOUNT,
+            launch_popcount_segs(c->d_sq_words, c->d_eis_words, c->d_segs, pl.nseg,
                                  (u32)((kPassCandidates + 31) / 32), c->d_counts, st));
     return EIS_OK;
 }
 
 static std::vector<u64> plan_key(const eis_ctx *c, const PassPlan &pl)
 {
-    u64 ws;
-    std::memcpy(&ws, &c->window_scale, sizeof(ws));
     return {pl.nseg, pl.nblocks, pl.np_max, pl.words, pl.plain_cand ? 1ull : 0ull,
             pl.giant_cand ? 1ull : 0ull, pl.emax, pl.tsize, pl.batch, pl.nbatches, pl.grid_plain,
-            pl.grid_win, pl.grid_giant, pl.grid_fb, ws, c->cfg.max_steps_per_d};
+            pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d};
 }
 
 // Run one pass of segments (counts are accumulated into d_counts, which the
@@ -610,6 +717,14 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
                     PassPlan &pl)
 {
     (void)hipGetLastError();  // launch checks below must not see an older error
+    if (c->uncollected) {
+        // the tail pass of an asynchronous call: its buffers are about to be
+        // reused, and its status belongs to eis_last_error
+        HIP_TRY(hipStreamSynchronize(c->pending_stream));
+        int prc = collect_pass(c);
+        if (prc != EIS_OK && c->async_status == EIS_OK) c->async_status = prc;
+    }
+    c->kev_used = 0;
     int rc = ensure_pass_buffers(c);
     if (rc != EIS_OK) return rc;
     plan_pass(c, segs, pl);
@@ -648,6 +763,8 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
         rc = enqueue_pass_body(c, pl, st, true);
         if (rc != EIS_OK) return rc;
     }
+    c->uncollected = true;
+    c->pending_stream = st;
     std::lock_guard<std::mutex> lk(c->stats_mu);
     c->stats.launches += launches;
     return EIS_OK;
@@ -656,15 +773,32 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
 // Read the pass counters after the stream has finished the pass.
 static int collect_pass(eis_ctx *c)
 {
+    c->uncollected = false;
     PassCounters h[3];
     if (hipMemcpy(h, c->d_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
     if (!have_ms) (void)hipGetLastError();
+    std::vector<float> kms(c->kev_used, 0.f);
+    bool have_kms = true;
+    for (u32 i = 0; i < c->kev_used && have_kms; i++)
+        have_kms = hipEventElapsedTime(&kms[i], c->kev[2 * i], c->kev[2 * i + 1]) == hipSuccess;
+    if (!have_kms) (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(c->stats_mu);
     if (have_ms) c->stats.last_walk_ms = wms;
+    if (have_kms) {
+        for (u32 i = 0; i < c->kev_used; i++) {
+            c->stats.kernel_launches[c->kev_kind[i]]++;
+            c->stats.kernel_ms[c->kev_kind[i]] += kms[i];
+        }
+    }
+    c->kev_used = 0;
     c->stats.discriminants += (u64)h[0].list_len + h[1].list_len;
-    c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[2].baby_steps;
+    c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[1].chunk_steps + h[2].baby_steps;
+    c->stats.kernel_steps[EIS_K_WALK_PLAIN] += h[0].baby_steps;
+    c->stats.kernel_steps[EIS_K_WALK_WINDOW] += h[1].baby_steps;
+    c->stats.kernel_steps[EIS_K_WALK_GIANT] += h[1].chunk_steps;
+    c->stats.kernel_steps[EIS_K_WALK_HANDOFF] += h[2].baby_steps;
     c->stats.giant_steps += h[1].giant_steps;
     c->stats.refills += h[0].refills + h[1].refills + h[2].refills;
     c->stats.fallbacks += h[2].list_len;
@@ -699,6 +833,7 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
         segs[0].n = pn;
         segs[0].slot = 0;
         segs[0].method = method_for(c, segs[0].d0);
+        segs[0].wscale = (float)scale_for(c, segs[0].d0);
         segs[0].dst_bit = off;
         PassPlan pl;
         rc = run_pass(c, segs, st, false, pl);
@@ -811,9 +946,11 @@ extern "C" int eis_last_error(eis_ctx *c)
     if (!c) return EIS_EINVAL;
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    HIP_TRY(hipStreamSynchronize(c->stream));
     int rc = EIS_OK;
-    if (c->pass_ready) rc = collect_pass(c);
+    if (c->uncollected) {
+        HIP_TRY(hipStreamSynchronize(c->pending_stream));
+        rc = collect_pass(c);
+    }
     if (rc == EIS_OK) rc = c->async_status;
     c->async_status = EIS_OK;
     return rc;
@@ -843,6 +980,7 @@ static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>>
             h.n = (u32)std::min<u64>(kPassCandidates, n - off);
             h.slot = slot;
             h.method = method_for(c, h.d0);
+            h.wscale = (float)scale_for(c, h.d0);
             h.dst_bit = off;
             pieces.push_back(h);
         }
@@ -957,6 +1095,7 @@ static void server_loop(eis_ctx *c)
                 h.n = (u32)take;
                 h.slot = (u32)segs.size();
                 h.method = method_for(c, h.d0);
+            h.wscale = (float)scale_for(c, h.d0);
                 h.dst_bit = 0;
                 segs.push_back(h);
                 parts.emplace_back(t, take);
@@ -1086,6 +1225,111 @@ extern "C" int eis_cancel(eis_ctx *c, uint64_t ticket)
     }
     c->dcv.notify_all();
     c->scv.notify_all();
+    return EIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+// Device time of one pass over [d0, d0 + 8 n) with a given method and scale.
+static int time_pass(eis_ctx *c, u64 d0, u32 n, u32 method, double ws, float &ms)
+{
+    std::vector<HostSeg> segs(1);
+    segs[0].d0 = d0;
+    segs[0].n = n;
+    segs[0].slot = 0;
+    segs[0].method = method;
+    segs[0].wscale = (float)ws;
+    segs[0].dst_bit = 0;
+    hipStream_t st = c->stream;
+    int rc = ensure_counts(c, 1);
+    if (rc == EIS_OK && launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4, st) != hipSuccess)
+        rc = EIS_EDEVICE;
+    PassPlan pl;
+    if (rc == EIS_OK && hipEventRecord(c->ev_all0, st) != hipSuccess) rc = EIS_EDEVICE;
+    if (rc == EIS_OK) rc = run_pass(c, segs, st, false, pl);
+    if (rc == EIS_OK && hipEventRecord(c->ev_all1, st) != hipSuccess) rc = EIS_EDEVICE;
+    if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
+    if (rc == EIS_OK) {
+        int prc = collect_pass(c);
+        if (prc != EIS_OK) rc = prc;
+    }
+    if (rc == EIS_OK && hipEventElapsedTime(&ms, c->ev_all0, c->ev_all1) != hipSuccess) rc = EIS_EDEVICE;
+    return rc;
+}
+
+extern "C" int eis_tune(eis_ctx *c)
+{
+    if (!c) return EIS_EINVAL;
+    std::lock_guard<std::mutex> g(c->gpu_mu);
+    if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
+    const double scales[] = {1.0, 1.5, 2.5, 3.5, 5.0, 7.0};
+    const u32 n = 1u << 21;  // candidates per sample: enough d's to fill the device
+    int method[13];
+    double wsc[13], plain_ms[13], giant_ms[13];
+    for (int k = 0; k <= 12; k++) {
+        method[k] = 0;
+        wsc[k] = kDefaultWindowScale;
+        plain_ms[k] = giant_ms[k] = 0.0;
+    }
+    float ms = 0.f;
+    // one untimed pass of each method allocates every buffer
+    int rc = time_pass(c, 1000000005ull, n, 0, kDefaultWindowScale, ms);
+    if (rc == EIS_OK) rc = time_pass(c, 1000000005ull, n, 1, 7.0, ms);
+    if (rc != EIS_OK) return rc;
+    // decades 10^6 .. 10^11, sampled at their geometric middle; d < 10^12
+    for (int k = 6; k <= 11; k++) {
+        const u64 d0 = eis_first_candidate((u64)std::llround(std::pow(10.0, k + 0.5)));
+        rc = time_pass(c, d0, n, 0, kDefaultWindowScale, ms);
+        if (rc != EIS_OK) return rc;
+        plain_ms[k] = ms;
+        double best = 1e30, best_ws = kDefaultWindowScale;
+        for (double ws : scales) {
+            rc = time_pass(c, d0, n, 1, ws, ms);
+            if (rc != EIS_OK) return rc;
+            if (ms < best) {
+                best = ms;
+                best_ws = ws;
+            }
+        }
+        giant_ms[k] = best;
+        method[k] = best < plain_ms[k] ? 1 : 0;
+        wsc[k] = best_ws;
+    }
+    // below 10^6 the plain walk; the last decade holds d = 10^12 only
+    for (int k = 0; k < 6; k++) wsc[k] = wsc[6];
+    method[12] = method[11];
+    wsc[12] = wsc[11];
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        for (int k = 0; k <= 12; k++) {
+            c->tuned_method[k] = method[k];
+            c->tuned_ws[k] = wsc[k];
+        }
+        c->tuned = true;
+    }
+    if (!c->tune_path.empty()) {
+        FILE *f = std::fopen(c->tune_path.c_str(), "w");
+        if (!f) return EIS_EINVAL;
+        std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"decades\": [\n", n);
+        for (int k = 0; k <= 12; k++)
+            std::fprintf(f,
+                         "  {\"k\": %d, \"method\": %d, \"window_scale\": %.3f, "
+                         "\"plain_ms\": %.3f, \"giant_ms\": %.3f}%s\n",
+                         k, method[k], wsc[k], plain_ms[k], giant_ms[k], k < 12 ? "," : "");
+        std::fprintf(f, "]}\n");
+        if (std::fclose(f) != 0) return EIS_EINVAL;
+    }
+    return EIS_OK;
+}
+
+extern "C" int eis_tuned_choice(eis_ctx *c, uint64_t d, int *method, double *window_scale)
+{
+    if (!c) return EIS_EINVAL;
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (method) *method = (int)method_for(c, d) ? EIS_METHOD_INFRA : EIS_METHOD_BABY;
+    if (window_scale) *window_scale = scale_for(c, d);
     return EIS_OK;
 }
 

@@ -384,19 +384,17 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
     return S;
 }
 
-// Dictionary keys and slots (shared by the table build and the lookups).
-__device__ __forceinline__ unsigned long long dict_key(u32 Q, u32 P)
-{
-    return ((unsigned long long)Q << 32) | ((unsigned long long)P << 2);
-}
-
-__device__ __forceinline__ u32 dict_slot(u32 Q, u32 P, u32 mask)
+// Dictionary hash of a key (the fp32 bit patterns of Q and P); its low bits
+// pick the first slot, its high 16 bits are the slot's fingerprint.
+__device__ __forceinline__ u32 dict_hash(u32 Q, u32 P)
 {
     u32 h = (Q * 0x9E3779B1u) ^ (P * 0x85EBCA77u);
     h ^= h >> 15;
     h *= 0x2C1B3C6Du;
     h ^= h >> 13;
-    return h & mask;
+    h *= 0x297A2D39u;
+    h ^= h >> 16;
+    return h;
 }
 
 }  // namespace eis

@@ -8,13 +8,15 @@
 //                  half-period symmetry exit; the "distinguished" ideals of
 //                  the walk (Q = 2 mod 64, about one in 16) are appended to
 //                  the d's dictionary list.  mu_1 is the n-th distinguished
-//                  ideal (n = window_scale * d^(1/4) / 16, at least 16); the
+//                  ideal (n = wscale * d^(1/4) / 16, at least 16); the
 //                  window ends at the first distinguished ideal at least six
 //                  steps after mu_1 (the two extra ideals of the algorithm,
 //                  with margin), and that extension must stay within a
 //                  quarter of mu_1's step count.
-//   k_build_tables one wave per d: the list becomes an open-addressed hash
-//                  table, built in LDS and written out whole.
+//   k_build_tables one wave per d: the list is indexed by an open-addressed
+//                  hash table of 32-bit slots (list index + 16-bit
+//                  fingerprint; a fingerprint match is confirmed against the
+//                  list entry), built in LDS and written out whole.
 //   k_walk_giant   one d per lane, lanes refilled from a queue: mu_k =
 //                  reduce(mu_1 * mu_{k-1}) (NUDUPL for k = 2, then NUCOMP),
 //                  the residue updated with log mu_1 + log mu_{k-1} - log gamma
@@ -52,6 +54,7 @@ __device__ __forceinline__ bool is_dp(float Q) { return __builtin_amdgcn_fractf(
 
 constexpr u32 kTableMax = 1024;     // largest table (slots) per d
 constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
+constexpr u32 kWalkChunk = 24;      // of which one iteration of the giant walk takes at most this many
 constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
 constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
 
@@ -66,12 +69,29 @@ __device__ __forceinline__ unsigned long long entry_of(float Q, float P, u32 S)
 // 64 lanes append to one tile of the list array (tile-interleaved layout:
 // the writes of a wave stay within one small region of memory).
 // ---------------------------------------------------------------------------
+// Window bookkeeping of one reduction step that landed on (Q, P) with
+// residue sum S at step jc: append a distinguished ideal to the list (lp
+// points at its next slot), note the step of mu_1 (the emain-th entry) and of
+// the last entry.
+__device__ __forceinline__ void window_insert(unsigned long long *&lp, float Q, float P, u32 S,
+                                              u32 jc, u32 emain, u32 &cnt, u32 &j1, u32 &jlast)
+{
+    if (is_dp(Q)) {
+        *lp = entry_of(Q, P, S);
+        lp += 64;
+        cnt++;
+        j1 = (cnt == emain) ? jc : j1;
+        jlast = jc;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
 {
     const u32 lane = __lane_id();
     const u32 total = p.list_ctr->list_len;
     const u32 nb = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 ntiles = (nb + 63) / 64;
+    const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
     u64 my_steps = 0, my_refills = 0;
 
     for (;;) {
@@ -80,9 +100,9 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
         t = __shfl(t, 0, 64);
         if (t >= ntiles) break;
         const u32 pos = t * 64 + lane;
-        unsigned long long *lst = p.lists + (u64)t * p.emax * 64 + lane;  // entry e at lst[64 e]
+        unsigned long long *lp = p.lists + (u64)t * p.emax * 64 + lane;  // entry e at base[64 e]
         float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
-        u32 S = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1 = 0, m1q = 0, m1p = 0;
+        u32 S = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1 = 0, jlast = 0;
         bool active = false, to_giant = false, to_plain = false;
         u32 item = 0;
         if (pos < nb) {
@@ -103,58 +123,76 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                 Q = (float)Q1;
                 S = S1;
                 // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
-                lst[0] = entry_of(2.f, P, 0u);
+                *lp = entry_of(2.f, P, 0u);
+                lp += 64;
                 cnt = 1;
-                const float n = p.window_scale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
+                const float n = p.segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
                 emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
-                if (is_dp(Q)) {
-                    lst[64] = entry_of(Q, P, S);
-                    cnt = 2;
-                }
+                window_insert(lp, Q, P, S, 1, emain, cnt, j1, jlast);
                 active = true;
             }
         }
-        while (active) {
-            float Pn, Qn;
-            baby_step(s, P, Q, Qp, Pn, Qn, S);
-            j++;
-            if (Qn == Q || Pn == P) {
-                // half-period symmetry: the unit is found without giant steps
-                const u32 rj = 1u + (((u32)Pn >> 1) & 1u);
-                const u32 v = (Qn == Q) ? (2u * S - rj) : (2u * (S - rj));
-                emit_flag(p.eis_words, idx, v % 3u == 0u);
-                active = false;
-            } else {
-                Qp = Q;
-                Q = Qn;
-                P = Pn;
-                if (is_dp(Q)) {
-                    lst[(u64)cnt * 64] = entry_of(Q, P, S);
-                    cnt++;
-                    if (cnt == emain) {
-                        m1q = __float_as_uint(Q);
-                        m1p = __float_as_uint(P) | (S % 3u);
-                        j1 = j;
-                    } else if (j1 != 0 && j >= j1 + kExtraSteps) {
-                        // end of the window; its extension past mu_1 must be
-                        // short next to mu_1's own distance (see above)
-                        if (j - j1 <= j1 / 4 && cnt < p.emax) {
-                            WindowState st;
-                            st.q_bits = m1q;
-                            st.p_bits = m1p;
-                            st.count = cnt;
-                            st.item = item;
-                            p.state[pos] = st;
-                            to_giant = true;
-                        } else {
-                            to_plain = true;
-                        }
-                        active = false;
+        while (__any(active)) {
+            if (active) {
+                // Two steps per iteration; the loop leaves as soon as any lane
+                // reaches the half-period or the end of its window.  The
+                // window ends once an entry at least kExtraSteps past mu_1 is
+                // stored (or the list is full).
+                u32 k = 0;
+                u64 mh = 0, ms = 0;
+                bool first_half = false;
+                float P1 = 0.f, Q1 = 0.f;
+                for (;;) {
+                    float P2, Q2;
+                    baby_step(s, P, Q, Qp, P1, Q1, S);
+                    mh = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
+                    window_insert(lp, Q1, P1, S, j + k + 1, emain, cnt, j1, jlast);
+                    if (mh) {
+                        first_half = true;
+                        break;
                     }
-                    if (active && (cnt >= p.emax || j > p.max_steps)) {
+                    baby_step(s, P1, Q1, Q, P2, Q2, S);
+                    mh = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
+                    window_insert(lp, Q2, P2, S, j + k + 2, emain, cnt, j1, jlast);
+                    ms = __builtin_amdgcn_ballot_w64(j1 != 0 && jlast >= j1 + kExtraSteps) |
+                         __builtin_amdgcn_ballot_w64(cnt + 2 > p.emax);
+                    Qp = Q1;
+                    Q = Q2;
+                    P = P2;
+                    k += 2;
+                    if ((mh | ms) || k >= K) break;
+                }
+                if (first_half) {
+                    Qp = Q;
+                    Q = Q1;
+                    P = P1;
+                    k += 1;
+                }
+                j += k;
+                if ((mh >> lane) & 1ull) {
+                    // half-period symmetry: the unit is found without giant steps
+                    const u32 rj = 1u + (((u32)P >> 1) & 1u);
+                    const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
+                    emit_flag(p.eis_words, idx, v % 3u == 0u);
+                    active = false;
+                } else if ((ms >> lane) & 1ull) {
+                    // end of the window; its extension past mu_1 must be short
+                    // next to mu_1's own distance (see above)
+                    if (j1 != 0 && jlast - j1 <= j1 / 4 && cnt < p.emax) {
+                        WindowState st;
+                        st.emain = emain;
+                        st.count = cnt;
+                        st.item = item;
+                        st.pad = 0;
+                        p.state[pos] = st;
+                        to_giant = true;
+                    } else {
                         to_plain = true;
-                        active = false;
                     }
+                    active = false;
+                } else if (j > p.max_steps) {
+                    to_plain = true;
+                    active = false;
                 }
             }
         }
@@ -201,7 +239,7 @@ int walk_window_blocks_per_cu()
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
 {
-    __shared__ unsigned long long tab[4][kTableMax];
+    __shared__ u32 tab[4][kTableMax];
     const u32 nblk = gridDim.x, b = blockIdx.x;
     const u32 xcd = b % 8, q = nblk / 8, r = nblk % 8;
     const u32 lb = xcd * q + min(xcd, r) + b / 8;  // logical block
@@ -210,7 +248,7 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     const u32 n = *p.giant_len;
     const bool valid = w < n;
     const u32 mask = p.tsize - 1;
-    for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0ull;
+    for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
     __syncthreads();
     u32 pos = 0;
     if (valid) {
@@ -220,17 +258,19 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
         for (u32 e = lane; e < cnt; e += 64) {
             const unsigned long long ent = lst[(u64)e * 64];
             const u32 qb = (u32)(ent >> 32), pb = (u32)ent & ~3u;
-            u32 slot = dict_slot(qb, pb, mask);
+            const u32 h = dict_hash(qb, pb);
+            const u32 val = (e + 1) | (h & 0xffff0000u);
+            u32 slot = h & mask;
             for (u32 probe = 0; probe < p.tsize; probe++) {
-                const unsigned long long prev = atomicCAS(&tab[wv][slot], 0ull, ent);
-                if (prev == 0ull) break;
+                const u32 prev = atomicCAS(&tab[wv][slot], 0u, val);
+                if (prev == 0u) break;
                 slot = (slot + 1) & mask;
             }
         }
     }
     __syncthreads();
     if (valid) {
-        unsigned long long *tbl = p.tables + (u64)pos * p.tsize;
+        u32 *tbl = p.tables + (u64)pos * p.tsize;
         for (u32 t = lane; t < p.tsize; t += 64) tbl[t] = tab[wv][t];
     }
 }
@@ -256,7 +296,11 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     float sf = 0.f;
     double m1Q = 0.0, m1P = 0.0, cQ = 0.0, cP = 0.0;
     u32 m1S = 0, cS = 0;
-    const unsigned long long *tbl = nullptr;
+    const u32 *tbl = nullptr;
+    const unsigned long long *lst = nullptr;
+    float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state
+    u32 Sw = 0, w = 0;
+    bool walking = false;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool active = false, exhausted = false;
     u64 my_giants = 0, my_steps = 0;
@@ -273,6 +317,8 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 } else {
                     const u32 pos = p.giant_list[g];
                     const WindowState st = p.state[pos];
+                    lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
+                    const unsigned long long m1 = lst[(u64)(st.emain - 1) * 64];
                     item = st.item;
                     idx = item_bit(p.segs, item);
                     const u64 d = item_d(p.segs, item);
@@ -281,9 +327,9 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     sd = (double)s64;
                     sf = (float)s64;
                     L = (double)isqrt_u64(s64);
-                    m1Q = (double)__uint_as_float(st.q_bits);
-                    m1P = (double)__uint_as_float(st.p_bits & ~3u);
-                    m1S = st.p_bits & 3u;
+                    m1Q = (double)__uint_as_float((u32)(m1 >> 32));
+                    m1P = (double)__uint_as_float((u32)m1 & ~3u);
+                    m1S = (u32)m1 & 3u;
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;
@@ -296,56 +342,74 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
         if (!__any(active)) break;
 
         if (active) {
+            // Two phases per iteration: a lane that is not walking composes
+            // (and reduces) its next giant ideal; then every walking lane
+            // takes up to kWalkChunk reduction steps towards the next
+            // distinguished ideal.  A lane with a long walk continues it in
+            // the next iteration instead of holding up the other lanes.
             bool bad = false;
-            Form f3;
-            Gamma gm;
-            nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, bad);
-            const u32 lg = gamma_log(gm, bad);
-            double Qk, Pk, Qpk;
-            const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, bad);
-            const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
-            ng++;
+            if (!walking) {
+                Form f3;
+                Gamma gm;
+                nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, bad);
+                const u32 lg = gamma_log(gm, bad);
+                double Qk, Pk, Qpk;
+                const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, bad);
+                const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
+                ng++;
+                if (!bad) {
+                    cQ = Qk;
+                    cP = Pk;
+                    cS = Sk;
+                    Qw = (float)Qk;
+                    Pw = (float)Pk;
+                    Qpw = (float)Qpk;
+                    Sw = Sk;
+                    w = 0;
+                    walking = true;
+                }
+            }
             bool done = false, flag = false;
-            if (!bad) {
-                cQ = Qk;
-                cP = Pk;
-                cS = Sk;
-                // forward to the first distinguished ideal
-                float Qw = (float)Qk, Pw = (float)Pk, Qpw = (float)Qpk;
-                u32 Sw = Sk;
-                u32 w = 0;
-                while (!is_dp(Qw) && w < kWalkLimit) {
+            if (walking) {
+                u32 u = 0;
+                for (; u < kWalkChunk && !is_dp(Qw); u++) {
                     float Pn, Qn;
                     baby_step(sf, Pw, Qw, Qpw, Pn, Qn, Sw);
                     Qpw = Qw;
                     Qw = Qn;
                     Pw = Pn;
-                    w++;
                 }
-                my_steps += w;
-                if (!is_dp(Qw)) {
-                    bad = true;
-                } else if (!bad) {
+                w += u;
+                my_steps += u;
+                if (is_dp(Qw)) {
+                    walking = false;
                     const u32 qb = __float_as_uint(Qw), pb = __float_as_uint(Pw);
                     const unsigned long long key = ((unsigned long long)qb << 32) | pb;
-                    u32 slot = dict_slot(qb, pb, mask);
+                    const u32 h = dict_hash(qb, pb);
+                    u32 slot = h & mask;
                     for (u32 probe = 0; probe < p.tsize; probe++) {
-                        const unsigned long long e = tbl[slot];
-                        if (e == 0ull) break;
-                        if ((e & ~3ull) == key) {
-                            // a hit at k = 2 is skipped: mu_2 may lie inside
-                            // the window (a "unit" of distance 0); if it was a
-                            // true hit, the next one is at eps or eps^2, whose
-                            // residues are both 0 or both not
-                            if (ng > 1) {
-                                const u32 St = (u32)e & 3u;
-                                flag = ((Sw + 3u - St) % 3u) == 0u;
-                                done = true;
+                        const u32 v = tbl[slot];
+                        if (v == 0u) break;
+                        if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
+                            // fingerprint matches: compare the full key
+                            const unsigned long long e = lst[(u64)((v & 0xffffu) - 1) * 64];
+                            if ((e & ~3ull) == key) {
+                                // a hit at k = 2 is skipped: mu_2 may lie inside
+                                // the window (a "unit" of distance 0); if it was a
+                                // true hit, the next one is at eps or eps^2, whose
+                                // residues are both 0 or both not
+                                if (ng > 1) {
+                                    const u32 St = (u32)e & 3u;
+                                    flag = ((Sw + 3u - St) % 3u) == 0u;
+                                    done = true;
+                                }
+                                break;
                             }
-                            break;
                         }
                         slot = (slot + 1) & mask;
                     }
+                } else if (w >= kWalkLimit) {
+                    bad = true;
                 }
             }
             if (done) {
@@ -357,6 +421,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 p.fb_list[f] = item;
                 my_giants += ng;
                 active = false;
+                walking = false;
             }
         }
     }
@@ -365,7 +430,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
         my_giants += __shfl_down(my_giants, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
+        atomicAdd(&p.ctr->chunk_steps, (unsigned long long)my_steps);
         atomicAdd(&p.ctr->giant_steps, (unsigned long long)my_giants);
     }
 }

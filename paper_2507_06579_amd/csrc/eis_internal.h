@@ -42,7 +42,8 @@ struct SegInfo {
     u32 roff_off;    // the segment's prime offsets start here
     u32 method;      // 0 = plain walk, 1 = giant steps
     u32 count_slot;  // counts go to counts[2 slot] (D) and counts[2 slot + 1] (E)
-    u32 pad;
+    float wscale;    // giant steps: mu_1 is the distinguished ideal number
+                     // round(wscale * d^(1/4) / 16)
 };
 
 // Per-pass device counters (one cache line each to avoid false sharing).
@@ -53,10 +54,11 @@ struct PassCounters {
     u32 pad1[15];
     u32 err_count;     // walks that exceeded the step budget
     u32 pad2[15];
-    unsigned long long baby_steps;
+    unsigned long long baby_steps;   // rho steps of the window or plain walk
     unsigned long long refills;
     unsigned long long giant_steps;
-    u64 pad3[5];
+    unsigned long long chunk_steps;  // rho steps inside the giant-step walk
+    u64 pad3[4];
 };
 
 __device__ __forceinline__ u64 item_d(const SegInfo *segs, u32 item)
@@ -81,10 +83,10 @@ struct WalkParams {
 // ---- infrastructure method ------------------------------------------------
 // Per-d record written by the window walk for the giant-step walk.
 struct WindowState {
-    u32 q_bits;   // fp32 bit pattern of Q of mu_1 (the giant step)
-    u32 p_bits;   // fp32 bit pattern of P of mu_1, OR its residue (2 bits)
+    u32 emain;    // mu_1 (the giant step) is list entry emain - 1
     u32 count;    // dictionary entries written
     u32 item;     // the d's work item
+    u32 pad;
 };
 
 struct InfraParams {
@@ -102,11 +104,9 @@ struct InfraParams {
     WindowState *state;         // per batch position
     unsigned long long *lists;  // window lists, tile-interleaved: entry e of batch
                                 // position k at ((k / 64) * emax + e) * 64 + k % 64
-    unsigned long long *tables; // hash tables, tsize slots per batch position
+    u32 *tables;                // hash tables, tsize slots per batch position
     u32 emax;                   // list capacity per d
     u32 tsize;                  // table slots per d (power of two)
-    float window_scale;         // mu_1 is the distinguished ideal number
-                                // round(window_scale * d^(1/4) / 16)
     u32 max_steps;              // per-d budget of reduction steps (window)
     u32 max_giants;             // per-d budget of giant steps
     u32 *eis_words;             // output bitmaps of the pass

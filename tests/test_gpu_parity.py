@@ -191,6 +191,41 @@ def test_step_budget_overrun_is_an_error_not_a_wrong_bit():
                                        oracle.classify_range(5, 200)["n_eis"])
 
 
+def test_async_overrun_reported_by_last_error_after_other_calls():
+    # an asynchronous call whose walks overrun the (host-forced) budget, then
+    # a synchronous call that fits: the overrun still reaches eis_last_error
+    import torch
+    with eis.Context(method=eis.Method.BABY, max_steps_per_d=64) as c:
+        _say("async overrun then sync call")
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        c.eis_classify_async(10**9, 10**9 + 100_000, 0, 0, cnt.data_ptr(), 0)
+        assert c.eis_count(5, 200) == (oracle.mobius_count(5, 200),
+                                       oracle.classify_range(5, 200)["n_eis"])
+        assert c.eis_last_error() == eis.Status.EINTERNAL
+        assert c.eis_last_error() == 0
+
+
+def test_async_on_a_torch_stream_then_sync_call(ctx):
+    import torch
+    a, b = 10**9, 10**9 + 400_000
+    n = eis.eis_num_candidates(a, b)
+    nb = (n + 7) // 8
+    _say("async on a side stream, then a synchronous call")
+    s = torch.cuda.Stream()
+    eb = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    s.wait_stream(torch.cuda.current_stream())  # the zero fills come first
+    ctx.eis_classify_async(a, b, 0, eb.data_ptr(), cnt.data_ptr(), s.cuda_stream)
+    # the next call reuses the pass buffers: it must wait for the side stream
+    ref = oracle.classify_range(10**6, 10**6 + 50_000, want_bits=False)
+    assert ctx.eis_count(10**6, 10**6 + 50_000) == (ref["n_sqfree"], ref["n_eis"])
+    s.synchronize()
+    assert ctx.eis_last_error() == 0
+    hsq, heb, ns, ne = ctx.eis_classify(a, b)
+    assert np.array_equal(eb.cpu().numpy(), heb)
+    assert cnt.cpu().tolist() == [ns, ne]
+
+
 def test_methods_agree_on_mid_config():
     # the plain walk and the giant-step method on the same GPU, whole range
     a, b = workloads.MID

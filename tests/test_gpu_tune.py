@@ -1,0 +1,89 @@
+"""GPU tests of the autotuner (method and window-scale choice per height).
+
+The tuner changes only timing: every choice must give the same bits, which
+the plain walk (itself pinned to the oracle by the parity tests) fixes.
+"""
+import json
+import sys
+
+import pytest
+
+import paper_2507_06579_amd as eis
+
+pytestmark = pytest.mark.gpu
+
+SCALES = {1.0, 1.5, 2.5, 3.5, 5.0, 7.0}
+
+
+def _say(msg):
+    print(f"[gpu-tune] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def test_tune_choices_cache_and_bits(tmp_path):
+    path = str(tmp_path / "tune.json")
+    heights = [10**5, 3 * 10**6, 10**8, 4 * 10**9, 10**11, 10**12 - 10**6]
+    with eis.Context(tune_cache_path=path) as c:
+        _say("tuning")
+        c.eis_tune()
+        choices = [c.eis_tuned_choice(d) for d in heights]
+        for m, w in choices:
+            assert m in (eis.Method.BABY, eis.Method.INFRA)
+            assert w in SCALES
+        assert choices[0][0] == eis.Method.BABY  # below 10^6
+        # the bits do not depend on the choice
+        ranges = [(10**8, 10**8 + 10**6), (10**11 - 4 * 10**6, 10**11), (10**12 - 10**6, 10**12)]
+        tuned = [c.eis_classify(a, b) for a, b in ranges]
+    with open(path) as f:
+        doc = json.load(f)
+    assert doc["arch"] == "gfx950" and len(doc["decades"]) == 13
+    with eis.Context(method=eis.Method.BABY) as c:
+        plain = [c.eis_classify(a, b) for a, b in ranges]
+    for (sq1, e1, n1, m1), (sq2, e2, n2, m2) in zip(tuned, plain):
+        assert (n1, m1) == (n2, m2)
+        assert bytes(sq1) == bytes(sq2) and bytes(e1) == bytes(e2)
+    # a new context loads the cache
+    with eis.Context(tune_cache_path=path) as c:
+        assert [c.eis_tuned_choice(d) for d in heights] == choices
+    # an explicit method and scale win over the tuned choice
+    with eis.Context(tune_cache_path=path, method=eis.Method.INFRA, window_scale=2.0) as c:
+        assert c.eis_tuned_choice(10**11) == (eis.Method.INFRA, 2.0)
+
+
+def test_untuned_defaults():
+    with eis.Context() as c:
+        assert c.eis_tuned_choice(10**6)[0] == eis.Method.BABY
+        assert c.eis_tuned_choice(10**11)[0] == eis.Method.INFRA
+        assert c.eis_tuned_choice(10**11)[1] == 3.5
+
+
+def test_tune_cache_rejects_partial_file(tmp_path):
+    path = tmp_path / "bad.json"
+    path.write_text('{"arch": "gfx950", "decades": [{"k": 6, "method": 1, "window_scale": 2.5}]}')
+    with eis.Context(tune_cache_path=str(path)) as c:
+        # not every decade present: defaults stay in force
+        assert c.eis_tuned_choice(10**6) == (eis.Method.BABY, 3.5)
+
+
+def test_kernel_times_and_step_counts():
+    a, b = 10**11 - 4 * 10**6, 10**11
+    for method in (eis.Method.BABY, eis.Method.INFRA):
+        with eis.Context(method=method, flags=eis.EIS_FLAG_KERNEL_TIMES) as c:
+            c.eis_count(a, b)
+            st = c.eis_get_stats()
+        ks, kl, kms = st["kernel_steps"], st["kernel_launches"], st["kernel_ms"]
+        assert sum(ks) == st["baby_steps"] > 0
+        k = eis.KERNELS
+        assert kl[k.index("sieve")] == 1 and kl[k.index("popcount")] == 1
+        if method == eis.Method.BABY:
+            assert kl[k.index("walk_plain")] == 1 and kl[k.index("walk_window")] == 0
+            assert ks[k.index("walk_plain")] == st["baby_steps"]
+        else:
+            assert kl[k.index("walk_window")] >= 1 and kl[k.index("walk_giant")] >= 1
+            assert ks[k.index("walk_window")] > 0 and st["giant_steps"] > 0
+        assert all(x >= 0 for x in kms)
+        assert 0 < sum(kms) <= st["last_total_ms"] * 1.05 + 0.5
+    # without the flag nothing is timed
+    with eis.Context() as c:
+        c.eis_count(10**9, 10**9 + 10**5)
+        assert sum(c.eis_get_stats()["kernel_launches"]) == 0
