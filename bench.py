@@ -30,11 +30,45 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # VALU instructions per rho step of the walk kernels, counted in the gfx950
 # code of the built loops (two steps per iteration, averaged).  The
 # reciprocal estimate issues on the transcendental unit beside them and is
-# not counted.  Plain walk: quotient with one correction (7), P and Q updates
-# (3), Z/3 residue (3), two exit tests (2), plus a register move every other
-# step.  Window walk: the same step plus the distinguished-ideal test (3),
-# the step index, and the end-of-window tests once per two steps.
-VALU_PER_STEP = {"walk_plain": 15.5, "walk_handoff": 15.5, "walk_window": 24.0}
+# not counted.  Plain walk: the biased quotient (fma, mul, floor), the
+# overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma), two
+# exit tests, and a register copy every other step.  Window walk: the same
+# step, the distinguished-ideal test (mul, fract, cmp), the list append
+# (addresses, count, residue sum, mu_1 bookkeeping: 10), which runs for the
+# wave whenever any of its 64 lanes appends, i.e. at nearly every step, and
+# the window-end tests once per two steps.
+VALU_PER_STEP = {"walk_plain": 11.5, "walk_handoff": 11.5, "walk_window": 26.0}
+
+
+# Device code whose HBM byte counts profiles/traffic.json records; the
+# record is used only while these files are unchanged.
+DEVICE_SOURCES = ["eis_kernels.hip", "eis_infra.hip", "eis_walk.h", "eis_giant.h",
+                  "eis_internal.h"]
+
+
+def device_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_06579_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the counter runs
+    recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, each scaled
+    by the same counter's reading for a copy of known size), or None when
+    there is no record or the device code has changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    ent = doc.get(kernel, {}).get(workload)
+    if not ent or ent.get("device_sources_sha256") != device_sources_sha256():
+        return None
+    return int(ent["hbm_bytes_per_launch"])
 
 
 def log(msg):
@@ -76,6 +110,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="auto", choices=["auto", "baby", "infra"])
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one elementwise copy of this many MiB before the workload "
+                         "(the reference kernel for scaling HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="auto method without running the autotuner first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -112,6 +149,13 @@ def main():
     def step():
         ctx.eis_classify_async(a, b, sq.data_ptr(), eb.data_ptr(), counts.data_ptr(), 0)
 
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written")
+        del src, dst
     log(f"workload [{a}, {b}) candidates={n} method={args.method}")
     for i in range(args.warmup):
         step()
@@ -159,12 +203,14 @@ def main():
     achieved = VALU_PER_STEP[dom] * units_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-instr/s",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_LANE_OPS, 4),
+                "traffic": None,
                 "kernel": "k_walk_baby" if dom != "walk_window" else "k_walk_window",
                 "ops_per_unit": VALU_PER_STEP[dom], "unit_of_work": "rho step",
                 "units_per_launch": int(units_per_launch),
                 "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                 "share_of_step_time": round(kms[kd] / (1e3 * elapsed), 3)}
+    roofline["traffic"] = measured_traffic(roofline["kernel"], f"large:{chosen.name.lower()}")
     out = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -159,7 +159,9 @@ struct eis_ctx {
     // giant-step scratch
     WindowState *d_state = nullptr;
     unsigned long long *d_lists = nullptr;
+    u32 *d_lres = nullptr;
     u32 *d_tables = nullptr;
+    u64 infra_bytes = 0;
     u32 *d_glist = nullptr;
     u64 infra_batch_cap = 0;
     u32 infra_emax_cap = 0;
@@ -276,11 +278,15 @@ static void free_infra(eis_ctx *c)
 {
     (void)hipFree(c->d_state);
     (void)hipFree(c->d_lists);
+    (void)hipFree(c->d_lres);
     (void)hipFree(c->d_tables);
     (void)hipFree(c->d_glist);
     c->d_state = nullptr;
     c->d_lists = nullptr;
+    c->d_lres = nullptr;
     c->d_tables = nullptr;
+    c->bytes_held -= c->infra_bytes;
+    c->infra_bytes = 0;
     c->d_glist = nullptr;
     c->infra_batch_cap = 0;
     c->infra_emax_cap = c->infra_tsize_cap = 0;
@@ -366,6 +372,11 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     int rc = EIS_OK;
     do {
         if (hipSetDevice(c->device) != hipSuccess) { rc = EIS_EDEVICE; break; }
+        if (c->cfg.mem_budget_bytes == 0) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { rc = EIS_EDEVICE; break; }
+            c->cfg.mem_budget_bytes = free_b / 4;
+        }
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
             rc = EIS_EDEVICE;
             break;
@@ -416,7 +427,7 @@ static int ensure_pass_buffers(eis_ctx *c)
     if (c->pass_ready) return EIS_OK;
     const u64 need = kMaxSegments * sizeof(SegInfo) + 2ull * kPassWords * 4 +
                      3ull * kPassCandidates * 4 + 3 * sizeof(PassCounters) + 3 * 64;
-    if (c->cfg.mem_budget_bytes && need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
+    if (c->bytes_held + need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_segs), kMaxSegments * sizeof(SegInfo),
                       hipHostMallocDefault) != hipSuccess ||
@@ -480,15 +491,18 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)emax * 8 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(u32));
-    if (c->cfg.mem_budget_bytes && c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
+    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(u32));
+    if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
+        hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
         hipMalloc(&c->d_tables, cap * tsize * 4) != hipSuccess ||
         hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
         hipMalloc(&c->d_glist, cap * sizeof(u32)) != hipSuccess) {
         free_infra(c);
         return EIS_ENOMEM;
     }
+    c->infra_bytes = bytes;
+    c->bytes_held += bytes;
     c->infra_batch_cap = cap;
     c->infra_emax_cap = emax;
     c->infra_tsize_cap = tsize;
@@ -605,6 +619,18 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
 
 static int collect_pass(eis_ctx *c);
 
+// Wait for the pass an asynchronous call left running (it may be on another
+// stream) before anything of a new call touches the shared buffers; its
+// status goes to eis_last_error.
+static int settle_pending(eis_ctx *c)
+{
+    if (!c->uncollected) return EIS_OK;
+    HIP_TRY(hipStreamSynchronize(c->pending_stream));
+    int prc = collect_pass(c);
+    if (prc != EIS_OK && c->async_status == EIS_OK) c->async_status = prc;
+    return EIS_OK;
+}
+
 // Per-kernel timing: an event pair around one launch, read by collect_pass.
 static int kt_begin(eis_ctx *c, hipStream_t st, int kind)
 {
@@ -679,6 +705,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.fb_ctr = ctr_fb;
         ip.state = c->d_state;
         ip.lists = c->d_lists;
+        ip.lres = c->d_lres;
         ip.tables = c->d_tables;
         ip.emax = pl.emax;
         ip.tsize = pl.tsize;
@@ -717,15 +744,10 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
                     PassPlan &pl)
 {
     (void)hipGetLastError();  // launch checks below must not see an older error
-    if (c->uncollected) {
-        // the tail pass of an asynchronous call: its buffers are about to be
-        // reused, and its status belongs to eis_last_error
-        HIP_TRY(hipStreamSynchronize(c->pending_stream));
-        int prc = collect_pass(c);
-        if (prc != EIS_OK && c->async_status == EIS_OK) c->async_status = prc;
-    }
+    int rc = settle_pending(c);
+    if (rc != EIS_OK) return rc;
     c->kev_used = 0;
-    int rc = ensure_pass_buffers(c);
+    rc = ensure_pass_buffers(c);
     if (rc != EIS_OK) return rc;
     plan_pass(c, segs, pl);
     rc = ensure_roff(c, std::max<u64>(pl.roff_total, 1));
@@ -819,7 +841,8 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
                      unsigned long long *d_counts_out, hipStream_t st, bool sync)
 {
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    int rc = ensure_counts(c, 1);
+    int rc = settle_pending(c);
+    if (rc == EIS_OK) rc = ensure_counts(c, 1);
     if (rc != EIS_OK) return rc;
     const u64 n = eis_num_candidates(a, b);
     const u64 d0 = eis_first_candidate(a);
@@ -1019,7 +1042,8 @@ extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b,
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     pack_passes(c, ranges, passes);
-    int rc = ensure_counts(c, std::max<u64>(n, 1));
+    int rc = settle_pending(c);
+    if (rc == EIS_OK) rc = ensure_counts(c, std::max<u64>(n, 1));
     if (rc != EIS_OK) return rc;
     hipStream_t st = c->stream;
     HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * std::max<u64>(n, 1), st));
@@ -1106,7 +1130,8 @@ static void server_loop(eis_ctx *c)
         int rc = EIS_OK;
         {
             std::lock_guard<std::mutex> g(c->gpu_mu);
-            rc = ensure_counts(c, segs.size());
+            rc = settle_pending(c);
+            if (rc == EIS_OK) rc = ensure_counts(c, segs.size());
             if (rc == EIS_OK) {
                 hipStream_t st = c->stream;
                 if (launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * segs.size(), st) != hipSuccess)
@@ -1243,7 +1268,8 @@ static int time_pass(eis_ctx *c, u64 d0, u32 n, u32 method, double ws, float &ms
     segs[0].wscale = (float)ws;
     segs[0].dst_bit = 0;
     hipStream_t st = c->stream;
-    int rc = ensure_counts(c, 1);
+    int rc = settle_pending(c);
+    if (rc == EIS_OK) rc = ensure_counts(c, 1);
     if (rc == EIS_OK && launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4, st) != hipSuccess)
         rc = EIS_EDEVICE;
     PassPlan pl;

@@ -7,7 +7,8 @@
 //   k_walk_window  one d per lane: reduction steps from (1), with the
 //                  half-period symmetry exit; the "distinguished" ideals of
 //                  the walk (Q = 2 mod 64, about one in 16) are appended to
-//                  the d's dictionary list.  mu_1 is the n-th distinguished
+//                  the d's dictionary list (the ideal's (Q/4, P/4) as fp32
+//                  bits, and twice its residue sum beside it).  mu_1 is the n-th distinguished
 //                  ideal (n = wscale * d^(1/4) / 16, at least 16); the
 //                  window ends at the first distinguished ideal at least six
 //                  steps after mu_1 (the two extra ideals of the algorithm,
@@ -47,10 +48,11 @@
 
 namespace eis {
 
-// Q = 2 (mod 64): fract(Q / 64) = 1/32 exactly for integer-valued Q < 2^24.
-constexpr float kDpScale = 1.0f / 64.0f;
+// Q = 2 (mod 64), tested on the quarter-unit value Q/4: fract(Q/64) = 1/32
+// exactly for integer-valued Q < 2^24.
+constexpr float kDpScale = 1.0f / 16.0f;
 constexpr float kDpHit = 2.0f / 64.0f;
-__device__ __forceinline__ bool is_dp(float Q) { return __builtin_amdgcn_fractf(Q * kDpScale) == kDpHit; }
+__device__ __forceinline__ bool is_dp(float Q4) { return __builtin_amdgcn_fractf(Q4 * kDpScale) == kDpHit; }
 
 constexpr u32 kTableMax = 1024;     // largest table (slots) per d
 constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
@@ -58,9 +60,10 @@ constexpr u32 kWalkChunk = 24;      // of which one iteration of the giant walk 
 constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
 constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
 
-__device__ __forceinline__ unsigned long long entry_of(float Q, float P, u32 S)
+// dictionary key of a reduced ideal: its quarter-unit (Q, P) as fp32 bits
+__device__ __forceinline__ unsigned long long entry_of(float Q4, float P4)
 {
-    return ((unsigned long long)__float_as_uint(Q) << 32) | (unsigned long long)(__float_as_uint(P) | (S % 3u));
+    return ((unsigned long long)__float_as_uint(Q4) << 32) | (unsigned long long)__float_as_uint(P4);
 }
 
 // ---------------------------------------------------------------------------
@@ -69,19 +72,23 @@ __device__ __forceinline__ unsigned long long entry_of(float Q, float P, u32 S)
 // 64 lanes append to one tile of the list array (tile-interleaved layout:
 // the writes of a wave stay within one small region of memory).
 // ---------------------------------------------------------------------------
-// Window bookkeeping of one reduction step that landed on (Q, P) with
-// residue sum S at step jc: append a distinguished ideal to the list (lp
-// points at its next slot), note the step of mu_1 (the emain-th entry) and of
-// the last entry.
-__device__ __forceinline__ void window_insert(unsigned long long *&lp, float Q, float P, u32 S,
-                                              u32 jc, u32 emain, u32 &cnt, u32 &j1, u32 &jlast)
+// Window bookkeeping of one reduction step that landed on (Q, P) (quarter
+// units): append a distinguished ideal to the list -- entry cnt of this lane
+// of the tile at lt[64 cnt + lane], twice its residue sum at rt[...] -- and
+// note the step jc = jb + k of the last entry and, for mu_1 (the emain-th
+// entry), the step from which an entry ends the window (jc + kExtraSteps).
+// S2k + acc is twice the residue sum up to this step.
+__device__ __forceinline__ void window_insert(unsigned long long *lt, u32 *rt, u32 lane, float Q,
+                                              float P, u32 S2k, float acc, u32 jb, u32 k,
+                                              u32 emain, u32 &cnt, u32 &j1e, u32 &jlast)
 {
     if (is_dp(Q)) {
-        *lp = entry_of(Q, P, S);
-        lp += 64;
+        const u32 o = cnt * 64u + lane;
+        lt[o] = entry_of(Q, P);
+        rt[o] = S2k + (u32)acc;
         cnt++;
-        j1 = (cnt == emain) ? jc : j1;
-        jlast = jc;
+        jlast = jb + k;
+        j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
     }
 }
 
@@ -92,17 +99,23 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
     const u32 nb = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 ntiles = (nb + 63) / 64;
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
+    const u32 cnt_end = p.emax - 1;  // a full list ends the window (then the d goes plain)
     u64 my_steps = 0, my_refills = 0;
 
     for (;;) {
         u32 t = 0;
         if (lane == 0) t = atomicAdd(p.win_next, 1u);
-        t = __shfl(t, 0, 64);
+        t = __builtin_amdgcn_readfirstlane(t);
         if (t >= ntiles) break;
         const u32 pos = t * 64 + lane;
-        unsigned long long *lp = p.lists + (u64)t * p.emax * 64 + lane;  // entry e at base[64 e]
-        float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
-        u32 S = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1 = 0, jlast = 0;
+        // the tile's list and residue entries (wave-uniform bases)
+        unsigned long long *lt = p.lists + (u64)t * p.emax * 64;
+        u32 *rt = p.lres + (u64)t * p.emax * 64;
+        // walk state in quarter units (see rho_step_q); S2 = twice the
+        // residue sum at the start of the current chunk of steps; an entry
+        // at step >= j1e ends the window (j1e = step of mu_1 + kExtraSteps)
+        float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
+        u32 S2 = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
         bool active = false, to_giant = false, to_plain = false;
         u32 item = 0;
         if (pos < nb) {
@@ -118,17 +131,18 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
             if (Q1 == 2) {
                 emit_flag(p.eis_words, idx, S1 % 3u == 0u);
             } else {
-                s = (float)si;
-                P = (float)P1;
-                Q = (float)Q1;
-                S = S1;
+                sq = (float)si * 0.25f;
+                sqc = sq * kQuotBias;
+                P = (float)P1 * 0.25f;
+                Q = (float)Q1 * 0.25f;
+                S2 = 2u * S1;
                 // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
-                *lp = entry_of(2.f, P, 0u);
-                lp += 64;
+                lt[lane] = entry_of(0.5f, P);
+                rt[lane] = 0u;
                 cnt = 1;
                 const float n = p.segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
                 emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
-                window_insert(lp, Q, P, S, 1, emain, cnt, j1, jlast);
+                window_insert(lt, rt, lane, Q, P, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
                 active = true;
             }
         }
@@ -141,21 +155,28 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                 u32 k = 0;
                 u64 mh = 0, ms = 0;
                 bool first_half = false;
-                float P1 = 0.f, Q1 = 0.f;
+                float P1 = 0.f, Q1 = 0.f, acc = 0.f;
                 for (;;) {
                     float P2, Q2;
-                    baby_step(s, P, Q, Qp, P1, Q1, S);
+                    rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
                     mh = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-                    window_insert(lp, Q1, P1, S, j + k + 1, emain, cnt, j1, jlast);
+                    window_insert(lt, rt, lane, Q1, P1, S2 + k + 1, acc, j + 1, k, emain, cnt, j1e,
+                                  jlast);
                     if (mh) {
+                        // the window-end test runs on every exit from the
+                        // loop, so that no lane starts a pair with fewer than
+                        // two free list entries
+                        ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
+                             __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
                         first_half = true;
                         break;
                     }
-                    baby_step(s, P1, Q1, Q, P2, Q2, S);
+                    rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
                     mh = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
-                    window_insert(lp, Q2, P2, S, j + k + 2, emain, cnt, j1, jlast);
-                    ms = __builtin_amdgcn_ballot_w64(j1 != 0 && jlast >= j1 + kExtraSteps) |
-                         __builtin_amdgcn_ballot_w64(cnt + 2 > p.emax);
+                    window_insert(lt, rt, lane, Q2, P2, S2 + k + 2, acc, j + 2, k, emain, cnt, j1e,
+                                  jlast);
+                    ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
+                         __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
                     Qp = Q1;
                     Q = Q2;
                     P = P2;
@@ -169,16 +190,19 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                     k += 1;
                 }
                 j += k;
+                S2 += k + (u32)acc;
                 if ((mh >> lane) & 1ull) {
                     // half-period symmetry: the unit is found without giant steps
-                    const u32 rj = 1u + (((u32)P >> 1) & 1u);
+                    const u32 S = S2 >> 1;
+                    const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
                     const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
                     emit_flag(p.eis_words, idx, v % 3u == 0u);
                     active = false;
                 } else if ((ms >> lane) & 1ull) {
                     // end of the window; its extension past mu_1 must be short
                     // next to mu_1's own distance (see above)
-                    if (j1 != 0 && jlast - j1 <= j1 / 4 && cnt < p.emax) {
+                    const u32 j1 = j1e - kExtraSteps;
+                    if (j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2 < (1u << 24)) {
                         WindowState st;
                         st.emain = emain;
                         st.count = cnt;
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
         const u32 cnt = p.state[pos].count;
         for (u32 e = lane; e < cnt; e += 64) {
             const unsigned long long ent = lst[(u64)e * 64];
-            const u32 qb = (u32)(ent >> 32), pb = (u32)ent & ~3u;
+            const u32 qb = (u32)(ent >> 32), pb = (u32)ent;
             const u32 h = dict_hash(qb, pb);
             const u32 val = (e + 1) | (h & 0xffff0000u);
             u32 slot = h & mask;
@@ -293,12 +317,13 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     // per-lane state
     u32 idx = 0, item = 0, ng = 0;
     double dd = 0.0, sd = 0.0, L = 0.0;
-    float sf = 0.f;
     double m1Q = 0.0, m1P = 0.0, cQ = 0.0, cP = 0.0;
     u32 m1S = 0, cS = 0;
     const u32 *tbl = nullptr;
     const unsigned long long *lst = nullptr;
-    float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state
+    const u32 *lrs = nullptr;
+    float sq = 0.f, sqc = 0.f;
+    float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state, quarter units
     u32 Sw = 0, w = 0;
     bool walking = false;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
@@ -318,6 +343,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     const u32 pos = p.giant_list[g];
                     const WindowState st = p.state[pos];
                     lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
+                    lrs = p.lres + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
                     const unsigned long long m1 = lst[(u64)(st.emain - 1) * 64];
                     item = st.item;
                     idx = item_bit(p.segs, item);
@@ -325,11 +351,12 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     const u64 s64 = isqrt_u64(d);
                     dd = (double)d;
                     sd = (double)s64;
-                    sf = (float)s64;
+                    sq = (float)s64 * 0.25f;
+                    sqc = sq * kQuotBias;
                     L = (double)isqrt_u64(s64);
-                    m1Q = (double)__uint_as_float((u32)(m1 >> 32));
-                    m1P = (double)__uint_as_float((u32)m1 & ~3u);
-                    m1S = (u32)m1 & 3u;
+                    m1Q = 4.0 * (double)__uint_as_float((u32)(m1 >> 32));
+                    m1P = 4.0 * (double)__uint_as_float((u32)m1);
+                    m1S = (lrs[(u64)(st.emain - 1) * 64] >> 1) % 3u;
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;
@@ -361,9 +388,9 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     cQ = Qk;
                     cP = Pk;
                     cS = Sk;
-                    Qw = (float)Qk;
-                    Pw = (float)Pk;
-                    Qpw = (float)Qpk;
+                    Qw = (float)Qk * 0.25f;
+                    Pw = (float)Pk * 0.25f;
+                    Qpw = (float)Qpk * 0.25f;
                     Sw = Sk;
                     w = 0;
                     walking = true;
@@ -372,13 +399,15 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             bool done = false, flag = false;
             if (walking) {
                 u32 u = 0;
+                float acc = 0.f;
                 for (; u < kWalkChunk && !is_dp(Qw); u++) {
                     float Pn, Qn;
-                    baby_step(sf, Pw, Qw, Qpw, Pn, Qn, Sw);
+                    rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc);
                     Qpw = Qw;
                     Qw = Qn;
                     Pw = Pn;
                 }
+                Sw += (u + (u32)acc) >> 1;
                 w += u;
                 my_steps += u;
                 if (is_dp(Qw)) {
@@ -392,14 +421,14 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                         if (v == 0u) break;
                         if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
                             // fingerprint matches: compare the full key
-                            const unsigned long long e = lst[(u64)((v & 0xffffu) - 1) * 64];
-                            if ((e & ~3ull) == key) {
+                            const u32 e = (v & 0xffffu) - 1;
+                            if (lst[(u64)e * 64] == key) {
                                 // a hit at k = 2 is skipped: mu_2 may lie inside
                                 // the window (a "unit" of distance 0); if it was a
                                 // true hit, the next one is at eps or eps^2, whose
                                 // residues are both 0 or both not
                                 if (ng > 1) {
-                                    const u32 St = (u32)e & 3u;
+                                    const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
                                     flag = ((Sw + 3u - St) % 3u) == 0u;
                                     done = true;
                                 }

@@ -103,7 +103,9 @@ struct InfraParams {
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position
     unsigned long long *lists;  // window lists, tile-interleaved: entry e of batch
-                                // position k at ((k / 64) * emax + e) * 64 + k % 64
+                                // position k at ((k / 64) * emax + e) * 64 + k % 64;
+                                // an entry is the ideal's (Q/4, P/4) as fp32 bits
+    u32 *lres;                  // 2 S (twice the residue sum) of each entry, same layout
     u32 *tables;                // hash tables, tsize slots per batch position
     u32 emax;                   // list capacity per d
     u32 tsize;                  // table slots per d (power of two)

@@ -235,7 +235,8 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
     // inner-loop length between budget checks; a walk that has not ended
     // after max_steps (rounded up to a multiple of K) is abandoned and counted
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
-    float s = 0.f, P = 1.f, Q = 2.f, Qp = 2.f;
+    // walk state in quarter units (see rho_step_q)
+    float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
     u32 S = 0, j = 0, idx = 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool active = false, exhausted = false;
@@ -266,10 +267,11 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
                         // Q_1 = Q_0: log eps = S_1 + S_0 = S_1
                         emit_flag(p.eis_words, idx, S1 % 3u == 0u);
                     } else {
-                        s = (float)si;
-                        P = (float)P1;
-                        Q = (float)Q1;
-                        Qp = 2.f;
+                        sq = (float)si * 0.25f;
+                        sqc = sq * kQuotBias;
+                        P = (float)P1 * 0.25f;
+                        Q = (float)Q1 * 0.25f;
+                        Qp = 0.5f;
                         S = S1;
                         j = 1;
                         active = true;
@@ -286,16 +288,16 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
             u32 k = 0;
             u64 em = 0;
             bool first_half = false;
-            float P1 = 0.f, Q1 = 0.f;
+            float P1 = 0.f, Q1 = 0.f, acc = 0.f;
             for (;;) {
                 float P2, Q2;
-                baby_step(s, P, Q, Qp, P1, Q1, S);
+                rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
                 em = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
                 if (em) {
                     first_half = true;
                     break;
                 }
-                baby_step(s, P1, Q1, Q, P2, Q2, S);
+                rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
                 em = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
                 Qp = Q1;
                 Q = Q2;
@@ -310,9 +312,11 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
                 k += 1;
             }
             j += k;
+            // sum of the residues of these k steps
+            S += (k + (u32)acc) >> 1;
             const bool ex = (em >> __lane_id()) & 1ull;
             if (ex) {
-                const u32 rj = 1u + (((u32)P >> 1) & 1u);
+                const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
                 // Q-rule first (it also covers the tie at the period's end)
                 const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
                 emit_flag(p.eis_words, idx, v % 3u == 0u);

@@ -19,21 +19,45 @@ __device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
     if (eis) atomicOr(&eis_words[idx >> 5], 1u << (idx & 31));
 }
 
-// One reduction step from (P, Q) with predecessor Qp to (Pn, Qn); S gains the
-// residue of the relative generator (Pn + sqrt d)/Q.
-__device__ __forceinline__ void baby_step(float s, float P, float Q, float Qp, float &Pn,
-                                          float &Qn, u32 &S)
+// One reduction step rho (Appendix A) from (P, Q) with predecessor Qp:
+//   q = floor((P + sqrt d)/Q) = floor((P + s)/Q),  P' = qQ - P,
+//   Q' = (d - P'^2)/Q = Qp + q (P - P')   (division-free form),
+// and the residue r(P') of the relative generator (P' + sqrt d)/Q in Z/3.
+// For d < 10^12 every quantity is an integer below 2^21, so fp32 adds and
+// fmas are exact.  The state is kept in quarter units (P/4, Q/4, Qp/4, s/4:
+// exact power-of-two scalings), and the quotient is
+//   q = floor(fl(fl(P c + s c) rcp(Q)))  with c = 1 + 2^-21.
+// The relative errors of the roundings (the product s c, the fma, the
+// reciprocal's 1 ulp, the product) add up to less than 2^-21, so the bias c
+// keeps the estimate at or above t/Q = (P + s)/Q, and q is never below the
+// true floor k (k is representable, so rounding a value >= k cannot fall
+// below it).  q exceeds k by at most one, and only when t/Q is within about
+// 2^-20 (t/Q) of k + 1; then P' = qQ - P = (s - r) + Q > s, where r < Q is
+// the true remainder, while the true P' = s - r is at most s.  So P' > s
+// detects the overshoot exactly, and q - 1, P' - Q undo it.  For d < 10^12
+// that happens about once per 10^6 steps, and only above 10^11.
+// The residue: P' is odd, so fract(P'/4) is 1/4 when P' = 1 (mod 4) and 3/4
+// when P' = 3 (mod 4); acc sums 4 fract(P'/4), i.e. 1 or 3 per step (an exact
+// integer while acc < 2^24), and the caller folds it into S: over k steps,
+// the residues r = 1 + bit1(P') add up to (k + acc) / 2.
+constexpr float kQuotBias = 1.f + 0x1p-21f;
+
+__device__ __forceinline__ void rho_step_q(float sq, float sqc, float P, float Q, float Qp,
+                                           float &Pn, float &Qn, float &acc)
 {
-    const float t = P + s;
     const float rq = __builtin_amdgcn_rcpf(Q);
-    // floor(t/Q) - 1 <= q0 <= floor(t/Q): the estimate t*rq is within 0.16
-    // of t/Q for t/Q < 2^20, and the bias -0.5 keeps it on the low side
-    const float q0 = floorf(fmaf(t, rq, -0.5f));
-    const float r = fmaf(-q0, Q, t);
-    const float q = (r >= Q) ? q0 + 1.f : q0;
+    float q = floorf(fmaf(P, kQuotBias, sqc) * rq);
     Pn = fmaf(q, Q, -P);
+    if (__builtin_amdgcn_ballot_w64(Pn > sq)) {
+        // rare: keep it a branch (an empty volatile asm is not speculated)
+        __asm__ volatile("");
+        if (Pn > sq) {
+            q -= 1.f;
+            Pn -= Q;
+        }
+    }
     Qn = fmaf(q, P - Pn, Qp);
-    S += 1u + (((u32)Pn >> 1) & 1u);
+    acc = fmaf(__builtin_amdgcn_fractf(Pn), 4.f, acc);
 }
 
 // Wave-level work queue.  A wave claims kQueueChunk consecutive items of a
