@@ -204,15 +204,16 @@ int eis_cancel(eis_ctx *ctx, uint64_t ticket);
 /* ----- Autotuner ----------------------------------------------------- */
 
 /* Time the plain walk and the giant-step method (window scales 1 to 7) on
- * sample ranges of 2^21 candidates starting at 10^6.5, 10^7.5, ..., 10^11.5
- * and keep, per height decade 10^k <= d < 10^(k+1), the faster method and its
- * best window scale (below 10^6: the plain walk).  The AUTO method then
- * follows these choices (an explicit method or window scale in the config
- * still wins).  With cfg.tune_cache_path set at eis_create, the choices are
- * loaded from that file when it exists and holds every decade, and eis_tune
- * writes them there (EIS_EINVAL if the file cannot be written; the choices
- * are in force anyway).  Every choice gives the same bits; only the time
- * differs.  Takes a few seconds.  Thread-safe against the other calls. */
+ * sample ranges of 2^23 candidates, one per half-decade height bin
+ * 10^(b/2) <= d < 10^((b+1)/2) from 10^6 to 10^12, starting at the bin's
+ * geometric middle, and keep per bin the faster method and its best window
+ * scale (below 10^6: the plain walk).  The AUTO method then follows these
+ * choices (an explicit method or window scale in the config still wins).
+ * With cfg.tune_cache_path set at eis_create, the choices are loaded from
+ * that file when it exists and holds every bin, and eis_tune writes them
+ * there (EIS_EINVAL if the file cannot be written; the choices are in force
+ * anyway).  Every choice gives the same bits; only the time differs.  Takes
+ * a few seconds.  Thread-safe against the other calls. */
 int eis_tune(eis_ctx *ctx);
 
 /* The choice in force for height d: *method (an eis_method, BABY or INFRA)

@@ -107,6 +107,10 @@ struct Request {
 
 }  // namespace
 
+// Autotuner height bins: bin b holds 10^(b/2) <= d < 10^((b+1)/2), b < 25.
+constexpr int kTuneBins = 25;
+constexpr int kTuneFirstBin = 12;  // below 10^6 the plain walk, untimed
+
 struct eis_ctx {
     eis_config cfg{};
     int device = 0;
@@ -119,10 +123,10 @@ struct eis_ctx {
     double window_scale = kDefaultWindowScale;
     u64 infra_min_height = kDefaultInfraMinHeight;
     bool use_graphs = true;
-    // autotuner choices per height decade 10^k, k = 0..12
+    // autotuner choices per height bin (half decades, see bin_of)
     bool tuned = false;
-    int tuned_method[13] = {};
-    double tuned_ws[13] = {};
+    int tuned_method[kTuneBins] = {};
+    double tuned_ws[kTuneBins] = {};
     std::string tune_path;
 
     // prime table
@@ -162,7 +166,6 @@ struct eis_ctx {
     u32 *d_lres = nullptr;
     u32 *d_tables = nullptr;
     u64 infra_bytes = 0;
-    u32 *d_glist = nullptr;
     u64 infra_batch_cap = 0;
     u32 infra_emax_cap = 0;
     u32 infra_tsize_cap = 0;
@@ -244,8 +247,8 @@ extern "C" void eis_config_default(eis_config *cfg)
 }
 
 // Autotuner cache: a small JSON object written by eis_tune,
-//   {"arch": "gfx950", "decades": [{"k": 6, "method": 0, "window_scale": 3.5, ...}, ...]}
-// read back by scanning for the three keys of every decade.
+//   {"arch": "gfx950", "bins": [{"b": 12, "method": 0, "window_scale": 3.5, ...}, ...]}
+// read back by scanning for the three keys of every bin.
 static void load_tune_cache(eis_ctx *c)
 {
     FILE *f = std::fopen(c->tune_path.c_str(), "r");
@@ -256,22 +259,29 @@ static void load_tune_cache(eis_ctx *c)
     while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
     std::fclose(f);
     if (txt.find("\"gfx950\"") == std::string::npos) return;
-    int seen = 0;
+    int method[kTuneBins];
+    double ws[kTuneBins];
+    u32 seen = 0;
     size_t at = 0;
-    while ((at = txt.find("\"k\":", at)) != std::string::npos) {
-        int k = -1, m = -1;
-        double ws = 0.0;
-        const char *q = txt.c_str() + at;
-        if (std::sscanf(q, "\"k\": %d, \"method\": %d, \"window_scale\": %lf", &k, &m, &ws) == 3 &&
-            k >= 0 && k <= 12 && (m == 0 || m == 1) && ws > 0.0 && ws < 100.0) {
-            c->tuned_method[k] = m;
-            c->tuned_ws[k] = ws;
-            seen |= 1 << k;
+    while ((at = txt.find("\"b\":", at)) != std::string::npos) {
+        int b = -1, m = -1;
+        double w = 0.0;
+        if (std::sscanf(txt.c_str() + at, "\"b\": %d, \"method\": %d, \"window_scale\": %lf", &b, &m,
+                        &w) == 3 &&
+            b >= 0 && b < kTuneBins && (m == 0 || m == 1) && w > 0.0 && w < 100.0) {
+            method[b] = m;
+            ws[b] = w;
+            seen |= 1u << b;
         }
         at += 4;
     }
-    // every decade must be present
-    if (seen == (1 << 13) - 1) c->tuned = true;
+    // every bin must be present
+    if (seen != (1u << kTuneBins) - 1) return;
+    for (int b = 0; b < kTuneBins; b++) {
+        c->tuned_method[b] = method[b];
+        c->tuned_ws[b] = ws[b];
+    }
+    c->tuned = true;
 }
 
 static void free_infra(eis_ctx *c)
@@ -280,14 +290,12 @@ static void free_infra(eis_ctx *c)
     (void)hipFree(c->d_lists);
     (void)hipFree(c->d_lres);
     (void)hipFree(c->d_tables);
-    (void)hipFree(c->d_glist);
     c->d_state = nullptr;
     c->d_lists = nullptr;
     c->d_lres = nullptr;
     c->d_tables = nullptr;
     c->bytes_held -= c->infra_bytes;
     c->infra_bytes = 0;
-    c->d_glist = nullptr;
     c->infra_batch_cap = 0;
     c->infra_emax_cap = c->infra_tsize_cap = 0;
 }
@@ -491,13 +499,12 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(u32));
+    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState));
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
         hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
         hipMalloc(&c->d_tables, cap * tsize * 4) != hipSuccess ||
-        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
-        hipMalloc(&c->d_glist, cap * sizeof(u32)) != hipSuccess) {
+        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess) {
         free_infra(c);
         return EIS_ENOMEM;
     }
@@ -531,26 +538,35 @@ static void infra_geometry(double scaled_root, u32 &emax, u32 &tsize)
     while (tsize < 2 * (std::min(emain, emax - 8) + 4)) tsize <<= 1;
 }
 
-// k with 10^k <= d < 10^(k+1), at most 12
-static int decade_of(u64 d)
+// lower end of tuner bin b: 10^(b/2), rounded up for odd b
+static u64 bin_start(int b)
 {
-    int k = 0;
-    for (u64 p = 10; k < 12 && d >= p; p *= 10) k++;
-    return k;
+    u64 p = 1;
+    for (int t = 0; t < b / 2; t++) p *= 10;
+    if (b % 2) p = (u64)std::ceil((double)p * 3.1622776601683795);
+    return p;
+}
+
+// b with bin_start(b) <= d < bin_start(b + 1), at most kTuneBins - 1
+static int bin_of(u64 d)
+{
+    int b = 0;
+    while (b < kTuneBins - 1 && d >= bin_start(b + 1)) b++;
+    return b;
 }
 
 static u32 method_for(const eis_ctx *c, u64 d0)
 {
     if (c->cfg.method == EIS_METHOD_INFRA) return 1;
     if (c->cfg.method == EIS_METHOD_BABY) return 0;
-    if (c->tuned) return (u32)c->tuned_method[decade_of(d0)];
+    if (c->tuned) return (u32)c->tuned_method[bin_of(d0)];
     return d0 >= c->infra_min_height ? 1 : 0;
 }
 
 static double scale_for(const eis_ctx *c, u64 d0)
 {
     if (c->cfg.window_scale > 0) return c->cfg.window_scale;
-    if (c->tuned) return c->tuned_ws[decade_of(d0)];
+    if (c->tuned) return c->tuned_ws[bin_of(d0)];
     return c->window_scale;
 }
 
@@ -683,6 +699,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk0, st));
     WalkParams wp;
     wp.segs = c->d_segs;
+    wp.nseg = pl.nseg;
     wp.eis_words = c->d_eis_words;
     wp.max_steps = (u32)c->cfg.max_steps_per_d;
     if (pl.plain_cand) {
@@ -693,14 +710,13 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
     if (pl.giant_cand) {
         InfraParams ip;
         ip.segs = c->d_segs;
+        ip.nseg = pl.nseg;
         ip.list = c->d_list_giant;
         ip.list_ctr = ctr_giant;
         ip.batch = (u32)pl.batch;
         ip.ctr = ctr_giant;
         ip.win_next = c->d_q;
-        ip.giant_len = c->d_q + 16;
-        ip.giant_next = c->d_q + 32;
-        ip.giant_list = c->d_glist;
+        ip.giant_next = c->d_q + 16;
         ip.fb_list = c->d_fb_list;
         ip.fb_ctr = ctr_fb;
         ip.state = c->d_state;
@@ -1291,25 +1307,26 @@ extern "C" int eis_tune(eis_ctx *c)
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     const double scales[] = {1.0, 1.5, 2.5, 3.5, 5.0, 7.0};
-    const u32 n = 1u << 21;  // candidates per sample: enough d's to fill the device
-    int method[13];
-    double wsc[13], plain_ms[13], giant_ms[13];
-    for (int k = 0; k <= 12; k++) {
-        method[k] = 0;
-        wsc[k] = kDefaultWindowScale;
-        plain_ms[k] = giant_ms[k] = 0.0;
+    const u32 n = 1u << 23;  // candidates per sample: half a full pass
+    int method[kTuneBins];
+    double wsc[kTuneBins], plain_ms[kTuneBins], giant_ms[kTuneBins];
+    for (int b = 0; b < kTuneBins; b++) {
+        method[b] = 0;
+        wsc[b] = kDefaultWindowScale;
+        plain_ms[b] = giant_ms[b] = 0.0;
     }
     float ms = 0.f;
     // one untimed pass of each method allocates every buffer
     int rc = time_pass(c, 1000000005ull, n, 0, kDefaultWindowScale, ms);
     if (rc == EIS_OK) rc = time_pass(c, 1000000005ull, n, 1, 7.0, ms);
     if (rc != EIS_OK) return rc;
-    // decades 10^6 .. 10^11, sampled at their geometric middle; d < 10^12
-    for (int k = 6; k <= 11; k++) {
-        const u64 d0 = eis_first_candidate((u64)std::llround(std::pow(10.0, k + 0.5)));
+    // bins from 10^6 up, each sampled from its geometric middle: the last
+    // sample, at 10^11.75, ends below 10^12
+    for (int b = kTuneFirstBin; b < kTuneBins - 1; b++) {
+        const u64 d0 = eis_first_candidate((u64)std::llround(std::pow(10.0, (b + 0.5) / 2.0)));
         rc = time_pass(c, d0, n, 0, kDefaultWindowScale, ms);
         if (rc != EIS_OK) return rc;
-        plain_ms[k] = ms;
+        plain_ms[b] = ms;
         double best = 1e30, best_ws = kDefaultWindowScale;
         for (double ws : scales) {
             rc = time_pass(c, d0, n, 1, ws, ms);
@@ -1319,31 +1336,32 @@ extern "C" int eis_tune(eis_ctx *c)
                 best_ws = ws;
             }
         }
-        giant_ms[k] = best;
-        method[k] = best < plain_ms[k] ? 1 : 0;
-        wsc[k] = best_ws;
+        giant_ms[b] = best;
+        method[b] = best < plain_ms[b] ? 1 : 0;
+        wsc[b] = best_ws;
     }
-    // below 10^6 the plain walk; the last decade holds d = 10^12 only
-    for (int k = 0; k < 6; k++) wsc[k] = wsc[6];
-    method[12] = method[11];
-    wsc[12] = wsc[11];
+    // below 10^6 the plain walk; the last bin holds d = 10^12 only
+    for (int b = 0; b < kTuneFirstBin; b++) wsc[b] = wsc[kTuneFirstBin];
+    method[kTuneBins - 1] = method[kTuneBins - 2];
+    wsc[kTuneBins - 1] = wsc[kTuneBins - 2];
     {
         std::lock_guard<std::mutex> lk(c->smu);
-        for (int k = 0; k <= 12; k++) {
-            c->tuned_method[k] = method[k];
-            c->tuned_ws[k] = wsc[k];
+        for (int b = 0; b < kTuneBins; b++) {
+            c->tuned_method[b] = method[b];
+            c->tuned_ws[b] = wsc[b];
         }
         c->tuned = true;
     }
     if (!c->tune_path.empty()) {
         FILE *f = std::fopen(c->tune_path.c_str(), "w");
         if (!f) return EIS_EINVAL;
-        std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"decades\": [\n", n);
-        for (int k = 0; k <= 12; k++)
+        std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"bins\": [\n", n);
+        for (int b = 0; b < kTuneBins; b++)
             std::fprintf(f,
-                         "  {\"k\": %d, \"method\": %d, \"window_scale\": %.3f, "
+                         "  {\"b\": %d, \"method\": %d, \"window_scale\": %.3f, \"from\": %llu, "
                          "\"plain_ms\": %.3f, \"giant_ms\": %.3f}%s\n",
-                         k, method[k], wsc[k], plain_ms[k], giant_ms[k], k < 12 ? "," : "");
+                         b, method[b], wsc[b], (unsigned long long)bin_start(b), plain_ms[b],
+                         giant_ms[b], b < kTuneBins - 1 ? "," : "");
         std::fprintf(f, "]}\n");
         if (std::fclose(f) != 0) return EIS_EINVAL;
     }

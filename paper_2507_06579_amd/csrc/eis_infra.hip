@@ -18,26 +18,35 @@
 //                  hash table of 32-bit slots (list index + 16-bit
 //                  fingerprint; a fingerprint match is confirmed against the
 //                  list entry), built in LDS and written out whole.
-//   k_walk_giant   one d per lane, lanes refilled from a queue: mu_k =
-//                  reduce(mu_1 * mu_{k-1}) (NUDUPL for k = 2, then NUCOMP),
-//                  the residue updated with log mu_1 + log mu_{k-1} - log gamma
-//                  + the residues of the reduction steps; then reduction steps
-//                  forward to the first distinguished ideal, which is looked
-//                  up.  A hit gives log eps = log(ideal) - log(stored ideal).
+//   k_walk_giant   one d per lane, lanes refilled from a queue: the giant
+//                  step is g = reduce(mu_1^2) (NUDUPL), then g_k =
+//                  reduce(g * g_{k-1}) (NUCOMP), the residue updated with
+//                  log g + log g_{k-1} - log gamma + the residues of the
+//                  reduction steps; then reduction steps forward to the first
+//                  distinguished ideal, which is looked up twice: itself (a
+//                  hit means one period past a window ideal: log eps =
+//                  log(ideal) - log(window ideal)) and its conjugate (one
+//                  period short of a window ideal: log eps = log(ideal) +
+//                  log(window ideal)).  The dictionary thus covers distances
+//                  on both sides of (1), and the giant step can be twice mu_1.
 //
 // Why the distinguished ideals: a dictionary with every window ideal would
 // cost one scattered 8-byte store per reduction step.  With only every 16th
 // ideal stored, the stores are rare and the tables small, at the price of a
-// short walk after every giant step.  Correctness is unchanged: giant steps
-// advance by at most the distance of mu_1 plus the few reduction steps of
-// the composition, so the first giant ideal past a full period lies at most
-// (position of mu_1 + 6) ideals past (1), and the first distinguished ideal
-// at or after it is in the dictionary.  A hit at k = 2 is skipped: when the
-// window is short, mu_2 can land inside the window itself, which reads as a
-// "unit" of distance 0.  From k = 3 on, the giant ideals lie beyond the
-// window's short extension, so a hit is at one regulator, or at two when the
-// skipped k = 2 hit was a true one; log eps^2 = 2 log eps is 0 in Z/3 exactly
-// when log eps is, so the flag is the same.
+// short walk after every giant step.  A distinguished ideal's conjugate is
+// distinguished too (Q_{l-m} = Q_m), so the conjugate lookups see the same
+// set.  Coverage: the dictionary holds the distinguished ideals at
+// distances [0, D] and, through the conjugate lookups, [-D, 0] (mod the
+// regulator), where D is the window's end; the giant step g = mu_1^2
+// advances by about twice mu_1's distance, and the window runs at least six
+// ideals past mu_1, so consecutive giant ideals cannot jump over the covered
+// stretch around a period.  A direct hit at the first lookup (g itself) is
+// skipped: when the window is short, g can land inside the window, which
+// reads as a "unit" of distance 0.  Later giant ideals lie beyond the
+// window, so a direct hit is at one regulator (or two after a skipped true
+// hit); a conjugate hit can never be at distance 0, since giant ideals move
+// forward.  log eps^2 = 2 log eps is 0 in Z/3 exactly when log eps is, so a
+// hit at two regulators gives the same flag.
 //
 // Any arithmetic check that fails (fp64 exactness, exact divisions, step or
 // walk budgets, table overflow) sends the d to the plain walk, which is exact
@@ -67,25 +76,26 @@ __device__ __forceinline__ unsigned long long entry_of(float Q4, float P4)
 }
 
 // ---------------------------------------------------------------------------
-// k_walk_window: a wave takes a tile of 64 consecutive batch positions, one d
-// per lane, and keeps it until every lane's window has ended, so that the
-// 64 lanes append to one tile of the list array (tile-interleaved layout:
-// the writes of a wave stay within one small region of memory).
+// k_walk_window: persistent, one d per lane; a lane whose window ends takes
+// the next batch position from a queue (claimed 64 at a time per wave, so a
+// wave's lanes work on neighbouring positions and append to neighbouring
+// list tiles).  The per-position outcome goes to p.state: count > 0 = the
+// d takes giant steps; count = 0 = its flag is out (half period) or it was
+// handed to the plain walk.
 // ---------------------------------------------------------------------------
 // Window bookkeeping of one reduction step that landed on (Q, P) (quarter
-// units): append a distinguished ideal to the list -- entry cnt of this lane
-// of the tile at lt[64 cnt + lane], twice its residue sum at rt[...] -- and
-// note the step jc = jb + k of the last entry and, for mu_1 (the emain-th
-// entry), the step from which an entry ends the window (jc + kExtraSteps).
-// S2k + acc is twice the residue sum up to this step.
-__device__ __forceinline__ void window_insert(unsigned long long *lt, u32 *rt, u32 lane, float Q,
-                                              float P, u32 S2k, float acc, u32 jb, u32 k,
-                                              u32 emain, u32 &cnt, u32 &j1e, u32 &jlast)
+// units): append a distinguished ideal to the d's list -- entry cnt at
+// lb[64 cnt], twice its residue sum at rb[64 cnt] -- and note the step
+// jc = jb + k of the last entry and, for mu_1 (the emain-th entry), the step
+// from which an entry ends the window (jc + kExtraSteps).  S2k + acc is
+// twice the residue sum up to this step.
+__device__ __forceinline__ void window_insert(unsigned long long *lb, u32 *rb, float Q, float P,
+                                              u32 S2k, float acc, u32 jb, u32 k, u32 emain,
+                                              u32 &cnt, u32 &j1e, u32 &jlast)
 {
     if (is_dp(Q)) {
-        const u32 o = cnt * 64u + lane;
-        lt[o] = entry_of(Q, P);
-        rt[o] = S2k + (u32)acc;
+        lb[(u64)cnt * 64] = entry_of(Q, P);
+        rb[(u64)cnt * 64] = S2k + (u32)acc;
         cnt++;
         jlast = jb + k;
         j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
@@ -94,142 +104,153 @@ __device__ __forceinline__ void window_insert(unsigned long long *lt, u32 *rt, u
 
 __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
 {
+    __shared__ SegInfo segs[kMaxSegments];
+    load_segs(segs, p.segs, p.nseg);
     const u32 lane = __lane_id();
     const u32 total = p.list_ctr->list_len;
     const u32 nb = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
-    const u32 ntiles = (nb + 63) / 64;
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
     const u32 cnt_end = p.emax - 1;  // a full list ends the window (then the d goes plain)
+    // lane state: the d at batch position pos, its list (entry e at lb[64 e],
+    // rb[64 e]), the walk in quarter units (see rho_step_q), S2 = twice the
+    // residue sum at the start of the current chunk of steps, and the
+    // window bookkeeping (an entry at step >= j1e ends the window)
+    unsigned long long *lb = p.lists;
+    u32 *rb = p.lres;
+    float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
+    u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
+    u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
+    bool active = false;
     u64 my_steps = 0, my_refills = 0;
+    // the lane's next batch position and its work item, loaded one refill ahead
+    u32 npos = nb;
+    wave_take(p.win_next, nb, true, npos, cbase, cend);
+    u32 nitem = (npos < nb) ? p.list[p.k0 + npos] : 0u;
+    if (npos >= nb) npos = kNoItem;
 
     for (;;) {
-        u32 t = 0;
-        if (lane == 0) t = atomicAdd(p.win_next, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= ntiles) break;
-        const u32 pos = t * 64 + lane;
-        // the tile's list and residue entries (wave-uniform bases)
-        unsigned long long *lt = p.lists + (u64)t * p.emax * 64;
-        u32 *rt = p.lres + (u64)t * p.emax * 64;
-        // walk state in quarter units (see rho_step_q); S2 = twice the
-        // residue sum at the start of the current chunk of steps; an entry
-        // at step >= j1e ends the window (j1e = step of mu_1 + kExtraSteps)
-        float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
-        u32 S2 = 0, j = 0, idx = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
-        bool active = false, to_giant = false, to_plain = false;
-        u32 item = 0;
-        if (pos < nb) {
-            item = p.list[p.k0 + pos];
-            idx = item_bit(p.segs, item);
-            my_refills++;
-            const u64 d = item_d(p.segs, item);
-            const u64 si = isqrt_u64(d);
-            const u64 P1 = ((si + 1) >> 1) * 2 - 1;
-            const u64 Q1 = (d - P1 * P1) >> 1;
-            const u32 S1 = 1u + (u32)((P1 >> 1) & 1);
-            j = 1;
-            if (Q1 == 2) {
-                emit_flag(p.eis_words, idx, S1 % 3u == 0u);
-            } else {
-                sq = (float)si * 0.25f;
-                sqc = sq * kQuotBias;
-                P = (float)P1 * 0.25f;
-                Q = (float)Q1 * 0.25f;
-                S2 = 2u * S1;
-                // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
-                lt[lane] = entry_of(0.5f, P);
-                rt[lane] = 0u;
-                cnt = 1;
-                const float n = p.segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
-                emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
-                window_insert(lt, rt, lane, Q, P, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
-                active = true;
+        // ---- refill: lanes without a window start their prefetched d and
+        // claim the next one (whose load completes during the walk) --------
+        for (;;) {
+            const bool want = !active && npos != kNoItem;
+            if (!__any(want)) break;
+            u32 k = nb;
+            wave_take(p.win_next, nb, want, k, cbase, cend);
+            if (want) {
+                pos = npos;
+                item = nitem;
+                npos = (k < nb) ? k : kNoItem;
+                nitem = (k < nb) ? p.list[p.k0 + k] : 0u;
+                {
+                    idx = item_bit(segs, item);
+                    my_refills++;
+                    lb = p.lists + ((u64)(pos / 64) * p.emax * 64 + pos % 64);
+                    rb = p.lres + ((u64)(pos / 64) * p.emax * 64 + pos % 64);
+                    const u64 d = item_d(segs, item);
+                    const u64 si = isqrt_u64(d);
+                    const u64 P1 = ((si + 1) >> 1) * 2 - 1;
+                    const u64 Q1 = (d - P1 * P1) >> 1;
+                    const u32 S1 = 1u + (u32)((P1 >> 1) & 1);
+                    j = 1;
+                    my_steps += 1;
+                    if (Q1 == 2) {
+                        emit_flag(p.eis_words, idx, S1 % 3u == 0u);
+                        WindowState st = {0u, 0u, item, 0u};
+                        p.state[pos] = st;
+                    } else {
+                        sq = (float)si * 0.25f;
+                        sqc = sq * kQuotBias;
+                        P = (float)P1 * 0.25f;
+                        Q = (float)Q1 * 0.25f;
+                        Qp = 0.5f;
+                        S2 = 2u * S1;
+                        // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
+                        lb[0] = entry_of(0.5f, P);
+                        rb[0] = 0u;
+                        cnt = 1;
+                        j1e = ~0u;
+                        jlast = 0;
+                        const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
+                        emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
+                        window_insert(lb, rb, Q, P, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
+                        active = true;
+                    }
+                }
             }
         }
-        while (__any(active)) {
-            if (active) {
-                // Two steps per iteration; the loop leaves as soon as any lane
-                // reaches the half-period or the end of its window.  The
-                // window ends once an entry at least kExtraSteps past mu_1 is
-                // stored (or the list is full).
-                u32 k = 0;
-                u64 mh = 0, ms = 0;
-                bool first_half = false;
-                float P1 = 0.f, Q1 = 0.f, acc = 0.f;
-                for (;;) {
-                    float P2, Q2;
-                    rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
-                    mh = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-                    window_insert(lt, rt, lane, Q1, P1, S2 + k + 1, acc, j + 1, k, emain, cnt, j1e,
-                                  jlast);
-                    if (mh) {
-                        // the window-end test runs on every exit from the
-                        // loop, so that no lane starts a pair with fewer than
-                        // two free list entries
-                        ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
-                             __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
-                        first_half = true;
-                        break;
-                    }
-                    rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
-                    mh = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
-                    window_insert(lt, rt, lane, Q2, P2, S2 + k + 2, acc, j + 2, k, emain, cnt, j1e,
-                                  jlast);
+        if (!__any(active)) break;
+
+        if (active) {
+            // Two steps per iteration; the loop leaves as soon as any lane
+            // reaches the half-period or the end of its window.  The window
+            // ends once an entry at least kExtraSteps past mu_1 is stored (or
+            // the list is full).  The window-end test runs on every exit
+            // from the loop, so no lane starts a pair with fewer than two
+            // free list entries.
+            u32 k = 0;
+            u64 mh = 0, ms = 0;
+            bool first_half = false;
+            float P1 = 0.f, Q1 = 0.f, acc = 0.f;
+            for (;;) {
+                float P2, Q2;
+                rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
+                mh = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
+                window_insert(lb, rb, Q1, P1, S2 + k + 1, acc, j + 1, k, emain, cnt, j1e, jlast);
+                if (mh) {
                     ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
                          __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
-                    Qp = Q1;
-                    Q = Q2;
-                    P = P2;
-                    k += 2;
-                    if ((mh | ms) || k >= K) break;
+                    first_half = true;
+                    break;
                 }
-                if (first_half) {
-                    Qp = Q;
-                    Q = Q1;
-                    P = P1;
-                    k += 1;
+                rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
+                mh = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
+                window_insert(lb, rb, Q2, P2, S2 + k + 2, acc, j + 2, k, emain, cnt, j1e, jlast);
+                ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
+                     __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
+                Qp = Q1;
+                Q = Q2;
+                P = P2;
+                k += 2;
+                if ((mh | ms) || k >= K) break;
+            }
+            if (first_half) {
+                Qp = Q;
+                Q = Q1;
+                P = P1;
+                k += 1;
+            }
+            j += k;
+            my_steps += k;
+            S2 += k + (u32)acc;
+            if ((mh >> lane) & 1ull) {
+                // half-period symmetry: the unit is found without giant steps
+                const u32 S = S2 >> 1;
+                const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
+                const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
+                emit_flag(p.eis_words, idx, v % 3u == 0u);
+                WindowState st = {0u, 0u, item, 0u};
+                p.state[pos] = st;
+                active = false;
+            } else if ((ms >> lane) & 1ull) {
+                // end of the window; its extension past mu_1 must be short
+                // next to mu_1's own distance (see above)
+                const u32 j1 = j1e - kExtraSteps;
+                const bool ok = j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2 < (1u << 24);
+                WindowState st = {emain, ok ? cnt : 0u, item, 0u};
+                p.state[pos] = st;
+                if (!ok) {
+                    const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                    p.fb_list[f] = item;
                 }
-                j += k;
-                S2 += k + (u32)acc;
-                if ((mh >> lane) & 1ull) {
-                    // half-period symmetry: the unit is found without giant steps
-                    const u32 S = S2 >> 1;
-                    const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
-                    const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
-                    emit_flag(p.eis_words, idx, v % 3u == 0u);
-                    active = false;
-                } else if ((ms >> lane) & 1ull) {
-                    // end of the window; its extension past mu_1 must be short
-                    // next to mu_1's own distance (see above)
-                    const u32 j1 = j1e - kExtraSteps;
-                    if (j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2 < (1u << 24)) {
-                        WindowState st;
-                        st.emain = emain;
-                        st.count = cnt;
-                        st.item = item;
-                        st.pad = 0;
-                        p.state[pos] = st;
-                        to_giant = true;
-                    } else {
-                        to_plain = true;
-                    }
-                    active = false;
-                } else if (j > p.max_steps) {
-                    to_plain = true;
-                    active = false;
-                }
+                active = false;
+            } else if (j > p.max_steps) {
+                WindowState st = {0u, 0u, item, 0u};
+                p.state[pos] = st;
+                const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                p.fb_list[f] = item;
+                active = false;
             }
         }
-        // hand the tile's d's on, one atomic per wave and list
-        if (to_giant) {
-            const u32 gslot = atomicAdd(p.giant_len, 1u);
-            p.giant_list[gslot] = pos;
-        }
-        if (to_plain) {
-            const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-            p.fb_list[f] = item;
-        }
-        my_steps += j;
     }
     for (int off = 32; off > 0; off >>= 1) {
         my_steps += __shfl_down(my_steps, off, 64);
@@ -269,16 +290,17 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     const u32 lb = xcd * q + min(xcd, r) + b / 8;  // logical block
     const u32 wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const u32 w = lb * 4 + wv;
-    const u32 n = *p.giant_len;
-    const bool valid = w < n;
+    const u32 total = p.list_ctr->list_len;
+    const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
+    // the d at batch position w takes giant steps iff its window left entries
+    const u32 cnt = (w < n) ? p.state[w].count : 0u;
+    const bool valid = cnt != 0u;
     const u32 mask = p.tsize - 1;
     for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
     __syncthreads();
-    u32 pos = 0;
+    const u32 pos = w;
     if (valid) {
-        pos = p.giant_list[w];
         const unsigned long long *lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
-        const u32 cnt = p.state[pos].count;
         for (u32 e = lane; e < cnt; e += 64) {
             const unsigned long long ent = lst[(u64)e * 64];
             const u32 qb = (u32)(ent >> 32), pb = (u32)ent;
@@ -310,9 +332,34 @@ hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream)
 // ---------------------------------------------------------------------------
 // k_walk_giant
 // ---------------------------------------------------------------------------
+constexpr u32 kNoEntry = ~0u;
+
+// Index of the window entry with key (qb, pb) in a d's table (open
+// addressing, linear probing), or kNoEntry.  A slot's fingerprint match is
+// confirmed against the full key in the list.
+__device__ __forceinline__ u32 dict_find(const u32 *tbl, const unsigned long long *lst, u32 mask,
+                                         u32 tsize, u32 qb, u32 pb)
+{
+    const unsigned long long key = ((unsigned long long)qb << 32) | pb;
+    const u32 h = dict_hash(qb, pb);
+    u32 slot = h & mask;
+    for (u32 probe = 0; probe < tsize; probe++) {
+        const u32 v = tbl[slot];
+        if (v == 0u) break;
+        if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
+            const u32 e = (v & 0xffffu) - 1;
+            if (lst[(u64)e * 64] == key) return e;
+        }
+        slot = (slot + 1) & mask;
+    }
+    return kNoEntry;
+}
 __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 {
-    const u32 n = *p.giant_len;
+    __shared__ SegInfo segs[kMaxSegments];
+    load_segs(segs, p.segs, p.nseg);
+    const u32 total = p.list_ctr->list_len;
+    const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 mask = p.tsize - 1;
     // per-lane state
     u32 idx = 0, item = 0, ng = 0;
@@ -340,14 +387,16 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 if (g >= n) {
                     exhausted = true;
                 } else {
-                    const u32 pos = p.giant_list[g];
+                    const u32 pos = g;
                     const WindowState st = p.state[pos];
+                    // positions whose flag is out or that went plain are skipped
+                    if (st.count == 0u) continue;
                     lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
                     lrs = p.lres + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
                     const unsigned long long m1 = lst[(u64)(st.emain - 1) * 64];
                     item = st.item;
-                    idx = item_bit(p.segs, item);
-                    const u64 d = item_d(p.segs, item);
+                    idx = item_bit(segs, item);
+                    const u64 d = item_d(segs, item);
                     const u64 s64 = isqrt_u64(d);
                     dd = (double)d;
                     sd = (double)s64;
@@ -383,8 +432,14 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 double Qk, Pk, Qpk;
                 const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, bad);
                 const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
-                ng++;
                 if (!bad) {
+                    if (ng == 0) {
+                        // the first composition squares mu_1; its square is
+                        // the giant step from then on
+                        m1Q = Qk;
+                        m1P = Pk;
+                        m1S = Sk;
+                    }
                     cQ = Qk;
                     cP = Pk;
                     cS = Sk;
@@ -395,6 +450,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     w = 0;
                     walking = true;
                 }
+                ng++;
             }
             bool done = false, flag = false;
             if (walking) {
@@ -412,30 +468,32 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 my_steps += u;
                 if (is_dp(Qw)) {
                     walking = false;
-                    const u32 qb = __float_as_uint(Qw), pb = __float_as_uint(Pw);
-                    const unsigned long long key = ((unsigned long long)qb << 32) | pb;
-                    const u32 h = dict_hash(qb, pb);
-                    u32 slot = h & mask;
-                    for (u32 probe = 0; probe < p.tsize; probe++) {
-                        const u32 v = tbl[slot];
-                        if (v == 0u) break;
-                        if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
-                            // fingerprint matches: compare the full key
-                            const u32 e = (v & 0xffffu) - 1;
-                            if (lst[(u64)e * 64] == key) {
-                                // a hit at k = 2 is skipped: mu_2 may lie inside
-                                // the window (a "unit" of distance 0); if it was a
-                                // true hit, the next one is at eps or eps^2, whose
-                                // residues are both 0 or both not
-                                if (ng > 1) {
-                                    const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
-                                    flag = ((Sw + 3u - St) % 3u) == 0u;
-                                    done = true;
-                                }
-                                break;
-                            }
+                    // direct lookup: the ideal itself is a window ideal,
+                    // at one period past it
+                    const u32 qb = __float_as_uint(Qw);
+                    u32 e = dict_find(tbl, lst, mask, p.tsize, qb, __float_as_uint(Pw));
+                    // a direct hit at the first lookup (mu_1^2) is skipped: it
+                    // may lie inside the window (a "unit" of distance 0); if
+                    // it was a true hit, a later one is at eps or eps^2,
+                    // whose residues are both 0 or both not
+                    if (e != kNoEntry && ng > 1) {
+                        const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
+                        flag = ((Sw + 3u - St) % 3u) == 0u;
+                        done = true;
+                    } else {
+                        // conjugate lookup: the conjugate of the ideal
+                        // (Q_m, P_m) of the cycle is (Q_m, P_{m+1}); if that is
+                        // window ideal i, this ideal lies i ideals short of a
+                        // period, and log eps = S_m + S_i (conjugation acts as
+                        // log -> -log)
+                        float Pn, Qn, acc1 = 0.f;
+                        rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
+                        e = dict_find(tbl, lst, mask, p.tsize, qb, __float_as_uint(Pn));
+                        if (e != kNoEntry) {
+                            const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
+                            flag = ((Sw + St) % 3u) == 0u;
+                            done = true;
                         }
-                        slot = (slot + 1) & mask;
                     }
                 } else if (w >= kWalkLimit) {
                     bad = true;

@@ -74,6 +74,7 @@ __device__ __forceinline__ u32 item_bit(const SegInfo *segs, u32 item)
 
 struct WalkParams {
     const SegInfo *segs;          // segment table of the pass
+    u32 nseg;                     // its number of segments
     const u32 *list;              // items to walk
     PassCounters *ctr;            // list_len, queue head, error and step counters
     u32 *eis_words;               // output bitmaps of the pass
@@ -84,21 +85,20 @@ struct WalkParams {
 // Per-d record written by the window walk for the giant-step walk.
 struct WindowState {
     u32 emain;    // mu_1 (the giant step) is list entry emain - 1
-    u32 count;    // dictionary entries written
+    u32 count;    // dictionary entries written; 0 = the d takes no giant steps
     u32 item;     // the d's work item
     u32 pad;
 };
 
 struct InfraParams {
     const SegInfo *segs;        // segment table of the pass
+    u32 nseg;                   // its number of segments
     const u32 *list;            // items that take giant steps
     const PassCounters *list_ctr;  // list_ctr->list_len: number of such items
     u32 k0, batch;              // this launch handles list positions [k0, k0 + batch)
     PassCounters *ctr;          // step statistics
     u32 *win_next;              // window-walk queue head (per batch)
-    u32 *giant_list;            // batch-relative positions that need giant steps
-    u32 *giant_len;             // their number
-    u32 *giant_next;            // giant-walk queue head
+    u32 *giant_next;            // giant-walk queue head (per batch)
     u32 *fb_list;               // items handed to the plain walk
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position

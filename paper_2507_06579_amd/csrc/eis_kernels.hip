@@ -229,103 +229,129 @@ hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo
 // and d is Eisenstein iff log eps = 0 (mod 3).
 // ---------------------------------------------------------------------------
 
+// Exit batching: a lane whose walk ends idles (its steps are wasted) until
+// kBatch lanes of the wave are idle; then they are all refilled at once, so
+// that the wave-wide refill (queue, decode, first step) is paid once per
+// kBatch walks.  The best batch balances the refill cost against the idle
+// lanes: about sqrt(5.2e6 / sqrt(d)) for mean walks of 0.075 sqrt(d) steps,
+// i.e. 32 at 10^6, 13 at 10^9, 4 at 10^11.
+__device__ __forceinline__ u32 exit_batch(float s)
+{
+    return (u32)fminf(fmaxf(rintf(sqrtf(5.2e6f / s)), 1.f), 32.f);
+}
+
 __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
 {
+    __shared__ SegInfo segs[kMaxSegments];
+    load_segs(segs, p.segs, p.nseg);
     const u32 n = p.ctr->list_len;
     // inner-loop length between budget checks; a walk that has not ended
     // after max_steps (rounded up to a multiple of K) is abandoned and counted
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
+    const u32 lane = __lane_id();
     // walk state in quarter units (see rho_step_q)
     float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
     u32 S = 0, j = 0, idx = 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
-    bool active = false, exhausted = false;
+    bool live = false;        // the lane walks a d
+    bool drained = false;     // wave-uniform: the queue has no more items
+    u32 batch = 1;            // wave-uniform exit batch
     u64 my_steps = 0, my_refills = 0;
 
     for (;;) {
-        // ---- refill lanes without a walk --------------------------------
-        for (;;) {
-            bool want = !active && !exhausted;
+        // ---- refill every idle lane -------------------------------------
+        while (!drained) {
+            const bool want = !live;
             if (!__any(want)) break;
             u32 k = n;
             wave_take(&p.ctr->work_next, n, want, k, cbase, cend);
-            if (want) {
-                if (k >= n) {
-                    exhausted = true;
+            if (__any(want && k >= n)) drained = true;
+            if (want && k < n) {
+                const u32 item = p.list[k];
+                idx = item_bit(segs, item);
+                my_refills++;
+                double sd, P1, Q1;
+                u32 S1;
+                first_step(item_d(segs, item), sd, P1, Q1, S1);
+                my_steps += 1;
+                if (Q1 == 2.0) {
+                    // Q_1 = Q_0: log eps = S_1 + S_0 = S_1
+                    emit_flag(p.eis_words, idx, S1 % 3u == 0u);
                 } else {
-                    const u32 item = p.list[k];
-                    idx = item_bit(p.segs, item);
-                    my_refills++;
-                    u64 d = item_d(p.segs, item);
-                    u64 si = isqrt_u64(d);
-                    // first step from (P_0, Q_0) = (1, 2), in 64-bit integers
-                    u64 P1 = ((si + 1) >> 1) * 2 - 1;
-                    u64 Q1 = (d - P1 * P1) >> 1;
-                    u32 S1 = 1u + (u32)((P1 >> 1) & 1);
-                    my_steps += 1;
-                    if (Q1 == 2) {
-                        // Q_1 = Q_0: log eps = S_1 + S_0 = S_1
-                        emit_flag(p.eis_words, idx, S1 % 3u == 0u);
-                    } else {
-                        sq = (float)si * 0.25f;
-                        sqc = sq * kQuotBias;
-                        P = (float)P1 * 0.25f;
-                        Q = (float)Q1 * 0.25f;
-                        Qp = 0.5f;
-                        S = S1;
-                        j = 1;
-                        active = true;
-                    }
+                    sq = (float)sd * 0.25f;
+                    sqc = sq * kQuotBias;
+                    P = (float)P1 * 0.25f;
+                    Q = (float)Q1 * 0.25f;
+                    Qp = 0.5f;
+                    S = S1;
+                    j = 1;
+                    live = true;
                 }
             }
         }
-        if (!__any(active)) break;
-
-        if (active) {
-            // Up to K steps, leaving as soon as any lane of the wave reaches
-            // its exit; the loop control is wave-uniform (scalar branches).
-            // Two steps per iteration, so that the state never needs moves.
-            u32 k = 0;
-            u64 em = 0;
-            bool first_half = false;
-            float P1 = 0.f, Q1 = 0.f, acc = 0.f;
-            for (;;) {
-                float P2, Q2;
-                rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
-                em = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-                if (em) {
-                    first_half = true;
-                    break;
+        if (!__any(live)) break;
+        {
+            // the batch follows the walk lengths of the wave's current d's
+            // (those of its first walking lane)
+            const u32 first = (u32)__builtin_ctzll(__builtin_amdgcn_ballot_w64(live));
+            const float s0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(sq), first)) * 4.f;
+            batch = exit_batch(s0);
+        }
+        // Up to K steps, two per iteration (so that the state never needs
+        // moves); a lane whose walk ends emits its flag at once and idles.
+        // The loop control is wave-uniform and kept to a few scalar
+        // instructions per iteration (the scalar unit is shared by the four
+        // SIMDs of a CU): lm is the mask of walking lanes, and the exits of
+        // both steps are tested once per iteration.
+        u64 lm = __builtin_amdgcn_ballot_w64(live);
+        // leave for a refill once `batch` lanes idle (once all idle when the
+        // queue is drained): at most `keep` walking lanes
+        const u32 keep = drained ? 0u : 64u - batch;
+        const u32 iters = (K + 1) / 2;
+        u32 it = 0;
+        bool stop = false;
+        float P1 = 0.f, Q1 = 0.f, acc = 0.f;
+        for (;;) {
+            float P2, Q2;
+            rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
+            const u64 mA = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
+            rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
+            const u64 mB = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
+            const u64 em = (mA | mB) & lm;
+            if (em) {
+                // some walk ended at the first (A) or second (B) step
+                const bool exA = (mA & lm) >> lane & 1ull;
+                const bool exB = !exA && ((mB & lm) >> lane & 1ull);
+                if (exA || exB) {
+                    const u32 kx = 2 * it + (exA ? 1u : 2u);
+                    // acc up to the exit step (exact: small integers)
+                    const float accx = exA ? fmaf(__builtin_amdgcn_fractf(P2), -4.f, acc) : acc;
+                    const float Pj = exA ? P1 : P2;
+                    const bool qrule = exA ? (Q1 == Q) : (Q2 == Q1);
+                    const u32 Sj = S + ((kx + (u32)accx) >> 1);
+                    const u32 rj = __builtin_amdgcn_fractf(Pj) > 0.5f ? 2u : 1u;
+                    // Q-rule first (it also covers the tie at the period's end)
+                    const u32 v = qrule ? (2u * Sj - rj) : (2u * (Sj - rj));
+                    emit_flag(p.eis_words, idx, v % 3u == 0u);
+                    my_steps += j + kx - 1;
                 }
-                rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
-                em = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
-                Qp = Q1;
-                Q = Q2;
-                P = P2;
-                k += 2;
-                if (em || k >= K) break;
+                lm &= ~em;
+                stop = (u32)__builtin_popcountll(lm) <= keep;
             }
-            if (first_half) {
-                Qp = Q;
-                Q = Q1;
-                P = P1;
-                k += 1;
-            }
+            Qp = Q1;
+            Q = Q2;
+            P = P2;
+            if (++it >= iters || stop) break;
+        }
+        const u32 k = 2 * it;
+        live = (lm >> lane) & 1ull;
+        if (live) {
             j += k;
-            // sum of the residues of these k steps
             S += (k + (u32)acc) >> 1;
-            const bool ex = (em >> __lane_id()) & 1ull;
-            if (ex) {
-                const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
-                // Q-rule first (it also covers the tie at the period's end)
-                const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
-                emit_flag(p.eis_words, idx, v % 3u == 0u);
-                my_steps += j - 1;
-                active = false;
-            } else if (j > p.max_steps) {
+            if (j > p.max_steps) {
                 atomicAdd(&p.ctr->err_count, 1u);
                 my_steps += j - 1;
-                active = false;
+                live = false;
             }
         }
     }

@@ -14,6 +14,24 @@ __device__ __forceinline__ u64 isqrt_u64(u64 d)
     return s;
 }
 
+// The first reduction step of a walk, from (P_0, Q_0) = (1, 2):
+// s = isqrt(d), P_1 = the largest odd number <= s, Q_1 = (d - P_1^2)/2, and
+// the residue r(P_1).  In fp64: for d < 10^12 every value is an integer below
+// 2^41, so products and differences are exact, and the square root estimate
+// (off by at most one near squares) is corrected exactly.
+__device__ __forceinline__ void first_step(u64 d, double &s, double &P1, double &Q1, u32 &S1)
+{
+    const double dd = (double)d;
+    s = floor(sqrt(dd));
+    if (s * s > dd)
+        s -= 1.0;
+    else if ((s + 1.0) * (s + 1.0) <= dd)
+        s += 1.0;
+    P1 = 2.0 * floor((s + 1.0) * 0.5) - 1.0;
+    Q1 = (dd - P1 * P1) * 0.5;
+    S1 = 1u + (((u32)P1 >> 1) & 1u);
+}
+
 __device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
 {
     if (eis) atomicOr(&eis_words[idx >> 5], 1u << (idx & 31));
@@ -68,8 +86,8 @@ __device__ __forceinline__ void rho_step_q(float sq, float sqc, float P, float Q
 constexpr u32 kQueueChunk = 64;
 
 // Lanes with `want` set receive an item index in `item` (< n); lanes that
-// get nothing because the queue is drained get `item` = n.  Returns false
-// when the queue is drained for the whole wave.
+// get nothing because the queue is drained get `item` = n.  Must be called
+// by the whole wave (lane 0 claims the chunks).
 __device__ __forceinline__ void wave_take(u32 *head, u32 n, bool want, u32 &item, u32 &cbase,
                                           u32 &cend)
 {
@@ -103,6 +121,18 @@ __device__ __forceinline__ void wave_take(u32 *head, u32 n, bool want, u32 &item
 }
 
 // Iterations of the inner loop between two checks of the step budget.
+// The pass's segment table, copied into LDS by every block of a walk kernel
+// (decoding a work item then costs an LDS read, not a dependent global one).
+__device__ __forceinline__ void load_segs(SegInfo *dst, const SegInfo *src, u32 nseg)
+{
+    for (u32 i = threadIdx.x; i < nseg; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
+// Empty prefetch slot.  The walk kernels load the list entry of a lane's next
+// work item one refill ahead, so that the load's latency overlaps the walk.
+constexpr u32 kNoItem = ~0u;
+
 constexpr u32 kInnerChunk = 1u << 14;
 
 

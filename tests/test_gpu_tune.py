@@ -36,7 +36,7 @@ def test_tune_choices_cache_and_bits(tmp_path):
         tuned = [c.eis_classify(a, b) for a, b in ranges]
     with open(path) as f:
         doc = json.load(f)
-    assert doc["arch"] == "gfx950" and len(doc["decades"]) == 13
+    assert doc["arch"] == "gfx950" and len(doc["bins"]) == 25
     with eis.Context(method=eis.Method.BABY) as c:
         plain = [c.eis_classify(a, b) for a, b in ranges]
     for (sq1, e1, n1, m1), (sq2, e2, n2, m2) in zip(tuned, plain):
@@ -59,9 +59,9 @@ def test_untuned_defaults():
 
 def test_tune_cache_rejects_partial_file(tmp_path):
     path = tmp_path / "bad.json"
-    path.write_text('{"arch": "gfx950", "decades": [{"k": 6, "method": 1, "window_scale": 2.5}]}')
+    path.write_text('{"arch": "gfx950", "bins": [{"b": 12, "method": 1, "window_scale": 2.5}]}')
     with eis.Context(tune_cache_path=str(path)) as c:
-        # not every decade present: defaults stay in force
+        # not every bin present: defaults stay in force
         assert c.eis_tuned_choice(10**6) == (eis.Method.BABY, 3.5)
 
 
