@@ -37,7 +37,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # (addresses, count, residue sum, mu_1 bookkeeping: 10), which runs for the
 # wave whenever any of its 64 lanes appends, i.e. at nearly every step, and
 # the window-end tests once per two steps.
-VALU_PER_STEP = {"walk_plain": 11.5, "walk_handoff": 11.5, "walk_window": 26.0}
+VALU_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0, "walk_window": 30.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the

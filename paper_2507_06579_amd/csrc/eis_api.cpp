@@ -531,7 +531,7 @@ static void infra_geometry(double scaled_root, u32 &emax, u32 &tsize)
     double n = scaled_root / 16.0;
     u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
     emain = std::max<u32>(emain, 16);
-    emax = emain + 16;
+    emax = (emain + 16 + 7) / 8 * 8;  // whole 8-entry chunks (64-byte write-outs)
     if (emax > 496) emax = 496;
     // load factor at most 0.5 for the usual count (mu_1 plus a few)
     tsize = 32;

@@ -76,27 +76,62 @@ __device__ __forceinline__ unsigned long long entry_of(float Q4, float P4)
 }
 
 // ---------------------------------------------------------------------------
-// k_walk_window: persistent, one d per lane; a lane whose window ends takes
-// the next batch position from a queue (claimed 64 at a time per wave, so a
-// wave's lanes work on neighbouring positions and append to neighbouring
-// list tiles).  The per-position outcome goes to p.state: count > 0 = the
-// d takes giant steps; count = 0 = its flag is out (half period) or it was
-// handed to the plain walk.
+// k_walk_window: persistent, one d per lane.  A lane whose window ends (or
+// whose walk reaches the half period) idles until kBatch lanes of the wave
+// are idle; then all of them take their next batch position from a queue
+// (claimed 64 at a time per wave; the list entry of a lane's next d is
+// loaded one refill ahead).  The per-position outcome goes to p.state:
+// count > 0 = the d takes giant steps; count = 0 = its flag is out (half
+// period) or it was handed to the plain walk.
+//
+// List entries are staged in LDS, kRing per lane, and written out as one
+// contiguous chunk per kRing entries (64 bytes of keys, 32 of residue sums),
+// instead of one scattered 8-byte write each.
 // ---------------------------------------------------------------------------
-// Window bookkeeping of one reduction step that landed on (Q, P) (quarter
-// units): append a distinguished ideal to the d's list -- entry cnt at
-// lb[64 cnt], twice its residue sum at rb[64 cnt] -- and note the step
-// jc = jb + k of the last entry and, for mu_1 (the emain-th entry), the step
-// from which an entry ends the window (jc + kExtraSteps).  S2k + acc is
-// twice the residue sum up to this step.
-__device__ __forceinline__ void window_insert(unsigned long long *lb, u32 *rb, float Q, float P,
-                                              u32 S2k, float acc, u32 jb, u32 k, u32 emain,
-                                              u32 &cnt, u32 &j1e, u32 &jlast)
+constexpr u32 kRing = 8;
+
+struct WindowRing {
+    unsigned long long key[kRing][64];
+    u32 res[kRing][64];
+};
+
+// Write the lane's staged chunk (entries [base, base + kRing) of its list).
+__device__ __forceinline__ void ring_flush(const WindowRing &rg, u32 lane, unsigned long long *lb,
+                                           u32 *rb, u32 base)
 {
-    if (is_dp(Q)) {
-        lb[(u64)cnt * 64] = entry_of(Q, P);
-        rb[(u64)cnt * 64] = S2k + (u32)acc;
+    unsigned long long k[kRing];
+    u32 r[kRing];
+#pragma unroll
+    for (u32 e = 0; e < kRing; e++) {
+        k[e] = rg.key[e][lane];
+        r[e] = rg.res[e][lane];
+    }
+#pragma unroll
+    for (u32 e = 0; e < kRing; e += 2)
+        *reinterpret_cast<ulonglong2 *>(lb + base + e) = make_ulonglong2(k[e], k[e + 1]);
+#pragma unroll
+    for (u32 e = 0; e < kRing; e += 4)
+        *reinterpret_cast<uint4 *>(rb + base + e) = make_uint4(r[e], r[e + 1], r[e + 2], r[e + 3]);
+}
+
+// Window bookkeeping of one reduction step that landed on (Q, P) (quarter
+// units): stage a distinguished ideal as entry cnt of the lane's list (its
+// key and twice its residue sum, S2k + acc), write out a full chunk, and
+// note the step jc = jb + k of the last entry and, for mu_1 (the emain-th
+// entry), the step from which an entry ends the window (jc + kExtraSteps).
+// `hit` is the distinguished-ideal test value (see is_dp); idle lanes get
+// one that never matches.
+__device__ __forceinline__ void window_insert(WindowRing &rg, u32 lane, unsigned long long *lb,
+                                              u32 *rb, float Q, float P, float hit, u32 S2k,
+                                              float acc, u32 jb, u32 k, u32 emain, u32 &cnt,
+                                              u32 &j1e, u32 &jlast)
+{
+    if (__builtin_amdgcn_fractf(Q * kDpScale) == hit) {
+        const u32 slot = cnt % kRing;
+        rg.key[slot][lane] = entry_of(Q, P);
+        rg.res[slot][lane] = S2k + (u32)acc;
         cnt++;
+        if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
         jlast = jb + k;
         j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
     }
@@ -104,23 +139,29 @@ __device__ __forceinline__ void window_insert(unsigned long long *lb, u32 *rb, f
 
 __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
 {
-    __shared__ SegInfo segs[kMaxSegments];
+    __shared__ SegLds segs[kMaxSegments];
+    __shared__ WindowRing rings[4];
     load_segs(segs, p.segs, p.nseg);
     const u32 lane = __lane_id();
+    WindowRing &rg = rings[threadIdx.x >> 6];
     const u32 total = p.list_ctr->list_len;
     const u32 nb = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 K = __builtin_amdgcn_readfirstlane(min(kInnerChunk, max(p.max_steps, 1u)));
     const u32 cnt_end = p.emax - 1;  // a full list ends the window (then the d goes plain)
-    // lane state: the d at batch position pos, its list (entry e at lb[64 e],
-    // rb[64 e]), the walk in quarter units (see rho_step_q), S2 = twice the
-    // residue sum at the start of the current chunk of steps, and the
-    // window bookkeeping (an entry at step >= j1e ends the window)
+    // Exit batch: the refill (queue, decode, first step, window set-up) costs
+    // about as much as 30 reduction steps of the wave; a window is about
+    // 16 emain steps.
+    const u32 batch = (u32)fminf(fmaxf(rintf(sqrtf(16000.f / (float)(p.emax - 16))), 1.f), 32.f);
+    // lane state: the d at batch position pos, its list (entry e at lb[e],
+    // rb[e]), the walk in quarter units (see rho_step_q), S2 = twice the
+    // residue sum at the start of the current chunk of steps, and the window
+    // bookkeeping (an entry at step >= j1e ends the window)
     unsigned long long *lb = p.lists;
     u32 *rb = p.lres;
-    float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f;
+    float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f, hit = -1.f;
     u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
-    bool active = false;
+    bool live = false;
     u64 my_steps = 0, my_refills = 0;
     // the lane's next batch position and its work item, loaded one refill ahead
     u32 npos = nb;
@@ -129,10 +170,9 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
     if (npos >= nb) npos = kNoItem;
 
     for (;;) {
-        // ---- refill: lanes without a window start their prefetched d and
-        // claim the next one (whose load completes during the walk) --------
+        // ---- refill every idle lane that has a prefetched d -------------
         for (;;) {
-            const bool want = !active && npos != kNoItem;
+            const bool want = !live && npos != kNoItem;
             if (!__any(want)) break;
             u32 k = nb;
             wave_take(p.win_next, nb, want, k, cbase, cend);
@@ -141,114 +181,128 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                 item = nitem;
                 npos = (k < nb) ? k : kNoItem;
                 nitem = (k < nb) ? p.list[p.k0 + k] : 0u;
-                {
-                    idx = item_bit(segs, item);
-                    my_refills++;
-                    lb = p.lists + ((u64)(pos / 64) * p.emax * 64 + pos % 64);
-                    rb = p.lres + ((u64)(pos / 64) * p.emax * 64 + pos % 64);
-                    const u64 d = item_d(segs, item);
-                    const u64 si = isqrt_u64(d);
-                    const u64 P1 = ((si + 1) >> 1) * 2 - 1;
-                    const u64 Q1 = (d - P1 * P1) >> 1;
-                    const u32 S1 = 1u + (u32)((P1 >> 1) & 1);
-                    j = 1;
-                    my_steps += 1;
-                    if (Q1 == 2) {
-                        emit_flag(p.eis_words, idx, S1 % 3u == 0u);
-                        WindowState st = {0u, 0u, item, 0u};
-                        p.state[pos] = st;
-                    } else {
-                        sq = (float)si * 0.25f;
-                        sqc = sq * kQuotBias;
-                        P = (float)P1 * 0.25f;
-                        Q = (float)Q1 * 0.25f;
-                        Qp = 0.5f;
-                        S2 = 2u * S1;
-                        // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
-                        lb[0] = entry_of(0.5f, P);
-                        rb[0] = 0u;
-                        cnt = 1;
-                        j1e = ~0u;
-                        jlast = 0;
-                        const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
-                        emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
-                        window_insert(lb, rb, Q, P, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
-                        active = true;
-                    }
+                idx = item_bit(segs, item);
+                my_refills++;
+                lb = p.lists + (u64)pos * p.emax;
+                rb = p.lres + (u64)pos * p.emax;
+                const u64 d = item_d(segs, item);
+                double sd, P1, Q1;
+                u32 S1;
+                first_step(d, sd, P1, Q1, S1);
+                j = 1;
+                my_steps += 1;
+                if (Q1 == 2.0) {
+                    emit_flag(p.eis_words, idx, S1 % 3u == 0u);
+                    WindowState st = {0u, 0u, item, 0u};
+                    p.state[pos] = st;
+                } else {
+                    sq = (float)sd * 0.25f;
+                    sqc = sq * kQuotBias;
+                    P = (float)P1 * 0.25f;
+                    Q = (float)Q1 * 0.25f;
+                    Qp = 0.5f;
+                    S2 = 2u * S1;
+                    hit = kDpHit;
+                    // the ideal (1) = [1, (P_1 + sqrt d)/2], residue 0
+                    rg.key[0][lane] = entry_of(0.5f, P);
+                    rg.res[0][lane] = 0u;
+                    cnt = 1;
+                    j1e = ~0u;
+                    jlast = 0;
+                    const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
+                    emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
+                    window_insert(rg, lane, lb, rb, Q, P, hit, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
+                    live = true;
                 }
             }
         }
-        if (!__any(active)) break;
+        u64 lm = __builtin_amdgcn_ballot_w64(live);
+        if (lm == 0) break;
 
-        if (active) {
-            // Two steps per iteration; the loop leaves as soon as any lane
-            // reaches the half-period or the end of its window.  The window
-            // ends once an entry at least kExtraSteps past mu_1 is stored (or
-            // the list is full).  The window-end test runs on every exit
-            // from the loop, so no lane starts a pair with fewer than two
-            // free list entries.
-            u32 k = 0;
-            u64 mh = 0, ms = 0;
-            bool first_half = false;
-            float P1 = 0.f, Q1 = 0.f, acc = 0.f;
-            for (;;) {
-                float P2, Q2;
-                rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
-                mh = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-                window_insert(lb, rb, Q1, P1, S2 + k + 1, acc, j + 1, k, emain, cnt, j1e, jlast);
-                if (mh) {
-                    ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
-                         __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
-                    first_half = true;
-                    break;
+        // Two steps per iteration.  A lane that reaches the half period or
+        // the end of its window is finished at once and idles (its steps go
+        // on, but it appends nothing); the loop is left for a refill when
+        // `batch` lanes idle (when all idle once the queue is drained).  The
+        // window ends once an entry at least kExtraSteps past mu_1 is staged,
+        // or when the list is full; the test runs after every pair, so no
+        // lane starts a pair with fewer than two free entries.
+        const u32 keep = __any(npos != kNoItem) ? 64u - batch : 0u;
+        const u32 iters = (K + 1) / 2;
+        u32 it = 0;
+        bool stop = false;
+        float P1 = 0.f, Q1 = 0.f, acc = 0.f;
+        for (;;) {
+            float P2, Q2;
+            rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
+            const u64 mA = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
+            window_insert(rg, lane, lb, rb, Q1, P1, hit, S2 + 2 * it + 1, acc, j + 1, 2 * it, emain,
+                          cnt, j1e, jlast);
+            rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
+            const u64 mB = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
+            window_insert(rg, lane, lb, rb, Q2, P2, hit, S2 + 2 * it + 2, acc, j + 2, 2 * it, emain,
+                          cnt, j1e, jlast);
+            const u64 ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) | __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
+            const u64 ev = (mA | mB | ms) & lm;
+            if (ev) {
+                if ((ev >> lane) & 1ull) {
+                    const bool exA = (mA >> lane) & 1ull;
+                    const bool exB = !exA && ((mB >> lane) & 1ull);
+                    WindowState st = {0u, 0u, item, 0u};
+                    if (exA || exB) {
+                        // half-period symmetry: the unit is found without giant steps
+                        const u32 kx = 2 * it + (exA ? 1u : 2u);
+                        const float accx = exA ? fmaf(__builtin_amdgcn_fractf(P2), -4.f, acc) : acc;
+                        const float Pj = exA ? P1 : P2;
+                        const bool qrule = exA ? (Q1 == Q) : (Q2 == Q1);
+                        const u32 S = (S2 + kx + (u32)accx) >> 1;
+                        const u32 rj = __builtin_amdgcn_fractf(Pj) > 0.5f ? 2u : 1u;
+                        const u32 v = qrule ? (2u * S - rj) : (2u * (S - rj));
+                        emit_flag(p.eis_words, idx, v % 3u == 0u);
+                        my_steps += j + kx - 1;
+                    } else {
+                        // end of the window; its extension past mu_1 must be
+                        // short next to mu_1's own distance (see above)
+                        const u32 j1 = j1e - kExtraSteps;
+                        const u32 S2e = S2 + 2 * it + 2 + (u32)acc;
+                        const bool ok = j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2e < (1u << 24);
+                        if (ok) {
+                            if (cnt % kRing) ring_flush(rg, lane, lb, rb, cnt / kRing * kRing);
+                            st.emain = emain;
+                            st.count = cnt;
+                        } else {
+                            const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                            p.fb_list[f] = item;
+                        }
+                        my_steps += j + 2 * it + 1;
+                    }
+                    p.state[pos] = st;
+                    hit = -1.f;
+                    j1e = ~0u;
+                    cnt = 0;
                 }
-                rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
-                mh = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
-                window_insert(lb, rb, Q2, P2, S2 + k + 2, acc, j + 2, k, emain, cnt, j1e, jlast);
-                ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) |
-                     __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
-                Qp = Q1;
-                Q = Q2;
-                P = P2;
-                k += 2;
-                if ((mh | ms) || k >= K) break;
+                lm &= ~ev;
+                stop = (u32)__builtin_popcountll(lm) <= keep;
             }
-            if (first_half) {
-                Qp = Q;
-                Q = Q1;
-                P = P1;
-                k += 1;
-            }
+            Qp = Q1;
+            Q = Q2;
+            P = P2;
+            if (++it >= iters || stop) break;
+        }
+        live = (lm >> lane) & 1ull;
+        if (live) {
+            const u32 k = 2 * it;
             j += k;
-            my_steps += k;
             S2 += k + (u32)acc;
-            if ((mh >> lane) & 1ull) {
-                // half-period symmetry: the unit is found without giant steps
-                const u32 S = S2 >> 1;
-                const u32 rj = __builtin_amdgcn_fractf(P) > 0.5f ? 2u : 1u;
-                const u32 v = (Q == Qp) ? (2u * S - rj) : (2u * (S - rj));
-                emit_flag(p.eis_words, idx, v % 3u == 0u);
-                WindowState st = {0u, 0u, item, 0u};
-                p.state[pos] = st;
-                active = false;
-            } else if ((ms >> lane) & 1ull) {
-                // end of the window; its extension past mu_1 must be short
-                // next to mu_1's own distance (see above)
-                const u32 j1 = j1e - kExtraSteps;
-                const bool ok = j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2 < (1u << 24);
-                WindowState st = {emain, ok ? cnt : 0u, item, 0u};
-                p.state[pos] = st;
-                if (!ok) {
-                    const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                    p.fb_list[f] = item;
-                }
-                active = false;
-            } else if (j > p.max_steps) {
+            if (j > p.max_steps) {
                 WindowState st = {0u, 0u, item, 0u};
                 p.state[pos] = st;
                 const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
                 p.fb_list[f] = item;
-                active = false;
+                my_steps += j - 1;
+                hit = -1.f;
+                j1e = ~0u;
+                cnt = 0;
+                live = false;
             }
         }
     }
@@ -300,9 +354,9 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     __syncthreads();
     const u32 pos = w;
     if (valid) {
-        const unsigned long long *lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
+        const unsigned long long *lst = p.lists + (u64)pos * p.emax;
         for (u32 e = lane; e < cnt; e += 64) {
-            const unsigned long long ent = lst[(u64)e * 64];
+            const unsigned long long ent = lst[e];
             const u32 qb = (u32)(ent >> 32), pb = (u32)ent;
             const u32 h = dict_hash(qb, pb);
             const u32 val = (e + 1) | (h & 0xffff0000u);
@@ -348,7 +402,7 @@ __device__ __forceinline__ u32 dict_find(const u32 *tbl, const unsigned long lon
         if (v == 0u) break;
         if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
             const u32 e = (v & 0xffffu) - 1;
-            if (lst[(u64)e * 64] == key) return e;
+            if (lst[e] == key) return e;
         }
         slot = (slot + 1) & mask;
     }
@@ -356,7 +410,7 @@ __device__ __forceinline__ u32 dict_find(const u32 *tbl, const unsigned long lon
 }
 __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 {
-    __shared__ SegInfo segs[kMaxSegments];
+    __shared__ SegLds segs[kMaxSegments];
     load_segs(segs, p.segs, p.nseg);
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
@@ -391,9 +445,9 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     const WindowState st = p.state[pos];
                     // positions whose flag is out or that went plain are skipped
                     if (st.count == 0u) continue;
-                    lst = p.lists + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
-                    lrs = p.lres + (u64)(pos / 64) * p.emax * 64 + (pos % 64);
-                    const unsigned long long m1 = lst[(u64)(st.emain - 1) * 64];
+                    lst = p.lists + (u64)pos * p.emax;
+                    lrs = p.lres + (u64)pos * p.emax;
+                    const unsigned long long m1 = lst[st.emain - 1];
                     item = st.item;
                     idx = item_bit(segs, item);
                     const u64 d = item_d(segs, item);
@@ -405,7 +459,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     L = (double)isqrt_u64(s64);
                     m1Q = 4.0 * (double)__uint_as_float((u32)(m1 >> 32));
                     m1P = 4.0 * (double)__uint_as_float((u32)m1);
-                    m1S = (lrs[(u64)(st.emain - 1) * 64] >> 1) % 3u;
+                    m1S = (lrs[st.emain - 1] >> 1) % 3u;
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;
@@ -477,7 +531,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     // it was a true hit, a later one is at eps or eps^2,
                     // whose residues are both 0 or both not
                     if (e != kNoEntry && ng > 1) {
-                        const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
+                        const u32 St = (lrs[e] >> 1) % 3u;
                         flag = ((Sw + 3u - St) % 3u) == 0u;
                         done = true;
                     } else {
@@ -490,7 +544,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                         rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
                         e = dict_find(tbl, lst, mask, p.tsize, qb, __float_as_uint(Pn));
                         if (e != kNoEntry) {
-                            const u32 St = (lrs[(u64)e * 64] >> 1) % 3u;
+                            const u32 St = (lrs[e] >> 1) % 3u;
                             flag = ((Sw + St) % 3u) == 0u;
                             done = true;
                         }

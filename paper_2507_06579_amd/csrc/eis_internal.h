@@ -61,13 +61,22 @@ struct PassCounters {
     u64 pad3[4];
 };
 
-__device__ __forceinline__ u64 item_d(const SegInfo *segs, u32 item)
+// The fields of a segment that the walk kernels need, kept in LDS.
+struct SegLds {
+    u64 d0;
+    u32 word_off;
+    float wscale;
+};
+
+template <typename Seg>
+__device__ __forceinline__ u64 item_d(const Seg *segs, u32 item)
 {
     return segs[item >> kItemShift].d0 + 8ull * (item & kItemMask);
 }
 
 // bit of the pass bitmaps that belongs to an item
-__device__ __forceinline__ u32 item_bit(const SegInfo *segs, u32 item)
+template <typename Seg>
+__device__ __forceinline__ u32 item_bit(const Seg *segs, u32 item)
 {
     return segs[item >> kItemShift].word_off * 32u + (item & kItemMask);
 }
@@ -102,12 +111,12 @@ struct InfraParams {
     u32 *fb_list;               // items handed to the plain walk
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position
-    unsigned long long *lists;  // window lists, tile-interleaved: entry e of batch
-                                // position k at ((k / 64) * emax + e) * 64 + k % 64;
-                                // an entry is the ideal's (Q/4, P/4) as fp32 bits
+    unsigned long long *lists;  // window lists: entry e of batch position k at
+                                // k * emax + e; an entry is the ideal's
+                                // (Q/4, P/4) as fp32 bits
     u32 *lres;                  // 2 S (twice the residue sum) of each entry, same layout
     u32 *tables;                // hash tables, tsize slots per batch position
-    u32 emax;                   // list capacity per d
+    u32 emax;                   // list capacity per d (a multiple of 8)
     u32 tsize;                  // table slots per d (power of two)
     u32 max_steps;              // per-d budget of reduction steps (window)
     u32 max_giants;             // per-d budget of giant steps

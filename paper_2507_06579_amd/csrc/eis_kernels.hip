@@ -242,7 +242,7 @@ __device__ __forceinline__ u32 exit_batch(float s)
 
 __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
 {
-    __shared__ SegInfo segs[kMaxSegments];
+    __shared__ SegLds segs[kMaxSegments];
     load_segs(segs, p.segs, p.nseg);
     const u32 n = p.ctr->list_len;
     // inner-loop length between budget checks; a walk that has not ended

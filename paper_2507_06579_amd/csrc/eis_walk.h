@@ -123,9 +123,13 @@ __device__ __forceinline__ void wave_take(u32 *head, u32 n, bool want, u32 &item
 // Iterations of the inner loop between two checks of the step budget.
 // The pass's segment table, copied into LDS by every block of a walk kernel
 // (decoding a work item then costs an LDS read, not a dependent global one).
-__device__ __forceinline__ void load_segs(SegInfo *dst, const SegInfo *src, u32 nseg)
+__device__ __forceinline__ void load_segs(SegLds *dst, const SegInfo *src, u32 nseg)
 {
-    for (u32 i = threadIdx.x; i < nseg; i += blockDim.x) dst[i] = src[i];
+    for (u32 i = threadIdx.x; i < nseg; i += blockDim.x) {
+        dst[i].d0 = src[i].d0;
+        dst[i].word_off = src[i].word_off;
+        dst[i].wscale = src[i].wscale;
+    }
     __syncthreads();
 }
 
