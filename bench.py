@@ -24,20 +24,24 @@ if ROOT not in sys.path:
 METRIC = "discriminants classified/sec and baby-steps/sec at d≈1e11; p99 query latency"
 TABLE1_LARGE = 3345503
 
-# VALU issue rate of MI355X in 32-bit lane-instructions per second: 256 CUs
-# x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction takes 4 cycles).
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# wave64 instruction per SIMD every 4 cycles = 39.3 T lane-slots/s.  (The
+# published fp32 vector rate, 157.3 TFLOP/s, counts packed two-wide FMAs.)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# VALU instructions per rho step of the walk kernels, counted in the gfx950
-# code of the built loops (two steps per iteration, averaged).  The
-# reciprocal estimate issues on the transcendental unit beside them and is
-# not counted.  Plain walk: the biased quotient (fma, mul, floor), the
-# overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma), two
-# exit tests, and a register copy every other step.  Window walk: the same
-# step, the distinguished-ideal test (mul, fract, cmp), the list append
-# (addresses, count, residue sum, mu_1 bookkeeping: 10), which runs for the
-# wave whenever any of its 64 lanes appends, i.e. at nearly every step, and
-# the window-end tests once per two steps.
-VALU_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0, "walk_window": 30.0}
+# VALU issue slots per rho step of the walk kernels, counted in the gfx950
+# code of the built loops (two steps per iteration, averaged) with the issue
+# rules measured on the device (SQ_ACTIVE_INST_VALU / _VALU2 counters):
+# v_rcp_f32 takes two slots, and v_fract_f32 / v_floor_f32 issue beside
+# another VALU instruction of the same quad-cycle (no slot of their own).
+# Plain walk: 11 VALU + rcp: the biased quotient (fma, mul, floor), the
+# overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma) and
+# two exit tests -> 11 + 1 - 2 = 10 slots.  Window walk: the same step plus
+# the distinguished-ideal test (mul, fract, cmp): 12 slots, the list append
+# (15 VALU for the LDS staging, count, residue sum and mu_1 bookkeeping),
+# which runs for the wave whenever any of its 64 lanes appends, i.e. at
+# nearly every step (1 - (15/16)^64 = 0.98), and the window-end tests once
+# per two steps: 28 slots.
+VALU_SLOTS_PER_STEP = {"walk_plain": 10.0, "walk_handoff": 10.0, "walk_window": 28.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the
@@ -113,6 +117,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one elementwise copy of this many MiB before the workload "
                          "(the reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--window-scale", type=float, default=0.0,
+                    help="giant-step window scale (0: tuned or default)")
     ap.add_argument("--no-tune", action="store_true",
                     help="auto method without running the autotuner first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,7 +144,8 @@ def main():
     sq = torch.zeros(nb, dtype=torch.uint8, device=dev)
     eb = torch.zeros(nb, dtype=torch.uint8, device=dev)
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
-    ctx = eis.Context(device=0, method=method, flags=eis.EIS_FLAG_KERNEL_TIMES)
+    ctx = eis.Context(device=0, method=method, flags=eis.EIS_FLAG_KERNEL_TIMES,
+                      window_scale=args.window_scale)
     if method == eis.Method.AUTO and not args.no_tune:
         t = time.perf_counter()
         ctx.eis_tune()
@@ -196,17 +203,17 @@ def main():
                              "launches_per_step": kl[k] / args.steps,
                              "rho_steps_per_step": ks[k] // args.steps}
     # dominant kernel among the walks with an instruction count per step
-    dom = max(VALU_PER_STEP, key=lambda name: kms[eis.KERNELS.index(name)])
+    dom = max(VALU_SLOTS_PER_STEP, key=lambda name: kms[eis.KERNELS.index(name)])
     kd = eis.KERNELS.index(dom)
     avg_launch_s = kms[kd] / kl[kd] / 1e3
     units_per_launch = ks[kd] / kl[kd]
-    achieved = VALU_PER_STEP[dom] * units_per_launch / avg_launch_s
+    achieved = VALU_SLOTS_PER_STEP[dom] * units_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-instr/s",
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-slots/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4),
                 "traffic": None,
                 "kernel": "k_walk_baby" if dom != "walk_window" else "k_walk_window",
-                "ops_per_unit": VALU_PER_STEP[dom], "unit_of_work": "rho step",
+                "ops_per_unit": VALU_SLOTS_PER_STEP[dom], "unit_of_work": "rho step",
                 "units_per_launch": int(units_per_launch),
                 "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                 "share_of_step_time": round(kms[kd] / (1e3 * elapsed), 3)}

@@ -7,10 +7,15 @@
 // exact while the exact result stays below 2^53 in magnitude.  Every product
 // and every multi-term sum is checked against 2^52 (so that sums of two
 // checked values are exact too), and every division the algorithms declare
-// exact is checked for a zero remainder.  Any failed check sets `bad`; the
-// caller then discards the giant-step result for that d and classifies it
-// with the plain reduction walk instead.  The reduction after the
-// composition uses the division-free form of rho, so it never needs P^2.
+// exact is checked for a zero remainder.  Any failed check makes the
+// composition `bad`; the caller then discards the giant-step result for
+// that d and classifies it with the plain reduction walk instead.  The
+// checks accumulate in vector registers (the largest magnitude seen, the
+// sum of the remainders' magnitudes) and are tested once at the end, which
+// keeps the scalar unit free.  The extended and partial Euclid loops work
+// on numbers below 2^21 (ideal norms and their cofactors for d < 10^12)
+// and run in fp32, exact there.  The reduction after the composition uses
+// the division-free form of rho, so it never needs P^2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +29,15 @@ typedef long long i64;
 
 constexpr double kExactLimit = 4503599627370496.0;  // 2^52
 
-__device__ __forceinline__ void chk(double x, bool &bad) { bad |= !(fabs(x) < kExactLimit); }
+// Accumulated checks of one composition.
+struct Chk {
+    double mx = 0.0;   // largest magnitude checked against 2^52
+    double rs = 0.0;   // sum of the magnitudes of the exact divisions' remainders
+    bool fail = false; // explicit failures
+    __device__ __forceinline__ bool bad() const { return fail || !(mx < kExactLimit) || !(rs == 0.0); }
+};
+
+__device__ __forceinline__ void chk(double x, Chk &c) { c.mx = fmax(c.mx, fabs(x)); }
 
 // 1/b to nearly full fp64 precision: hardware estimate + one Newton step.
 __device__ __forceinline__ double rcp_nr(double b)
@@ -51,36 +64,53 @@ __device__ __forceinline__ double nn_mod(double a, double m)
 }
 
 // a / b where the quotient is an exact integer of magnitude < 2^50; the
-// remainder is checked.
-__device__ __forceinline__ double ex_div(double a, double b, bool &bad)
+// remainder goes to the checks.
+__device__ __forceinline__ double ex_div(double a, double b, Chk &c)
 {
     double q = rint(a * rcp_nr(b));
-    bad |= (fma(-q, b, a) != 0.0);
+    c.rs += fabs(fma(-q, b, a));
     return q;
 }
 
-// Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for |a|, |b| < 2^52.
-__device__ __forceinline__ void xgcd(double a, double b, double &x, double &y, double &g)
+// q = floor(a / b) and r = a - q b for integer-valued fp32 0 <= a < 2^22,
+// 0 < b < 2^22: the estimate a * rcp(b) is within 3 ulp of a / b < 2^22, so
+// within 0.75 of it, and one correction of q either way makes it exact.
+__device__ __forceinline__ float fl_div32(float a, float b, float &r)
 {
-    const double sa = a < 0.0 ? -1.0 : 1.0, sb = b < 0.0 ? -1.0 : 1.0;
-    a = fabs(a);
-    b = fabs(b);
-    double x0 = 1.0, x1 = 0.0, y0 = 0.0, y1 = 1.0;
-    while (b != 0.0) {
-        const double q = fl_div(a, b);
-        const double r = fma(-q, b, a);
+    float q = floorf(a * __builtin_amdgcn_rcpf(b));
+    r = fmaf(-q, b, a);
+    if (r < 0.f) {
+        q -= 1.f;
+        r += b;
+    } else if (r >= b) {
+        q += 1.f;
+        r -= b;
+    }
+    return q;
+}
+
+// Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for integers
+// |a|, |b| < 2^21 (then |x|, |y| < 2^21 too): exact in fp32.
+__device__ __forceinline__ void xgcd(double ad, double bd, double &x, double &y, double &g)
+{
+    const float sa = ad < 0.0 ? -1.f : 1.f, sb = bd < 0.0 ? -1.f : 1.f;
+    float a = (float)fabs(ad), b = (float)fabs(bd);
+    float x0 = 1.f, x1 = 0.f, y0 = 0.f, y1 = 1.f;
+    while (b != 0.f) {
+        float r;
+        const float q = fl_div32(a, b, r);
         a = b;
         b = r;
-        double t = fma(-q, x1, x0);
+        float t = fmaf(-q, x1, x0);
         x0 = x1;
         x1 = t;
-        t = fma(-q, y1, y0);
+        t = fmaf(-q, y1, y0);
         y0 = y1;
         y1 = t;
     }
-    g = a;
-    x = x0 * sa;
-    y = y0 * sb;
+    g = (double)a;
+    x = (double)(x0 * sa);
+    y = (double)(y0 * sb);
 }
 
 struct Form {
@@ -94,32 +124,36 @@ struct Gamma {
 
 // Partial Euclid shared by NUCOMP and NUDUPL: run while |b_y| > L and b_x != 0
 // (both stay non-negative), then flip the signs of b_y and y when the number
-// of steps z is odd.
-__device__ __forceinline__ void partial_euclid(double &bx, double &by, double &x, double &y,
+// of steps z is odd.  0 <= b_x < b_y < 2^21, so the loop runs in fp32.
+__device__ __forceinline__ void partial_euclid(double &bxd, double &byd, double &x, double &y,
                                                int &z, double L)
 {
-    x = 1.0;
-    y = 0.0;
+    float bx = (float)bxd, by = (float)byd, xf = 1.f, yf = 0.f;
+    const float Lf = (float)L;
     z = 0;
-    while (fabs(by) > L && bx != 0.0) {
-        const double q = fl_div(by, bx);
-        const double t = fma(-q, bx, by);
+    while (by > Lf && bx != 0.f) {
+        float t;
+        const float q = fl_div32(by, bx, t);
         by = bx;
         bx = t;
-        const double t2 = fma(-q, x, y);
-        y = x;
-        x = t2;
+        const float t2 = fmaf(-q, xf, yf);
+        yf = xf;
+        xf = t2;
         z++;
     }
     if (z & 1) {
         by = -by;
-        y = -y;
+        yf = -yf;
     }
+    bxd = (double)bx;
+    byd = (double)by;
+    x = (double)xf;
+    y = (double)yf;
 }
 
 // Algorithm NUCOMP: phi3 = (1/gamma) phi1 phi2, partially reduced with bound L.
 __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gamma &g,
-                                       bool &bad)
+                                       Chk &bad)
 {
     if (f1.w < f2.w) {
         const Form t = f1;
@@ -221,7 +255,7 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
 }
 
 // Algorithm NUDUPL: phi3 = (1/gamma) phi^2, partially reduced with bound L.
-__device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, bool &bad)
+__device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk &bad)
 {
     double x0, y0, G;
     xgcd(f.u, f.v, x0, y0, G);  // x0 u + y0 v = G
@@ -292,13 +326,13 @@ __device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, boo
 // mixed parity is odd (log 0).  The power of 2 stripped must equal that of C
 // (gamma is a 2-unit), else `bad`.  Only A, B mod 2^64 matter, and |A|, |B|
 // < 2^52 here, so the int64 images are exact.
-__device__ __forceinline__ u32 gamma_log(const Gamma &g, bool &bad)
+__device__ __forceinline__ u32 gamma_log(const Gamma &g, Chk &bad)
 {
     unsigned long long A = (unsigned long long)(i64)g.A;
     unsigned long long B = (unsigned long long)(i64)g.B;
     unsigned long long C = (unsigned long long)(i64)fabs(g.C);
     if (C == 0 || (A | B) == 0) {
-        bad = true;
+        bad.fail = true;
         return 0;
     }
     const int vA = __builtin_ctzll(A | B);  // common power of 2
@@ -311,7 +345,7 @@ __device__ __forceinline__ u32 gamma_log(const Gamma &g, bool &bad)
         lg = (((A - B) & 3) == 0) ? 1u : 2u;
     }
     const int vC = __builtin_ctzll(C);
-    bad |= (v != vC);
+    bad.fail |= (v != vC);
     return lg;
 }
 
@@ -321,7 +355,7 @@ __device__ __forceinline__ u32 gamma_log(const Gamma &g, bool &bad)
 // ideals: u_k < 2^21 and 0 < v_k < 2^21 for d < 2^40.
 __device__ __forceinline__ void nucomp_choose(double u1, double v1, double u2, double v2,
                                               double d, double L, Form &f3, Gamma &g,
-                                              bool &bad)
+                                              Chk &bad)
 {
     u1 = fabs(u1);
     u2 = fabs(u2);
@@ -337,7 +371,7 @@ __device__ __forceinline__ void nucomp_choose(double u1, double v1, double u2, d
         Form b = {0.5 * u2, -v2, w2};
         nucomp(a, b, L, f3, g, bad);
     }
-    bad |= (f3.u == 0.0);
+    bad.fail |= (f3.u == 0.0);
 }
 
 // Reduction of the composed ideal.  The ideal of the form (u3, v3, w3) is
@@ -354,7 +388,7 @@ __device__ __forceinline__ void nucomp_choose(double u1, double v1, double u2, d
 constexpr int kMaxReduce = 128;
 
 __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, double &Q,
-                                           double &P, double &Qp, bool &bad)
+                                           double &P, double &Qp, Chk &bad)
 {
     Q = fabs(2.0 * f.u);
     P = -f.v;
@@ -363,7 +397,7 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
     int it = 0;
     while (!(Q > 0.0 && P > 0.0 && P <= s && s - P < Q && Q <= s + P)) {
         if (++it > kMaxReduce || Q == 0.0) {
-            bad = true;
+            bad.fail = true;
             break;
         }
         const double q = (Q > 0.0) ? fl_div(P + s, Q) : fl_div(-P - s - 1.0, -Q);
@@ -374,13 +408,13 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
         chk(t, bad);
         const double Qn = Qp + t;
         chk(Qn, bad);
-        if (bad) break;
+        if (!(bad.mx < kExactLimit)) break;
         S += 1u + (u32)(((long long)Pn >> 1) & 1);
         Qp = Q;
         Q = Qn;
         P = Pn;
     }
-    bad |= (fma(Q, Qp, P * P) != d);
+    bad.fail |= (fma(Q, Qp, P * P) != d);
     return S;
 }
 

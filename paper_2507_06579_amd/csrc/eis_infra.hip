@@ -388,25 +388,41 @@ hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream)
 // ---------------------------------------------------------------------------
 constexpr u32 kNoEntry = ~0u;
 
-// Index of the window entry with key (qb, pb) in a d's table (open
-// addressing, linear probing), or kNoEntry.  A slot's fingerprint match is
-// confirmed against the full key in the list.
-__device__ __forceinline__ u32 dict_find(const u32 *tbl, const unsigned long long *lst, u32 mask,
-                                         u32 tsize, u32 qb, u32 pb)
+// Indices of the window entries with keys (qb, pa) and (qb, pc) in a d's
+// table (open addressing, linear probing), or kNoEntry.  The two probe
+// chains advance together, so that their loads overlap; a slot's
+// fingerprint match is confirmed against the full key in the list.
+__device__ __forceinline__ void dict_find2(const u32 *tbl, const unsigned long long *lst, u32 mask,
+                                           u32 tsize, u32 qb, u32 pa, u32 pc, u32 &ea, u32 &ec)
 {
-    const unsigned long long key = ((unsigned long long)qb << 32) | pb;
-    const u32 h = dict_hash(qb, pb);
-    u32 slot = h & mask;
-    for (u32 probe = 0; probe < tsize; probe++) {
-        const u32 v = tbl[slot];
-        if (v == 0u) break;
-        if ((v & 0xffff0000u) == (h & 0xffff0000u)) {
-            const u32 e = (v & 0xffffu) - 1;
-            if (lst[e] == key) return e;
+    const unsigned long long ka = ((unsigned long long)qb << 32) | pa;
+    const unsigned long long kc = ((unsigned long long)qb << 32) | pc;
+    const u32 ha = dict_hash(qb, pa), hc = dict_hash(qb, pc);
+    u32 sa = ha & mask, sc = hc & mask;
+    bool da = false, dc = false;
+    ea = ec = kNoEntry;
+    for (u32 probe = 0; probe < tsize && !(da && dc); probe++) {
+        const u32 va = da ? 0u : tbl[sa];
+        const u32 vc = dc ? 0u : tbl[sc];
+        if (!da) {
+            if (va == 0u) {
+                da = true;
+            } else if ((va & 0xffff0000u) == (ha & 0xffff0000u) && lst[(va & 0xffffu) - 1] == ka) {
+                ea = (va & 0xffffu) - 1;
+                da = true;
+            }
+            sa = (sa + 1) & mask;
         }
-        slot = (slot + 1) & mask;
+        if (!dc) {
+            if (vc == 0u) {
+                dc = true;
+            } else if ((vc & 0xffff0000u) == (hc & 0xffff0000u) && lst[(vc & 0xffffu) - 1] == kc) {
+                ec = (vc & 0xffffu) - 1;
+                dc = true;
+            }
+            sc = (sc + 1) & mask;
+        }
     }
-    return kNoEntry;
 }
 __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 {
@@ -428,35 +444,46 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     u32 Sw = 0, w = 0;
     bool walking = false;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
-    bool active = false, exhausted = false;
+    bool active = false;
     u64 my_giants = 0, my_steps = 0;
+    // the lane's next batch position and its window record, loaded one
+    // refill ahead so that the load completes during the giant walk
+    u32 npos = n;
+    wave_take(p.giant_next, n, true, npos, cbase, cend);
+    WindowState nst = {0u, 0u, 0u, 0u};
+    if (npos < n) nst = p.state[npos];
 
     for (;;) {
         for (;;) {
-            bool want = !active && !exhausted;
+            const bool want = !active && npos < n;
             if (!__any(want)) break;
             u32 g = n;
             wave_take(p.giant_next, n, want, g, cbase, cend);
             if (want) {
-                if (g >= n) {
-                    exhausted = true;
-                } else {
-                    const u32 pos = g;
-                    const WindowState st = p.state[pos];
-                    // positions whose flag is out or that went plain are skipped
-                    if (st.count == 0u) continue;
+                const u32 pos = npos;
+                const WindowState st = nst;
+                npos = g;
+                if (g < n) nst = p.state[g];
+                // positions whose flag is out or that went plain are skipped
+                if (st.count != 0u) {
                     lst = p.lists + (u64)pos * p.emax;
                     lrs = p.lres + (u64)pos * p.emax;
                     const unsigned long long m1 = lst[st.emain - 1];
                     item = st.item;
                     idx = item_bit(segs, item);
                     const u64 d = item_d(segs, item);
-                    const u64 s64 = isqrt_u64(d);
+                    double s64, P1, Q1;
+                    u32 S1;
+                    first_step(d, s64, P1, Q1, S1);
                     dd = (double)d;
-                    sd = (double)s64;
+                    sd = s64;
                     sq = (float)s64 * 0.25f;
                     sqc = sq * kQuotBias;
-                    L = (double)isqrt_u64(s64);
+                    L = floor(sqrt(s64));  // isqrt(s), corrected exactly
+                    if ((L + 1.0) * (L + 1.0) <= s64)
+                        L += 1.0;
+                    else if (L * L > s64)
+                        L -= 1.0;
                     m1Q = 4.0 * (double)__uint_as_float((u32)(m1 >> 32));
                     m1P = 4.0 * (double)__uint_as_float((u32)m1);
                     m1S = (lrs[st.emain - 1] >> 1) % 3u;
@@ -481,11 +508,13 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             if (!walking) {
                 Form f3;
                 Gamma gm;
-                nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, bad);
-                const u32 lg = gamma_log(gm, bad);
+                Chk ck;
+                nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, ck);
+                const u32 lg = gamma_log(gm, ck);
                 double Qk, Pk, Qpk;
-                const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, bad);
+                const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, ck);
                 const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
+                bad = ck.bad();
                 if (!bad) {
                     if (ng == 0) {
                         // the first composition squares mu_1; its square is
@@ -522,32 +551,29 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 my_steps += u;
                 if (is_dp(Qw)) {
                     walking = false;
-                    // direct lookup: the ideal itself is a window ideal,
-                    // at one period past it
-                    const u32 qb = __float_as_uint(Qw);
-                    u32 e = dict_find(tbl, lst, mask, p.tsize, qb, __float_as_uint(Pw));
+                    // Two lookups at once: the ideal (Q_m, P_m) itself -- a hit
+                    // means one period past a window ideal -- and its
+                    // conjugate (Q_m, P_{m+1}) -- a hit means as many ideals
+                    // short of a period as the window ideal lies past (1)
+                    // (conjugation reverses the cycle and acts as
+                    // log -> -log, so log eps = S_m + S_i).
+                    float Pn, Qn, acc1 = 0.f;
+                    rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
+                    u32 ed, ec;
+                    dict_find2(tbl, lst, mask, p.tsize, __float_as_uint(Qw), __float_as_uint(Pw),
+                               __float_as_uint(Pn), ed, ec);
                     // a direct hit at the first lookup (mu_1^2) is skipped: it
                     // may lie inside the window (a "unit" of distance 0); if
                     // it was a true hit, a later one is at eps or eps^2,
                     // whose residues are both 0 or both not
-                    if (e != kNoEntry && ng > 1) {
-                        const u32 St = (lrs[e] >> 1) % 3u;
+                    if (ed != kNoEntry && ng > 1) {
+                        const u32 St = (lrs[ed] >> 1) % 3u;
                         flag = ((Sw + 3u - St) % 3u) == 0u;
                         done = true;
-                    } else {
-                        // conjugate lookup: the conjugate of the ideal
-                        // (Q_m, P_m) of the cycle is (Q_m, P_{m+1}); if that is
-                        // window ideal i, this ideal lies i ideals short of a
-                        // period, and log eps = S_m + S_i (conjugation acts as
-                        // log -> -log)
-                        float Pn, Qn, acc1 = 0.f;
-                        rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
-                        e = dict_find(tbl, lst, mask, p.tsize, qb, __float_as_uint(Pn));
-                        if (e != kNoEntry) {
-                            const u32 St = (lrs[e] >> 1) % 3u;
-                            flag = ((Sw + St) % 3u) == 0u;
-                            done = true;
-                        }
+                    } else if (ec != kNoEntry) {
+                        const u32 St = (lrs[ec] >> 1) % 3u;
+                        flag = ((Sw + St) % 3u) == 0u;
+                        done = true;
                     }
                 } else if (w >= kWalkLimit) {
                     bad = true;

@@ -6,14 +6,6 @@
 
 namespace eis {
 
-__device__ __forceinline__ u64 isqrt_u64(u64 d)
-{
-    u64 s = (u64)sqrt((double)d);
-    while (s * s > d) s--;
-    while ((s + 1) * (s + 1) <= d) s++;
-    return s;
-}
-
 // The first reduction step of a walk, from (P_0, Q_0) = (1, 2):
 // s = isqrt(d), P_1 = the largest odd number <= s, Q_1 = (d - P_1^2)/2, and
 // the residue r(P_1).  In fp64: for d < 10^12 every value is an integer below
