@@ -1,0 +1,165 @@
+"""Paper-scale sweep: pi_D(x) and pi_E(x) for x up to 10^11 (Section 4).
+
+The range [0, X) is cut into segments whose ends include every power of ten;
+segments go to the GPU through eis_count_batch a few at a time, and after
+every batch the finished segments are written to a JSON checkpoint, so that
+an interrupted sweep resumes where it stopped.  From the segment counts the
+sweep reports
+
+  * pi_D(10^k) and pi_E(10^k) for every power of ten up to X;
+  * the coefficient c of the fitted law pi_E(x) ~ x / (3 pi^2) + c x^(5/6)
+    (the paper reports c = -0.024 from its own sweep to 10^11), by least
+    squares over the cumulative counts at every segment end above 10^6;
+  * per segment, the share P(d in E | d in D) next to the paper's
+    1/3 - 0.201 / d^(1/6), averaged over the segment.
+
+All counting runs in libeis.so; this module only plans, checkpoints and
+summarises.
+
+  python -m paper_2507_06579_amd.sweep --max 1e11 --checkpoint sweep.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+PAPER_C56 = -0.024       # Section 4, the fitted coefficient of x^(5/6)
+PAPER_DENSITY_B = 0.201  # Section 4, P(E | D) ~ 1/3 - b / d^(1/6)
+
+
+def segments(xmax: int, width: int):
+    """Half-open segments [a, b) covering [0, xmax): powers of ten up to
+    `width` are segment ends, then steps of `width` (also hitting every
+    power of ten above it)."""
+    ends = []
+    p = 10
+    while p < min(width, xmax):
+        ends.append(p)
+        p *= 10
+    x = width
+    while x < xmax:
+        ends.append(x)
+        x += width
+    ends.append(xmax)
+    out, a = [], 0
+    for b in sorted(set(ends)):
+        if b > a:
+            out.append((a, b))
+            a = b
+    return out
+
+
+def load_checkpoint(path: str, xmax: int, width: int):
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("max") != xmax or doc.get("width") != width:
+        raise SystemExit(f"{path} belongs to another sweep (max {doc.get('max')}, "
+                         f"width {doc.get('width')})")
+    return {(int(s["a"]), int(s["b"])): (int(s["n_sqfree"]), int(s["n_eis"]))
+            for s in doc["segments"]}
+
+
+def save_checkpoint(path: str, xmax: int, width: int, done: dict):
+    if not path:
+        return
+    doc = {"max": xmax, "width": width,
+           "segments": [{"a": a, "b": b, "n_sqfree": s, "n_eis": e}
+                        for (a, b), (s, e) in sorted(done.items())]}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(doc, f)
+    os.replace(tmp, path)
+
+
+def mean_inv_sixth_root(a: int, b: int) -> float:
+    """Mean of d^(-1/6) over [max(a, 5), b) (for the density law)."""
+    lo = max(a, 5)
+    if b <= lo:
+        return 0.0
+    return (1.2 * (b ** (5 / 6) - lo ** (5 / 6))) / (b - lo)
+
+
+def fit_c56(points):
+    """Least-squares c in pi_E(x) - x/(3 pi^2) = c x^(5/6) over (x, pi_E)."""
+    num = den = 0.0
+    for x, pe in points:
+        t = x ** (5 / 6)
+        num += (pe - x / (3 * math.pi ** 2)) * t
+        den += t * t
+    return num / den if den else float("nan")
+
+
+def summarise(done: dict, xmax: int):
+    segs = sorted(done.items())
+    cum_s = cum_e = 0
+    powers, cumulative, density = [], [], []
+    for (a, b), (s, e) in segs:
+        cum_s += s
+        cum_e += e
+        cumulative.append((b, cum_s, cum_e))
+        if b == 10 ** round(math.log10(b)):
+            powers.append({"x": b, "pi_D": cum_s, "pi_E": cum_e,
+                           "pi_D_over_x_pi2": round(cum_s * math.pi ** 2 / b, 6),
+                           "c56_at_x": round((cum_e - b / (3 * math.pi ** 2)) / b ** (5 / 6), 5)})
+        if s:
+            density.append({"a": a, "b": b, "share": round(e / s, 6),
+                            "paper_law": round(1 / 3 - PAPER_DENSITY_B * mean_inv_sixth_root(a, b), 6)})
+    fit_pts = [(x, pe) for x, _, pe in cumulative if x >= 10 ** 6]
+    return {"max": xmax, "pi_D": cum_s, "pi_E": cum_e, "powers_of_ten": powers,
+            "c56_fit": round(fit_c56(fit_pts), 5), "c56_paper": PAPER_C56,
+            "density": density}
+
+
+def run(xmax: int, width: int, checkpoint: str, per_call: int = 8, ctx=None, log=print):
+    from . import _lib as eis
+    done = load_checkpoint(checkpoint, xmax, width)
+    todo = [sg for sg in segments(xmax, width) if sg not in done]
+    log(f"[sweep] {len(done)} segments done, {len(todo)} to go")
+    own = ctx is None
+    if own:
+        ctx = eis.Context()
+    t0 = time.perf_counter()
+    try:
+        for i in range(0, len(todo), per_call):
+            part = todo[i:i + per_call]
+            s, e = ctx.eis_count_batch([a for a, _ in part], [b for _, b in part])
+            for sg, x, y in zip(part, s, e):
+                done[sg] = (int(x), int(y))
+            save_checkpoint(checkpoint, xmax, width, done)
+            log(f"[sweep] up to {part[-1][1]:.3e}: {len(done)} segments, "
+                f"{time.perf_counter() - t0:.1f} s")
+    finally:
+        if own:
+            ctx.close()
+    out = summarise(done, xmax)
+    out["seconds"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--max", type=float, default=1e11)
+    ap.add_argument("--width", type=float, default=1e9, help="segment width above 10^9")
+    ap.add_argument("--checkpoint", default="", help="JSON checkpoint (resume)")
+    ap.add_argument("--out", default="", help="write the summary here (JSON)")
+    ap.add_argument("--per-call", type=int, default=8, help="segments per eis_count_batch")
+    args = ap.parse_args(argv)
+    xmax, width = int(args.max), int(args.width)
+    res = run(xmax, width, args.checkpoint, args.per_call,
+              log=lambda m: print(m, file=sys.stderr, flush=True))
+    text = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    brief = {k: v for k, v in res.items() if k != "density"}
+    print(json.dumps(brief), flush=True)
+
+
+if __name__ == "__main__":
+    main()

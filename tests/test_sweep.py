@@ -1,0 +1,54 @@
+"""Host logic of the paper-scale sweep (no GPU): segment plan, checkpoint,
+fit and density summaries."""
+import json
+import math
+
+import pytest
+
+from paper_2507_06579_amd import sweep
+
+
+def test_segments_cover_and_hit_powers_of_ten():
+    for xmax, width in [(10**11, 10**9), (10**8, 10**9), (3 * 10**9 + 7, 10**9)]:
+        segs = sweep.segments(xmax, width)
+        assert segs[0][0] == 0 and segs[-1][1] == xmax
+        assert all(a < b for a, b in segs)
+        assert all(segs[i][1] == segs[i + 1][0] for i in range(len(segs) - 1))
+        ends = {b for _, b in segs}
+        p = 10
+        while p <= xmax:
+            assert p in ends
+            p *= 10
+        assert max(b - a for a, b in segs) <= width
+
+
+def test_fit_recovers_a_planted_coefficient():
+    pts = [(x, x / (3 * math.pi ** 2) - 0.031 * x ** (5 / 6)) for x in (10**6, 10**8, 10**10, 10**11)]
+    assert sweep.fit_c56(pts) == pytest.approx(-0.031, rel=1e-12)
+
+
+def test_mean_inv_sixth_root():
+    a, b = 10**6, 10**9
+    n = 200000
+    h = (b - a) / n
+    approx = sum((a + (i + 0.5) * h) ** (-1 / 6) for i in range(n)) / n
+    assert sweep.mean_inv_sixth_root(a, b) == pytest.approx(approx, rel=1e-6)
+
+
+def test_checkpoint_round_trip_and_mismatch(tmp_path):
+    p = str(tmp_path / "cp.json")
+    done = {(0, 10): (1, 0), (10, 100): (10, 3)}
+    sweep.save_checkpoint(p, 100, 10**9, done)
+    assert sweep.load_checkpoint(p, 100, 10**9) == done
+    with pytest.raises(SystemExit):
+        sweep.load_checkpoint(p, 1000, 10**9)
+    assert json.load(open(p))["segments"][1]["n_eis"] == 3
+
+
+def test_summary_of_mock_counts():
+    done = {(0, 10): (1, 0), (10, 100): (10, 3), (100, 1000): (100, 30)}
+    out = sweep.summarise(done, 1000)
+    assert out["pi_D"] == 111 and out["pi_E"] == 33
+    assert [p["x"] for p in out["powers_of_ten"]] == [10, 100, 1000]
+    assert out["powers_of_ten"][-1]["pi_E"] == 33
+    assert out["density"][2]["share"] == pytest.approx(0.3)
