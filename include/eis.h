@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 2
+#define EIS_ABI_VERSION 3
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -75,6 +75,11 @@ typedef enum {
     EIS_METHOD_INFRA = 1, /* baby window + infrastructure giant steps */
     EIS_METHOD_AUTO = 2   /* per-range choice by height (autotuned) */
 } eis_method;
+
+/* Candidate sets (the *_set calls): D itself, or the primes in D (the
+ * prime subsequence of Section 4; a prime d = 5 mod 8 is squarefree). */
+#define EIS_SET_SQUAREFREE 0
+#define EIS_SET_PRIME 1
 
 /* eis_config.flags bits */
 #define EIS_FLAG_NO_GRAPHS 1u    /* run batched passes as plain launches, not hipGraph replays */
@@ -180,6 +185,18 @@ int eis_last_error(eis_ctx *ctx);
  * Overlapping ranges are allowed and are counted independently. */
 int eis_count_batch(eis_ctx *ctx, const uint64_t *a, const uint64_t *b, size_t n,
                     uint64_t *n_sqfree, uint64_t *n_eis);
+
+/* Counts over a candidate set: *n_set = #(S n [a,b)) and *n_eis =
+ * #(E n S n [a,b)) for S = D (EIS_SET_SQUAREFREE, same as eis_count) or
+ * S = D n P, the primes p = 5 (mod 8) (EIS_SET_PRIME; Section 4, the prime
+ * subsequence pi_{E n P}).  The prime set is sieved by every odd prime up
+ * to sqrt(b) and only its members are walked.  EIS_EINVAL for another set. */
+int eis_count_set(eis_ctx *ctx, int set, uint64_t a, uint64_t b, uint64_t *n_set,
+                  uint64_t *n_eis);
+
+/* eis_count_batch over a candidate set (see eis_count_set). */
+int eis_count_batch_set(eis_ctx *ctx, int set, const uint64_t *a, const uint64_t *b, size_t n,
+                        uint64_t *n_set, uint64_t *n_eis);
 
 /* ----- Serving (continuous batching of range-count queries) ----------- */
 

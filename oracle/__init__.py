@@ -76,6 +76,8 @@ def _load():
     L.orc_classify_list.argtypes = [ctypes.c_void_p, u64, ctypes.c_void_p, c_int, P(u64)]
     L.orc_classify_list.restype = c_int
     L.orc_set_mutation.argtypes = [c_int]; L.orc_set_mutation.restype = None
+    L.orc_is_prime_trial.argtypes = [u64]; L.orc_is_prime_trial.restype = c_int
+    L.orc_count_primes_trial.argtypes = [u64, u64]; L.orc_count_primes_trial.restype = u64
     _lib = L
     return L
 
@@ -183,6 +185,27 @@ def classify_range(a: int, b: int, nthreads: int | None = None, want_bits: bool 
         raise RuntimeError("orc_classify_range failed")
     return dict(sq_bits=sq, eis_bits=eb, n_sqfree=int(nsq.value), n_eis=int(ne.value),
                 steps=int(steps.value))
+
+
+def is_prime_trial(n: int) -> bool:
+    return bool(_load().orc_is_prime_trial(n))
+
+
+def count_primes_trial(lo: int, hi: int) -> int:
+    """Number of primes in [lo, hi) by trial division."""
+    return int(_load().orc_count_primes_trial(lo, hi))
+
+
+def classify_primes(a: int, b: int, nthreads: int | None = None):
+    """The prime subsequence of [a, b) (Section 4): primes p = 5 (mod 8),
+    found by trial division, and how many of them lie in E (the full-period
+    walk).  Returns (n_primes, n_eis)."""
+    d0 = first_candidate(a)
+    ps = [d for d in range(d0, b, 8) if is_prime_trial(d)]
+    if not ps:
+        return 0, 0
+    flags, _ = classify_list(ps, nthreads)
+    return len(ps), int(flags.sum())
 
 
 def classify_list(ds, nthreads: int | None = None):

@@ -109,6 +109,28 @@ int orc_in_D_trial(uint64_t d)
     return (d % 8 == 5) && orc_is_squarefree_trial(d);
 }
 
+/* ------------------------------------------------------------------ */
+/* Primality by trial division (the definition of a prime), for the prime */
+/* subsequence of Section 4.                                              */
+/* ------------------------------------------------------------------ */
+int orc_is_prime_trial(uint64_t n)
+{
+    if (n < 2) return 0;
+    if (n < 4) return 1;
+    if (n % 2 == 0) return 0;
+    for (uint64_t p = 3; p * p <= n; p += 2)
+        if (n % p == 0) return 0;
+    return 1;
+}
+
+/* Number of primes n with lo <= n < hi, by trial division. */
+uint64_t orc_count_primes_trial(uint64_t lo, uint64_t hi)
+{
+    uint64_t c = 0;
+    for (uint64_t n = lo; n < hi; n++) c += (uint64_t)orc_is_prime_trial(n);
+    return c;
+}
+
 /* Number of candidates d = 5 (mod 8) with a <= d < b. */
 uint64_t orc_num_candidates(uint64_t a, uint64_t b)
 {

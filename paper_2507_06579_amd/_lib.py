@@ -13,7 +13,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
-ABI_VERSION = 2  # must match EIS_ABI_VERSION of include/eis.h
+ABI_VERSION = 3  # must match EIS_ABI_VERSION of include/eis.h
+EIS_SET_SQUAREFREE = 0
+EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
 EIS_FLAG_KERNEL_TIMES = 2
 # eis_kernel: index of the per-kernel entries of the stats
@@ -25,6 +27,7 @@ EXPORTED_SYMBOLS = [
     "eis_first_candidate", "eis_count", "eis_classify", "eis_classify_async",
     "eis_last_error", "eis_count_batch", "eis_submit", "eis_wait", "eis_cancel",
     "eis_get_stats", "eis_strerror", "eis_abi_version", "eis_tune", "eis_tuned_choice",
+    "eis_count_set", "eis_count_batch_set",
 ]
 
 
@@ -137,6 +140,10 @@ def lib():
     L.eis_strerror.argtypes = [c_int]; L.eis_strerror.restype = ctypes.c_char_p
     L.eis_abi_version.argtypes = []; L.eis_abi_version.restype = c_int
     L.eis_tune.argtypes = [vp]; L.eis_tune.restype = c_int
+    L.eis_count_set.argtypes = [vp, c_int, u64, u64, P(u64), P(u64)]
+    L.eis_count_set.restype = c_int
+    L.eis_count_batch_set.argtypes = [vp, c_int, vp, vp, sz, vp, vp]
+    L.eis_count_batch_set.restype = c_int
     L.eis_tuned_choice.argtypes = [vp, u64, P(c_int), P(ctypes.c_double)]
     L.eis_tuned_choice.restype = c_int
     if L.eis_abi_version() != ABI_VERSION:
@@ -246,6 +253,25 @@ class Context:
         e = np.zeros(max(1, n), dtype=np.uint64)
         _check(lib().eis_count_batch(self._h, a.ctypes.data, b.ctypes.data, n, s.ctypes.data,
                                      e.ctypes.data), "eis_count_batch")
+        return s[:n], e[:n]
+
+    def eis_count_set(self, set_: int, a: int, b: int):
+        s, e = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(lib().eis_count_set(self._h, int(set_), a, b, ctypes.byref(s), ctypes.byref(e)),
+               "eis_count_set")
+        return int(s.value), int(e.value)
+
+    def eis_count_batch_set(self, set_: int, a, b):
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.uint64))
+        if a.shape != b.shape:
+            raise ValueError("a and b must have the same length")
+        n = a.size
+        s = np.zeros(max(1, n), dtype=np.uint64)
+        e = np.zeros(max(1, n), dtype=np.uint64)
+        _check(lib().eis_count_batch_set(self._h, int(set_), a.ctypes.data, b.ctypes.data, n,
+                                         s.ctypes.data, e.ctypes.data), "eis_count_batch_set")
         return s[:n], e[:n]
 
     def eis_submit(self, a: int, b: int) -> int:

@@ -92,6 +92,7 @@ struct HostSeg {
     u32 method;    // 0 plain walk, 1 giant steps
     float wscale;  // giant steps: window scale of the segment
     u64 dst_bit;   // candidate offset of the segment in the caller's bitmap
+    u32 set = kSetSquarefree;  // the candidate set counted and walked
 };
 
 struct Request {
@@ -132,7 +133,8 @@ struct eis_ctx {
     // prime table
     std::vector<u32> primes_host;
     PrimeEntry *d_primes = nullptr;
-    u32 nsmall = 0;
+    u32 nsmall = 0;    // primes with p^2 < 4096
+    u32 nsmall_p = 0;  // primes with p < 4096
 
     // pass buffers
     SegInfo *d_segs = nullptr;
@@ -402,7 +404,16 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
             u64 p = c->primes_host[k];
             tab[k].m = p * p;
             tab[k].inv8 = (7 * tab[k].m + 1) / 8;
+            tab[k].p = (u32)p;
+            // 8^{-1} mod p = 8^(p-2) mod p (Fermat)
+            u64 inv = 1, base = 8 % p;
+            for (u64 e = p - 2; e; e >>= 1) {
+                if (e & 1) inv = inv * base % p;
+                base = base * base % p;
+            }
+            tab[k].inv8p = (u32)inv;
             if (tab[k].m < 4096) c->nsmall = (u32)(k + 1);
+            if (p < 4096) c->nsmall_p = (u32)(k + 1);
         }
         if (hipMalloc(&c->d_primes, tab.size() * sizeof(PrimeEntry)) != hipSuccess) {
             rc = EIS_ENOMEM;
@@ -605,6 +616,7 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
         g.method = h.method;
         g.count_slot = h.slot;
         g.wscale = h.wscale;
+        g.set = h.set;
         word += (h.n + 31) / 32;
         block += (h.n + kSegCandidates - 1) / kSegCandidates;
         roff += g.np;
@@ -694,7 +706,8 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
     KLAUNCH(EIS_K_PRIME_OFFSETS,
             launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
     KLAUNCH(EIS_K_SIEVE, launch_sieve(c->d_primes, c->d_roff, c->d_segs, pl.nseg, pl.nblocks,
-                                      c->nsmall, c->d_sq_words, c->d_list_plain, ctr_plain,
+                                      c->nsmall, c->nsmall_p, c->d_sq_words, c->d_list_plain,
+                                      ctr_plain,
                                       c->d_list_giant, ctr_giant, st));
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk0, st));
     WalkParams wp;
@@ -854,7 +867,8 @@ static int check_range(uint64_t a, uint64_t b)
 // candidates; bitmaps go to host (h_*) or device (d_*) byte buffers.
 static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t *h_eis,
                      uint8_t *d_sq, uint8_t *d_eis, uint64_t *n_sq, uint64_t *n_eis,
-                     unsigned long long *d_counts_out, hipStream_t st, bool sync)
+                     unsigned long long *d_counts_out, hipStream_t st, bool sync,
+                     u32 set = kSetSquarefree)
 {
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     int rc = settle_pending(c);
@@ -874,6 +888,7 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
         segs[0].method = method_for(c, segs[0].d0);
         segs[0].wscale = (float)scale_for(c, segs[0].d0);
         segs[0].dst_bit = off;
+        segs[0].set = set;
         PassPlan pl;
         rc = run_pass(c, segs, st, false, pl);
         if (rc != EIS_OK) return rc;
@@ -913,19 +928,25 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
     return status;
 }
 
-extern "C" int eis_count(eis_ctx *c, uint64_t a, uint64_t b, uint64_t *n_sqfree, uint64_t *n_eis)
+extern "C" int eis_count_set(eis_ctx *c, int set, uint64_t a, uint64_t b, uint64_t *n_set,
+                             uint64_t *n_eis)
 {
-    if (!c) return EIS_EINVAL;
+    if (!c || (set != EIS_SET_SQUAREFREE && set != EIS_SET_PRIME)) return EIS_EINVAL;
     int rc = check_range(a, b);
     if (rc != EIS_OK) return rc;
     if (eis_num_candidates(a, b) == 0) {
-        if (n_sqfree) *n_sqfree = 0;
+        if (n_set) *n_set = 0;
         if (n_eis) *n_eis = 0;
         return EIS_OK;
     }
     std::lock_guard<std::mutex> g(c->gpu_mu);
-    return run_range(c, a, b, nullptr, nullptr, nullptr, nullptr, n_sqfree, n_eis, nullptr,
-                     c->stream, true);
+    return run_range(c, a, b, nullptr, nullptr, nullptr, nullptr, n_set, n_eis, nullptr,
+                     c->stream, true, (u32)set);
+}
+
+extern "C" int eis_count(eis_ctx *c, uint64_t a, uint64_t b, uint64_t *n_sqfree, uint64_t *n_eis)
+{
+    return eis_count_set(c, EIS_SET_SQUAREFREE, a, b, n_sqfree, n_eis);
 }
 
 extern "C" int eis_classify(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *sqfree_bits,
@@ -1005,7 +1026,7 @@ extern "C" int eis_last_error(eis_ctx *c)
 // them into passes of at most kMaxSegments pieces and kPassCandidates
 // candidates.
 static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>> &ranges,
-                        std::vector<std::vector<HostSeg>> &passes)
+                        std::vector<std::vector<HostSeg>> &passes, u32 set = kSetSquarefree)
 {
     std::vector<HostSeg> pieces;
     for (const auto &r : ranges) {
@@ -1021,6 +1042,7 @@ static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>>
             h.method = method_for(c, h.d0);
             h.wscale = (float)scale_for(c, h.d0);
             h.dst_bit = off;
+            h.set = set;
             pieces.push_back(h);
         }
     }
@@ -1043,10 +1065,11 @@ static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>>
     if (!cur.empty()) passes.push_back(cur);
 }
 
-extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b, size_t n,
-                               uint64_t *n_sqfree, uint64_t *n_eis)
+extern "C" int eis_count_batch_set(eis_ctx *c, int set, const uint64_t *a, const uint64_t *b,
+                                   size_t n, uint64_t *n_set, uint64_t *n_eis)
 {
     if (!c || (n && (!a || !b))) return EIS_EINVAL;
+    if (set != EIS_SET_SQUAREFREE && set != EIS_SET_PRIME) return EIS_EINVAL;
     for (size_t k = 0; k < n; k++) {
         int rc = check_range(a[k], b[k]);
         if (rc != EIS_OK) return rc;
@@ -1057,7 +1080,7 @@ extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b,
     std::vector<std::vector<HostSeg>> passes;
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    pack_passes(c, ranges, passes);
+    pack_passes(c, ranges, passes, (u32)set);
     int rc = settle_pending(c);
     if (rc == EIS_OK) rc = ensure_counts(c, std::max<u64>(n, 1));
     if (rc != EIS_OK) return rc;
@@ -1088,10 +1111,16 @@ extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b,
     }
     if (status != EIS_OK) return status;
     for (size_t k = 0; k < n; k++) {
-        if (n_sqfree) n_sqfree[k] = c->h_counts[2 * k];
+        if (n_set) n_set[k] = c->h_counts[2 * k];
         if (n_eis) n_eis[k] = c->h_counts[2 * k + 1];
     }
     return EIS_OK;
+}
+
+extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b, size_t n,
+                               uint64_t *n_sqfree, uint64_t *n_eis)
+{
+    return eis_count_batch_set(c, EIS_SET_SQUAREFREE, a, b, n, n_sqfree, n_eis);
 }
 
 // ---------------------------------------------------------------------------

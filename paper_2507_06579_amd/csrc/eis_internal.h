@@ -25,12 +25,19 @@ constexpr u32 kItemMask = (1u << kItemShift) - 1;
 constexpr u32 kSegCandidates = 32768;
 constexpr u32 kSegWords = kSegCandidates / 32;
 
-// Device-side prime table entry for the squarefree sieve: an odd prime p,
-// its square m = p^2, and 8^{-1} mod m.
+// Device-side prime table entry for the sieves: an odd prime p, its square
+// m = p^2 and 8^{-1} mod m (squarefree sieve), and 8^{-1} mod p (prime sieve).
 struct PrimeEntry {
     u64 m;
     u64 inv8;
+    u32 p;
+    u32 inv8p;
 };
+
+// The candidate set a segment counts and walks: D (squarefree d = 5 mod 8)
+// or its primes.
+constexpr u32 kSetSquarefree = 0;
+constexpr u32 kSetPrime = 1;
 
 // One segment of a pass: candidates d0 + 8 i, i < n.
 struct SegInfo {
@@ -44,6 +51,7 @@ struct SegInfo {
     u32 count_slot;  // counts go to counts[2 slot] (D) and counts[2 slot + 1] (E)
     float wscale;    // giant steps: mu_1 is the distinguished ideal number
                      // round(wscale * d^(1/4) / 16)
+    u32 set;         // kSetSquarefree or kSetPrime
 };
 
 // Per-pass device counters (one cache line each to avoid false sharing).
@@ -128,7 +136,8 @@ hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream);
 hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u32 nseg,
                                 u32 np_max, u64 *roff, hipStream_t stream);
 hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo *segs,
-                        u32 nseg, u32 nblocks, u32 nsmall, u32 *sq_words, u32 *list_plain,
+                        u32 nseg, u32 nblocks, u32 nsmall, u32 nsmall_p, u32 *sq_words,
+                        u32 *list_plain,
                         PassCounters *ctr_plain, u32 *list_giant, PassCounters *ctr_giant,
                         hipStream_t stream);
 hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream);

@@ -57,7 +57,8 @@ __device__ __forceinline__ u64 mulmod_small(u64 a, u64 b, u64 m)
 // ---------------------------------------------------------------------------
 // k_prime_offsets: for segment s (blockIdx.y) and prime k < np_s,
 // roff[roff_off_s + k] = the least i >= 0 with m_k | d0_s + 8 i, that is
-// i = (-d0_s) * 8^{-1} (mod m_k).
+// i = (-d0_s) * 8^{-1} (mod m_k), where m_k = p_k^2 for the squarefree set
+// and m_k = p_k for the primes.
 // ---------------------------------------------------------------------------
 __global__ void k_prime_offsets(const PrimeEntry *__restrict__ primes,
                                 const SegInfo *__restrict__ segs, u64 *__restrict__ roff)
@@ -65,10 +66,12 @@ __global__ void k_prime_offsets(const PrimeEntry *__restrict__ primes,
     const SegInfo sg = segs[blockIdx.y];
     const u32 k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= sg.np) return;
-    const u64 m = primes[k].m;
+    const PrimeEntry pe = primes[k];
+    const bool prime_set = sg.set == kSetPrime;
+    const u64 m = prime_set ? (u64)pe.p : pe.m;
     const u64 r = sg.d0 % m;
     const u64 neg = r ? m - r : 0;
-    roff[sg.roff_off + k] = mulmod_small(neg, primes[k].inv8, m);
+    roff[sg.roff_off + k] = mulmod_small(neg, prime_set ? (u64)pe.inv8p : pe.inv8, m);
 }
 
 hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u32 nseg,
@@ -85,9 +88,12 @@ hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u
 // segment (the segment is found from the workgroup index).
 //   1. LDS bitmap <- all candidates of the block that lie below the
 //      segment's n
-//   2. strike i = roff (mod m) for every prime square m.  The first `nsmall`
-//      primes (m < 4096, many strikes per block) are spread over all
-//      threads; each larger prime belongs to one thread.
+//   2. strike i = roff (mod m) for every prime square m (squarefree set)
+//      or every prime m (prime set).  The first primes (m < 4096, many
+//      strikes per block: `nsmall` squares or `nsmall_p` primes) are spread
+//      over all threads; each larger prime belongs to one thread.  In the
+//      prime set a sieving prime that is itself a candidate of the block
+//      struck itself; its bit is set again.
 //   3. write the bitmap words, and append the surviving items to the work
 //      list of the segment's method (block-wide prefix sum, one global atomic
 //      per block).  Workgroups beyond the pass's blocks exit at once, so that
@@ -96,7 +102,8 @@ hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u
 __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ primes,
                                                const u64 *__restrict__ roff,
                                                const SegInfo *__restrict__ segs, u32 nseg,
-                                               u32 nblocks, u32 nsmall, u32 *__restrict__ sq_words,
+                                               u32 nblocks, u32 nsmall, u32 nsmall_p,
+                                               u32 *__restrict__ sq_words,
                                                u32 *__restrict__ list_plain,
                                                PassCounters *__restrict__ ctr_plain,
                                                u32 *__restrict__ list_giant,
@@ -121,7 +128,8 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
     const u32 segn = min(kSegCandidates, n - seg0);
     const u64 *ro = roff + sg.roff_off;
     const u32 np = sg.np;
-    const u32 ns = min(nsmall, np);
+    const bool prime_set = sg.set == kSetPrime;
+    const u32 ns = min(prime_set ? nsmall_p : nsmall, np);
 
     for (u32 w = tid; w < kSegWords; w += 256) {
         const u32 l0 = w * 32;
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
 
     // small prime squares: all threads share each prime's strikes
     for (u32 k = 0; k < ns; k++) {
-        const u32 m = (u32)primes[k].m;
+        const u32 m = prime_set ? primes[k].p : (u32)primes[k].m;
         const u32 r = (u32)ro[k];
         const u32 off = seg0 % m;
         const u32 first = (r >= off) ? r - off : r + m - off;  // (r - seg0) mod m
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
     }
     // larger prime squares: one prime per thread
     for (u32 k = ns + tid; k < np; k += 256) {
-        const u64 m = primes[k].m;
+        const u64 m = prime_set ? (u64)primes[k].p : primes[k].m;
         const u64 r = ro[k];
         if (m >= (u64)n) {
             // at most one strike in the whole segment: index r itself
@@ -162,6 +170,19 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
             atomicAnd(&bits[i >> 5], ~(1u << (i & 31)));
     }
     __syncthreads();
+    if (prime_set) {
+        const u64 lo_d = sg.d0 + 8ull * seg0, hi_d = lo_d + 8ull * segn;
+        if (np > 0 && lo_d <= (u64)primes[np - 1].p) {
+            for (u32 k = tid; k < np; k += 256) {
+                const u64 pk = primes[k].p;
+                if (pk >= lo_d && pk < hi_d && (pk - lo_d) % 8 == 0) {
+                    const u32 i = (u32)((pk - lo_d) >> 3);
+                    atomicOr(&bits[i >> 5], 1u << (i & 31));
+                }
+            }
+        }
+        __syncthreads();
+    }
 
     // write bitmap words and compact the survivors
     const u32 wbase = sg.word_off + seg0 / 32;
@@ -203,13 +224,14 @@ __global__ __launch_bounds__(256) void k_sieve(const PrimeEntry *__restrict__ pr
 }
 
 hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo *segs,
-                        u32 nseg, u32 nblocks, u32 nsmall, u32 *sq_words, u32 *list_plain,
-                        PassCounters *ctr_plain, u32 *list_giant, PassCounters *ctr_giant,
-                        hipStream_t stream)
+                        u32 nseg, u32 nblocks, u32 nsmall, u32 nsmall_p, u32 *sq_words,
+                        u32 *list_plain, PassCounters *ctr_plain, u32 *list_giant,
+                        PassCounters *ctr_giant, hipStream_t stream)
 {
     if (nblocks == 0 || nseg == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sieve, dim3(nblocks), dim3(256), 0, stream, primes, roff, segs, nseg,
-                       nblocks, nsmall, sq_words, list_plain, ctr_plain, list_giant, ctr_giant);
+                       nblocks, nsmall, nsmall_p, sq_words, list_plain, ctr_plain, list_giant,
+                       ctr_giant);
     return hipGetLastError();
 }
 

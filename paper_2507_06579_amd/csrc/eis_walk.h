@@ -112,7 +112,6 @@ __device__ __forceinline__ void wave_take(u32 *head, u32 n, bool want, u32 &item
     }
 }
 
-// Iterations of the inner loop between two checks of the step budget.
 // The pass's segment table, copied into LDS by every block of a walk kernel
 // (decoding a work item then costs an LDS read, not a dependent global one).
 __device__ __forceinline__ void load_segs(SegLds *dst, const SegInfo *src, u32 nseg)
@@ -129,6 +128,7 @@ __device__ __forceinline__ void load_segs(SegLds *dst, const SegInfo *src, u32 n
 // work item one refill ahead, so that the load's latency overlaps the walk.
 constexpr u32 kNoItem = ~0u;
 
+// Iterations of the inner loop between two checks of the step budget.
 constexpr u32 kInnerChunk = 1u << 14;
 
 

@@ -244,3 +244,35 @@ def test_pins_pass_unmutated():
 def test_planted_mistake_is_caught(which):
     with oracle.mutation(which):
         assert not _pins_pass()
+
+
+# ---- prime subsequence (Section 4) ----------------------------------------
+
+# pi(x), the number of primes below x: classical values
+PRIME_COUNTS = {100: 25, 1000: 168, 10**4: 1229, 10**5: 9592, 10**6: 78498}
+
+
+def test_prime_trial_division_counts_classical_values():
+    for x, pi_x in PRIME_COUNTS.items():
+        assert oracle.count_primes_trial(0, x) == pi_x, x
+
+
+def test_primes_5_mod_8_are_in_D_and_split_evenly():
+    ps = [p for p in range(5, 200000, 8) if oracle.is_prime_trial(p)]
+    assert all(oracle.in_D_trial(p) for p in ps[:2000])
+    # Dirichlet: a quarter of the odd primes below 2*10^5 (17983 in all)
+    total = oracle.count_primes_trial(3, 200000)
+    assert abs(len(ps) / total - 0.25) < 0.01
+
+
+def test_classify_primes_equals_filtered_range():
+    a, b = 10**6, 10**6 + 80000
+    n_p, n_e = oracle.classify_primes(a, b)
+    r = oracle.classify_range(a, b)
+    import numpy as np
+    n = oracle.num_candidates(a, b)
+    d0 = oracle.first_candidate(a)
+    eb = np.unpackbits(r["eis_bits"], bitorder="little")[:n]
+    primes = [i for i in range(n) if oracle.is_prime_trial(d0 + 8 * i)]
+    assert n_p == len(primes)
+    assert n_e == sum(int(eb[i]) for i in primes)
