@@ -36,3 +36,18 @@ def test_sweep_to_1e8_and_resume(tmp_path):
     again = sweep.run(10**8, 10**9, cp, per_call=3, log=_say)
     assert (again["pi_D"], again["pi_E"]) == (full["pi_D"], full["pi_E"])
     assert again["density"] == full["density"]
+
+
+def test_prime_sweep_matches_oracle_at_powers_of_ten(tmp_path):
+    cp = str(tmp_path / "primes.json")
+    _say("prime sweep to 1e7")
+    out = sweep.run(10**7, 10**9, cp, per_call=4, log=_say, which="prime")
+    assert out["set"] == "prime"
+    pw = {p["x"]: p for p in out["powers_of_ten"]}
+    for k in range(1, 8):
+        n_p, n_e = oracle.classify_primes(0, 10**k)
+        assert (pw[10**k]["pi_DP"], pw[10**k]["pi_EP"]) == (n_p, n_e), k
+    # pi(10^7) = 664,579 primes, of which about a quarter are 5 mod 8
+    assert abs(out["pi_DP"] - 664579 / 4) < 300
+    with pytest.raises(SystemExit):
+        sweep.run(10**7, 10**9, cp, per_call=4, log=_say, which="squarefree")
