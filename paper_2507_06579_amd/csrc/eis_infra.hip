@@ -384,6 +384,65 @@ hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream)
 }
 
 // ---------------------------------------------------------------------------
+// k_giant_square: one lane per batch position whose window left entries: the
+// giant step g = reduce(mu_1^2) by NUDUPL, with its residue.  Every lane runs
+// the same squaring (only the Euclid loops' lengths differ), which keeps
+// NUDUPL out of the giant walk, whose lanes are at different giant steps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double isqrt_f64(double x)
+{
+    // floor(sqrt(x)) for integer-valued 0 <= x < 2^52, corrected exactly
+    double r = floor(sqrt(x));
+    if ((r + 1.0) * (r + 1.0) <= x)
+        r += 1.0;
+    else if (r * r > x)
+        r -= 1.0;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
+{
+    __shared__ SegLds segs[kMaxSegments];
+    load_segs(segs, p.segs, p.nseg);
+    const u32 total = p.list_ctr->list_len;
+    const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
+    const u32 pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n) return;
+    const WindowState st = p.state[pos];
+    if (st.count == 0u) return;
+    const u32 e1 = st.emain - 1;
+    const unsigned long long m1 = p.lists[(u64)pos * p.emax + e1];
+    const u32 m1S = (p.lres[(u64)pos * p.emax + e1] >> 1) % 3u;
+    const u64 d = item_d(segs, st.item);
+    double s, P1, Q1;
+    u32 S1;
+    first_step(d, s, P1, Q1, S1);
+    const double dd = (double)d;
+    const double L = isqrt_f64(s);
+    Form f3;
+    Gamma gm;
+    Chk ck;
+    square_ideal(4.0 * (double)__uint_as_float((u32)(m1 >> 32)), 4.0 * (double)__uint_as_float((u32)m1),
+                 dd, L, f3, gm, ck);
+    const u32 lg = gamma_log(gm, ck);
+    double Qk, Pk, Qpk;
+    const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck);
+    GiantStart g;
+    g.Q4 = (float)Qk * 0.25f;
+    g.P4 = (float)Pk * 0.25f;
+    g.Qp4 = (float)Qpk * 0.25f;
+    g.S = ck.bad() ? kSquareBad : (2u * m1S + 3u - lg + Sr) % 3u;
+    p.gstart[pos] = g;
+}
+
+hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream)
+{
+    if (p.batch == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_giant_square, dim3((p.batch + 255) / 256), dim3(256), 0, stream, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_walk_giant
 // ---------------------------------------------------------------------------
 constexpr u32 kNoEntry = ~0u;
@@ -424,6 +483,14 @@ __device__ __forceinline__ void dict_find2(const u32 *tbl, const unsigned long l
         }
     }
 }
+
+// One d per lane, lanes refilled from a queue; a lane starts at g (from the
+// squaring kernel).  Two phases per iteration: a lane that is not walking
+// composes (and reduces) its next giant ideal c_{k+1} = reduce(g c_k) by
+// NUCOMP; then every walking lane takes up to kWalkChunk reduction steps
+// towards the next distinguished ideal and, on reaching it, looks it up.  A
+// lane with a long walk continues it in the next iteration instead of
+// holding up the other lanes.
 __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 {
     __shared__ SegLds segs[kMaxSegments];
@@ -431,27 +498,31 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
     const u32 mask = p.tsize - 1;
-    // per-lane state
-    u32 idx = 0, item = 0, ng = 0;
-    double dd = 0.0, sd = 0.0, L = 0.0;
-    double m1Q = 0.0, m1P = 0.0, cQ = 0.0, cP = 0.0;
+    // per-lane state; the giant step g and the current giant ideal c are
+    // reduced ideals, kept like the walk in fp32 quarter units (exact)
+    u32 idx = 0, item = 0, ng = 0, pos = 0;
+    double dd = 0.0;
+    float L = 0.f;
+    float m1Q = 0.f, m1P = 0.f, cQ = 0.f, cP = 0.f;
     u32 m1S = 0, cS = 0;
-    const u32 *tbl = nullptr;
-    const unsigned long long *lst = nullptr;
-    const u32 *lrs = nullptr;
     float sq = 0.f, sqc = 0.f;
     float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state, quarter units
     u32 Sw = 0, w = 0;
     bool walking = false;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool active = false;
-    u64 my_giants = 0, my_steps = 0;
-    // the lane's next batch position and its window record, loaded one
-    // refill ahead so that the load completes during the giant walk
+    u32 my_giants = 0;
+    u64 my_steps = 0;
+    // the lane's next batch position and its records, loaded one refill
+    // ahead so that the loads complete during the giant walk
     u32 npos = n;
     wave_take(p.giant_next, n, true, npos, cbase, cend);
     WindowState nst = {0u, 0u, 0u, 0u};
-    if (npos < n) nst = p.state[npos];
+    GiantStart ngs = {0.f, 0.f, 0.f, 0u};
+    if (npos < n) {
+        nst = p.state[npos];
+        ngs = p.gstart[npos];
+    }
 
     for (;;) {
         for (;;) {
@@ -460,15 +531,20 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             u32 g = n;
             wave_take(p.giant_next, n, want, g, cbase, cend);
             if (want) {
-                const u32 pos = npos;
+                pos = npos;
                 const WindowState st = nst;
+                const GiantStart gs = ngs;
                 npos = g;
-                if (g < n) nst = p.state[g];
+                if (g < n) {
+                    nst = p.state[g];
+                    ngs = p.gstart[g];
+                }
                 // positions whose flag is out or that went plain are skipped
-                if (st.count != 0u) {
-                    lst = p.lists + (u64)pos * p.emax;
-                    lrs = p.lres + (u64)pos * p.emax;
-                    const unsigned long long m1 = lst[st.emain - 1];
+                if (st.count != 0u && gs.S == kSquareBad) {
+                    const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                    p.fb_list[f] = st.item;
+                    my_giants += 1;
+                } else if (st.count != 0u) {
                     item = st.item;
                     idx = item_bit(segs, item);
                     const u64 d = item_d(segs, item);
@@ -476,22 +552,23 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     u32 S1;
                     first_step(d, s64, P1, Q1, S1);
                     dd = (double)d;
-                    sd = s64;
                     sq = (float)s64 * 0.25f;
                     sqc = sq * kQuotBias;
-                    L = floor(sqrt(s64));  // isqrt(s), corrected exactly
-                    if ((L + 1.0) * (L + 1.0) <= s64)
-                        L += 1.0;
-                    else if (L * L > s64)
-                        L -= 1.0;
-                    m1Q = 4.0 * (double)__uint_as_float((u32)(m1 >> 32));
-                    m1P = 4.0 * (double)__uint_as_float((u32)m1);
-                    m1S = (lrs[st.emain - 1] >> 1) % 3u;
+                    L = (float)isqrt_f64(s64);
+                    // g = reduce(mu_1^2) is the first giant ideal and the step
+                    m1Q = gs.Q4;
+                    m1P = gs.P4;
+                    m1S = gs.S;
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;
-                    tbl = p.tables + (u64)pos * p.tsize;
-                    ng = 0;
+                    Qw = gs.Q4;
+                    Pw = gs.P4;
+                    Qpw = gs.Qp4;
+                    Sw = gs.S;
+                    w = 0;
+                    ng = 1;
+                    walking = true;
                     active = true;
                 }
             }
@@ -499,44 +576,32 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
         if (!__any(active)) break;
 
         if (active) {
-            // Two phases per iteration: a lane that is not walking composes
-            // (and reduces) its next giant ideal; then every walking lane
-            // takes up to kWalkChunk reduction steps towards the next
-            // distinguished ideal.  A lane with a long walk continues it in
-            // the next iteration instead of holding up the other lanes.
-            bool bad = false;
-            if (!walking) {
+            bool bad = false, done = false, flag = false;
+            if (!walking && ng < p.max_giants) {
                 Form f3;
                 Gamma gm;
                 Chk ck;
-                nucomp_choose(m1Q, m1P, cQ, cP, dd, L, f3, gm, ck);
+                compose_ideals(4.0 * (double)m1Q, 4.0 * (double)m1P, 4.0 * (double)cQ,
+                               4.0 * (double)cP, dd, (double)L, f3, gm, ck);
                 const u32 lg = gamma_log(gm, ck);
                 double Qk, Pk, Qpk;
-                const u32 Sr = reduce_form(f3, dd, sd, Qk, Pk, Qpk, ck);
+                const u32 Sr = reduce_form(f3, dd, 4.0 * (double)sq, Qk, Pk, Qpk, ck);
                 const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
                 bad = ck.bad();
                 if (!bad) {
-                    if (ng == 0) {
-                        // the first composition squares mu_1; its square is
-                        // the giant step from then on
-                        m1Q = Qk;
-                        m1P = Pk;
-                        m1S = Sk;
-                    }
-                    cQ = Qk;
-                    cP = Pk;
-                    cS = Sk;
                     Qw = (float)Qk * 0.25f;
                     Pw = (float)Pk * 0.25f;
                     Qpw = (float)Qpk * 0.25f;
+                    cQ = Qw;
+                    cP = Pw;
+                    cS = Sk;
                     Sw = Sk;
                     w = 0;
                     walking = true;
                 }
                 ng++;
             }
-            bool done = false, flag = false;
-            if (walking) {
+            if (walking && !bad) {
                 u32 u = 0;
                 float acc = 0.f;
                 for (; u < kWalkChunk && !is_dp(Qw); u++) {
@@ -550,22 +615,26 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 w += u;
                 my_steps += u;
                 if (is_dp(Qw)) {
-                    walking = false;
-                    // Two lookups at once: the ideal (Q_m, P_m) itself -- a hit
-                    // means one period past a window ideal -- and its
+                    // Two lookups at once: the ideal (Q_m, P_m) itself -- a
+                    // hit means one period past a window ideal -- and its
                     // conjugate (Q_m, P_{m+1}) -- a hit means as many ideals
                     // short of a period as the window ideal lies past (1)
                     // (conjugation reverses the cycle and acts as
-                    // log -> -log, so log eps = S_m + S_i).
+                    // log -> -log, so log eps = S_m + S_i).  A direct hit
+                    // at the first lookup (after g itself) is skipped: g may
+                    // lie inside the window (a "unit" of distance 0); if it
+                    // was a true hit, a later one is at eps or eps^2, whose
+                    // residues are both 0 or both not.
+                    walking = false;
                     float Pn, Qn, acc1 = 0.f;
                     rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
+                    const u32 qb = __float_as_uint(Qw), pa = __float_as_uint(Pw),
+                              pc = __float_as_uint(Pn);
+                    const u32 *tbl = p.tables + (u64)pos * p.tsize;
+                    const unsigned long long *lst = p.lists + (u64)pos * p.emax;
+                    const u32 *lrs = p.lres + (u64)pos * p.emax;
                     u32 ed, ec;
-                    dict_find2(tbl, lst, mask, p.tsize, __float_as_uint(Qw), __float_as_uint(Pw),
-                               __float_as_uint(Pn), ed, ec);
-                    // a direct hit at the first lookup (mu_1^2) is skipped: it
-                    // may lie inside the window (a "unit" of distance 0); if
-                    // it was a true hit, a later one is at eps or eps^2,
-                    // whose residues are both 0 or both not
+                    dict_find2(tbl, lst, mask, p.tsize, qb, pa, pc, ed, ec);
                     if (ed != kNoEntry && ng > 1) {
                         const u32 St = (lrs[ed] >> 1) % 3u;
                         flag = ((Sw + 3u - St) % 3u) == 0u;
@@ -583,7 +652,8 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 emit_flag(p.eis_words, idx, flag);
                 my_giants += ng;
                 active = false;
-            } else if (bad || ng >= p.max_giants) {
+                walking = false;
+            } else if (bad || (!walking && ng >= p.max_giants)) {
                 const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
                 p.fb_list[f] = item;
                 my_giants += ng;
@@ -592,13 +662,14 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             }
         }
     }
+    u64 my_giants64 = my_giants;
     for (int off = 32; off > 0; off >>= 1) {
         my_steps += __shfl_down(my_steps, off, 64);
-        my_giants += __shfl_down(my_giants, off, 64);
+        my_giants64 += __shfl_down(my_giants64, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&p.ctr->chunk_steps, (unsigned long long)my_steps);
-        atomicAdd(&p.ctr->giant_steps, (unsigned long long)my_giants);
+        atomicAdd(&p.ctr->giant_steps, (unsigned long long)my_giants64);
     }
 }
 

@@ -107,6 +107,16 @@ struct WindowState {
     u32 pad;
 };
 
+// Per-d start of the giant walk, written by the squaring kernel: the giant
+// step g = reduce(mu_1^2) as a reduced ideal (Q/4, P/4 in fp32, Qp/4 its rho
+// predecessor) and its residue S in Z/3; S = kSquareBad when a check of the
+// squaring failed (the d then goes to the plain walk).
+struct GiantStart {
+    float Q4, P4, Qp4;
+    u32 S;
+};
+constexpr u32 kSquareBad = ~0u;
+
 struct InfraParams {
     const SegInfo *segs;        // segment table of the pass
     u32 nseg;                   // its number of segments
@@ -119,6 +129,7 @@ struct InfraParams {
     u32 *fb_list;               // items handed to the plain walk
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position
+    GiantStart *gstart;         // per batch position (d's with count > 0)
     unsigned long long *lists;  // window lists: entry e of batch position k at
                                 // k * emax + e; an entry is the ideal's
                                 // (Q/4, P/4) as fp32 bits
@@ -147,6 +158,7 @@ hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const
 
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream);
 hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream);
+hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream);
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream);
 int walk_window_blocks_per_cu();
 int walk_giant_blocks_per_cu();
