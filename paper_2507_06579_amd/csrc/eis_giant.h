@@ -46,14 +46,14 @@ __device__ __forceinline__ double rcp_nr(double b)
     return fma(fma(-b, r, 1.0), r, r);
 }
 
-// floor(a / b) for integers |a| < 2^52, 0 < b < 2^52.
+// floor(a / b) for integers |a| < 2^52, 0 < b < 2^52.  The estimate is off
+// by at most one either way; the correction is arithmetic, not a branch, so
+// that lanes needing it do not split the wave.
 __device__ __forceinline__ double fl_div(double a, double b)
 {
-    double q = floor(a * rcp_nr(b));
-    double r = fma(-q, b, a);  // exact: |r| < 2b
-    if (r < 0.0) q -= 1.0;
-    else if (r >= b) q += 1.0;
-    return q;
+    const double q = floor(a * rcp_nr(b));
+    const double r = fma(-q, b, a);  // exact: |r| < 2b
+    return q + (double)((int)(r >= b) - (int)(r < 0.0));
 }
 
 // a mod m in [0, m) for integers |a| < 2^52, 0 < m < 2^52.
@@ -72,21 +72,23 @@ __device__ __forceinline__ double ex_div(double a, double b, Chk &c)
     return q;
 }
 
-// q = floor(a / b) and r = a - q b for integer-valued fp32 0 <= a < 2^22,
-// 0 < b < 2^22: the estimate a * rcp(b) is within 3 ulp of a / b < 2^22, so
-// within 0.75 of it, and one correction of q either way makes it exact.
+// q = floor(a / b) and r = a - q b for integer-valued fp32 0 <= a < 2^21,
+// 0 < b < 2^21.  The estimate floor(fl(a c) rcp(b)) with c = 1 + 2^-21 is
+// never below the true quotient k: the relative errors of the roundings
+// (the product a c, the reciprocal's 1 ulp, the final product) add up to
+// less than 2^-21.  It is at most k + 1: for b <= 2 the reciprocal and the
+// last product are exact and a 2^-21 < 1, and for b >= 3 the excess is
+// below (a / b) 1.5 2^-21 < 0.5.  So r < 0 detects the one possible
+// overshoot, undone without a branch.
+constexpr float kDivBias = 1.f + 0x1p-21f;
+
 __device__ __forceinline__ float fl_div32(float a, float b, float &r)
 {
-    float q = floorf(a * __builtin_amdgcn_rcpf(b));
-    r = fmaf(-q, b, a);
-    if (r < 0.f) {
-        q -= 1.f;
-        r += b;
-    } else if (r >= b) {
-        q += 1.f;
-        r -= b;
-    }
-    return q;
+    const float q = floorf((a * kDivBias) * __builtin_amdgcn_rcpf(b));
+    const float r0 = fmaf(-q, b, a);
+    const float over = r0 < 0.f ? 1.f : 0.f;
+    r = fmaf(over, b, r0);
+    return q - over;
 }
 
 // Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for integers
@@ -394,6 +396,11 @@ __device__ __forceinline__ void compose_ideals(double u1, double v1, double u2, 
 // and Q Qp = d - P^2 is checked.
 constexpr int kMaxReduce = 128;
 
+__device__ __forceinline__ bool is_reduced(double Q, double P, double s)
+{
+    return Q > 0.0 && P > 0.0 && P <= s && s - P < Q && Q <= s + P;
+}
+
 __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, double &Q,
                                            double &P, double &Qp, Chk &bad)
 {
@@ -402,12 +409,12 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
     Qp = (f.u > 0.0) ? -2.0 * f.w : 2.0 * f.w;
     u32 S = 0;
     int it = 0;
-    while (!(Q > 0.0 && P > 0.0 && P <= s && s - P < Q && Q <= s + P)) {
-        if (++it > kMaxReduce || Q == 0.0) {
-            bad.fail = true;
-            break;
-        }
-        const double q = (Q > 0.0) ? fl_div(P + s, Q) : fl_div(-P - s - 1.0, -Q);
+    // One exit: the loop also stops once a value is no longer exact or Q
+    // vanished (then the final checks fail).
+    while (!is_reduced(Q, P, s) && it < kMaxReduce && Q != 0.0 && bad.mx < kExactLimit) {
+        it++;
+        const double num = (Q > 0.0) ? P + s : -P - s - 1.0;
+        const double q = fl_div(num, fabs(Q));
         const double qQ = q * Q;
         chk(qQ, bad);
         const double Pn = qQ - P;
@@ -415,12 +422,15 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
         chk(t, bad);
         const double Qn = Qp + t;
         chk(Qn, bad);
-        if (!(bad.mx < kExactLimit)) break;
-        S += 1u + (u32)(((long long)Pn >> 1) & 1);
+        // r(Pn) = 1 + bit 1 of the odd Pn: 2 when Pn = 3 (mod 4), i.e. when
+        // the fractional part of Pn / 4 is 3/4 (for either sign of Pn)
+        const double t4 = Pn * 0.25;
+        S += (t4 - floor(t4) > 0.5) ? 2u : 1u;
         Qp = Q;
         Q = Qn;
         P = Pn;
     }
+    bad.fail |= !is_reduced(Q, P, s);
     bad.fail |= (fma(Q, Qp, P * P) != d);
     return S;
 }

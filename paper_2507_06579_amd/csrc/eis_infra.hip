@@ -12,8 +12,8 @@
 //                  ideal (n = wscale * d^(1/4) / 16, at least 16); the
 //                  window ends at the first distinguished ideal at least six
 //                  steps after mu_1 (the two extra ideals of the algorithm,
-//                  with margin), and that extension must stay within a
-//                  quarter of mu_1's step count.
+//                  with margin), and that extension must stay within
+//                  mu_1's own step count.
 //   k_build_tables one wave per d: the list is indexed by an open-addressed
 //                  hash table of 32-bit slots (list index + 16-bit
 //                  fingerprint; a fingerprint match is confirmed against the
@@ -45,8 +45,12 @@
 // reads as a "unit" of distance 0.  Later giant ideals lie beyond the
 // window, so a direct hit is at one regulator (or two after a skipped true
 // hit); a conjugate hit can never be at distance 0, since giant ideals move
-// forward.  log eps^2 = 2 log eps is 0 in Z/3 exactly when log eps is, so a
-// hit at two regulators gives the same flag.
+// forward.  "Beyond the window": the second giant ideal lies about four
+// times mu_1's distance from (1), while the window ends within twice it
+// (its extension past mu_1 is at most mu_1's own step count; a d whose
+// extension is longer goes to the plain walk), a margin of a factor two over
+// the fluctuation of distance per step.  log eps^2 = 2 log eps is 0 in Z/3
+// exactly when log eps is, so a hit at two regulators gives the same flag.
 //
 // Any arithmetic check that fails (fp64 exactness, exact divisions, step or
 // walk budgets, table overflow) sends the d to the plain walk, which is exact
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                         // short next to mu_1's own distance (see above)
                         const u32 j1 = j1e - kExtraSteps;
                         const u32 S2e = S2 + 2 * it + 2 + (u32)acc;
-                        const bool ok = j1e != ~0u && jlast - j1 <= j1 / 4 && cnt < p.emax && S2e < (1u << 24);
+                        const bool ok = j1e != ~0u && jlast - j1 <= j1 && cnt < p.emax && S2e < (1u << 24);
                         if (ok) {
                             if (cnt % kRing) ring_flush(rg, lane, lb, rb, cnt / kRing * kRing);
                             st.emain = emain;
