@@ -171,7 +171,7 @@ struct eis_ctx {
     GiantStart *d_gstart = nullptr;
     unsigned long long *d_lists = nullptr;
     u32 *d_lres = nullptr;
-    u32 *d_tables = nullptr;
+    u16 *d_tables = nullptr;
     u64 infra_bytes = 0;
     u64 infra_batch_cap = 0;
     u32 infra_emax_cap = 0;
@@ -517,11 +517,11 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 4 + sizeof(WindowState) + sizeof(GiantStart));
+    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 2 + sizeof(WindowState) + sizeof(GiantStart));
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
         hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
-        hipMalloc(&c->d_tables, cap * tsize * 4) != hipSuccess ||
+        hipMalloc(&c->d_tables, cap * tsize * 2) != hipSuccess ||
         hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
         hipMalloc(&c->d_gstart, cap * sizeof(GiantStart)) != hipSuccess) {
         free_infra(c);
@@ -599,7 +599,7 @@ struct PassPlan {
     u32 emax = 0, tsize = 0;
     u64 batch = 0;
     u32 nbatches = 0;
-    u32 grid_plain = 0, grid_win = 0, grid_giant = 0, grid_fb = 0;
+    u32 grid_plain = 0, grid_win = 0, grid_giant = 0, grid_fb = 0, grid_tables = 0;
     u64 roff_total = 0;
 };
 
@@ -644,7 +644,7 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     pl.grid_fb = (u32)c->num_cu;
     if (pl.giant_cand) {
         infra_geometry(nmax_giant, pl.emax, pl.tsize);
-        const u64 per_d = (u64)pl.emax * 12 + (u64)pl.tsize * 4 + sizeof(WindowState) + sizeof(GiantStart);
+        const u64 per_d = (u64)pl.emax * 12 + (u64)pl.tsize * 2 + sizeof(WindowState) + sizeof(GiantStart);
         const u64 held = c->bytes_held - c->infra_bytes;  // other buffers of the context
         const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
         const u64 fit = std::max<u64>(avail / per_d / kInfraBatchMin * kInfraBatchMin, kInfraBatchMin);
@@ -654,6 +654,8 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
         const u64 max_giant = (u64)c->num_cu * c->giant_blocks_per_cu;
         pl.grid_win = (u32)std::max<u64>(1, std::min((pl.batch + 255) / 256, max_win));
         pl.grid_giant = (u32)std::max<u64>(1, std::min((pl.batch + 255) / 256, max_giant));
+        // table build: 8 resident blocks per CU (16 KB of LDS each)
+        pl.grid_tables = (u32)std::max<u64>(1, std::min((pl.batch + 3) / 4, (u64)c->num_cu * 8));
     }
 }
 
@@ -758,7 +760,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
             ip.k0 = (u32)(bi * pl.batch);
             HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
             KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, st));
-            KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, st));
+            KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, pl.grid_tables, st));
             KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, st));
             KLAUNCH(EIS_K_WALK_GIANT, launch_walk_giant(ip, pl.grid_giant, st));
         }

@@ -15,7 +15,7 @@
 //                  with margin), and that extension must stay within
 //                  mu_1's own step count.
 //   k_build_tables one wave per d: the list is indexed by an open-addressed
-//                  hash table of 32-bit slots (list index + 16-bit
+//                  hash table of 16-bit slots (9-bit list index + 7-bit
 //                  fingerprint; a fingerprint match is confirmed against the
 //                  list entry), built in LDS and written out whole.
 //   k_walk_giant   one d per lane, lanes refilled from a queue: the giant
@@ -339,7 +339,31 @@ int walk_window_blocks_per_cu()
 // k_build_tables: one wave per d that needs giant steps.  Workgroups are
 // numbered so that consecutive ones (d's of the same list tile) run on the
 // same XCD and share its L2: hardware block b goes to XCD b % 8.
+//
+// A slot holds (fingerprint << 9) | (e + 1) for list entry e (emax <= 496,
+// so e + 1 < 2^9), the fingerprint being the top 7 bits of the key's hash;
+// 0 is empty.
 // ---------------------------------------------------------------------------
+constexpr u32 kSlotIndexBits = 9;
+constexpr u32 kSlotIndexMask = (1u << kSlotIndexBits) - 1;
+constexpr u32 kLoadsPerLane = 8;  // list entries per lane: 8 * 64 = 512 >= emax
+
+__device__ __forceinline__ u32 slot_fp(u32 h) { return h >> (32 - (16 - kSlotIndexBits)); }
+
+// The lane's list entries (entry lane + 64 k) of the d at batch position pos,
+// which has cnt of them.
+__device__ __forceinline__ void load_entries(const InfraParams &p, u32 pos, u32 cnt,
+                                             unsigned long long (&ent)[kLoadsPerLane])
+{
+    const unsigned long long *lst = p.lists + (u64)pos * p.emax;
+    const u32 lane = threadIdx.x & 63;
+#pragma unroll
+    for (u32 k = 0; k < kLoadsPerLane; k++) {
+        const u32 e = lane + 64 * k;
+        ent[k] = (e < cnt) ? lst[e] : 0ull;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
 {
     __shared__ u32 tab[4][kTableMax];
@@ -347,43 +371,62 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     const u32 xcd = b % 8, q = nblk / 8, r = nblk % 8;
     const u32 lb = xcd * q + min(xcd, r) + b / 8;  // logical block
     const u32 wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const u32 w = lb * 4 + wv;
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
-    // the d at batch position w takes giant steps iff its window left entries
-    const u32 cnt = (w < n) ? p.state[w].count : 0u;
-    const bool valid = cnt != 0u;
     const u32 mask = p.tsize - 1;
-    for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
-    __syncthreads();
-    const u32 pos = w;
-    if (valid) {
-        const unsigned long long *lst = p.lists + (u64)pos * p.emax;
-        for (u32 e = lane; e < cnt; e += 64) {
-            const unsigned long long ent = lst[e];
-            const u32 qb = (u32)(ent >> 32), pb = (u32)ent;
-            const u32 h = dict_hash(qb, pb);
-            const u32 val = (e + 1) | (h & 0xffff0000u);
-            u32 slot = h & mask;
-            for (u32 probe = 0; probe < p.tsize; probe++) {
-                const u32 prev = atomicCAS(&tab[wv][slot], 0u, val);
-                if (prev == 0u) break;
-                slot = (slot + 1) & mask;
+    // Persistent: the block takes groups of four positions (one per wave),
+    // the same number of groups for all four waves, so that the barriers
+    // below are reached by the whole block.  The entry count of a position
+    // is loaded two groups ahead and its entries one group ahead, so that
+    // the loads overlap the insertions of the current group.  A position
+    // takes giant steps iff its window left entries (count > 0).
+    auto count_of = [&](u32 g) -> u32 {
+        const u32 pos = 4 * g + wv;
+        return (pos < n) ? p.state[pos].count : 0u;
+    };
+    u32 cnt0 = count_of(lb), cnt1 = count_of(lb + nblk);
+    unsigned long long ent0[kLoadsPerLane], ent1[kLoadsPerLane];
+    load_entries(p, 4 * lb + wv, cnt0, ent0);
+    for (u32 g = lb; 4 * g < n; g += nblk) {
+        const u32 pos = 4 * g + wv;
+        const u32 cnt2 = count_of(g + 2 * nblk);
+        load_entries(p, pos + 4 * nblk, cnt1, ent1);
+        for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (u32 k = 0; k < kLoadsPerLane; k++) {
+            const u32 e = lane + 64 * k;
+            if (e < cnt0) {
+                const u32 qb = (u32)(ent0[k] >> 32), pb = (u32)ent0[k];
+                const u32 h = dict_hash(qb, pb);
+                const u32 val = (e + 1) | (slot_fp(h) << kSlotIndexBits);
+                u32 slot = h & mask;
+                for (u32 probe = 0; probe < p.tsize; probe++) {
+                    const u32 prev = atomicCAS(&tab[wv][slot], 0u, val);
+                    if (prev == 0u) break;
+                    slot = (slot + 1) & mask;
+                }
             }
         }
-    }
-    __syncthreads();
-    if (valid) {
-        u32 *tbl = p.tables + (u64)pos * p.tsize;
-        for (u32 t = lane; t < p.tsize; t += 64) tbl[t] = tab[wv][t];
+        __syncthreads();
+        if (cnt0 != 0u) {
+            // two slots per 32-bit store
+            u32 *tbl = reinterpret_cast<u32 *>(p.tables + (u64)pos * p.tsize);
+            for (u32 t = lane; t < p.tsize / 2; t += 64) tbl[t] = tab[wv][2 * t] | (tab[wv][2 * t + 1] << 16);
+        }
+        __syncthreads();
+        cnt0 = cnt1;
+        cnt1 = cnt2;
+#pragma unroll
+        for (u32 k = 0; k < kLoadsPerLane; k++) ent0[k] = ent1[k];
     }
 }
 
-hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream)
+hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t stream)
 {
-    if (p.batch == 0) return hipSuccess;
+    if (p.batch == 0 || grid == 0) return hipSuccess;
     if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_build_tables, dim3((p.batch + 3) / 4), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(k_build_tables, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -455,12 +498,13 @@ constexpr u32 kNoEntry = ~0u;
 // table (open addressing, linear probing), or kNoEntry.  The two probe
 // chains advance together, so that their loads overlap; a slot's
 // fingerprint match is confirmed against the full key in the list.
-__device__ __forceinline__ void dict_find2(const u32 *tbl, const unsigned long long *lst, u32 mask,
+__device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long long *lst, u32 mask,
                                            u32 tsize, u32 qb, u32 pa, u32 pc, u32 &ea, u32 &ec)
 {
     const unsigned long long ka = ((unsigned long long)qb << 32) | pa;
     const unsigned long long kc = ((unsigned long long)qb << 32) | pc;
     const u32 ha = dict_hash(qb, pa), hc = dict_hash(qb, pc);
+    const u32 fa = slot_fp(ha), fc = slot_fp(hc);
     u32 sa = ha & mask, sc = hc & mask;
     bool da = false, dc = false;
     ea = ec = kNoEntry;
@@ -470,8 +514,8 @@ __device__ __forceinline__ void dict_find2(const u32 *tbl, const unsigned long l
         if (!da) {
             if (va == 0u) {
                 da = true;
-            } else if ((va & 0xffff0000u) == (ha & 0xffff0000u) && lst[(va & 0xffffu) - 1] == ka) {
-                ea = (va & 0xffffu) - 1;
+            } else if ((va >> kSlotIndexBits) == fa && lst[(va & kSlotIndexMask) - 1] == ka) {
+                ea = (va & kSlotIndexMask) - 1;
                 da = true;
             }
             sa = (sa + 1) & mask;
@@ -479,8 +523,8 @@ __device__ __forceinline__ void dict_find2(const u32 *tbl, const unsigned long l
         if (!dc) {
             if (vc == 0u) {
                 dc = true;
-            } else if ((vc & 0xffff0000u) == (hc & 0xffff0000u) && lst[(vc & 0xffffu) - 1] == kc) {
-                ec = (vc & 0xffffu) - 1;
+            } else if ((vc >> kSlotIndexBits) == fc && lst[(vc & kSlotIndexMask) - 1] == kc) {
+                ec = (vc & kSlotIndexMask) - 1;
                 dc = true;
             }
             sc = (sc + 1) & mask;
@@ -634,7 +678,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
                     const u32 qb = __float_as_uint(Qw), pa = __float_as_uint(Pw),
                               pc = __float_as_uint(Pn);
-                    const u32 *tbl = p.tables + (u64)pos * p.tsize;
+                    const u16 *tbl = p.tables + (u64)pos * p.tsize;
                     const unsigned long long *lst = p.lists + (u64)pos * p.emax;
                     const u32 *lrs = p.lres + (u64)pos * p.emax;
                     u32 ed, ec;

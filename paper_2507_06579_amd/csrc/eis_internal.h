@@ -8,6 +8,7 @@
 
 namespace eis {
 
+typedef uint16_t u16;
 typedef uint32_t u32;
 typedef uint64_t u64;
 
@@ -134,7 +135,7 @@ struct InfraParams {
                                 // k * emax + e; an entry is the ideal's
                                 // (Q/4, P/4) as fp32 bits
     u32 *lres;                  // 2 S (twice the residue sum) of each entry, same layout
-    u32 *tables;                // hash tables, tsize slots per batch position
+    u16 *tables;                // hash tables, tsize 16-bit slots per batch position
     u32 emax;                   // list capacity per d (a multiple of 8)
     u32 tsize;                  // table slots per d (power of two)
     u32 max_steps;              // per-d budget of reduction steps (window)
@@ -157,7 +158,7 @@ hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const
                                 hipStream_t stream);
 
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream);
-hipError_t launch_build_tables(const InfraParams &p, hipStream_t stream);
+hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t stream);
 hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream);
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream);
 int walk_window_blocks_per_cu();
