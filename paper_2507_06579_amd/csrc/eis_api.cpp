@@ -43,7 +43,7 @@ namespace {
 constexpr u64 kDefaultMaxSteps = u64(1) << 28;
 // mu_1 is the distinguished ideal number window_scale * d^(1/4) / 16, about
 // window_scale * d^(1/4) reduction steps from (1).
-constexpr double kDefaultWindowScale = 3.5;
+constexpr double kDefaultWindowScale = 2.0;
 // AUTO method: segments starting at or above this height take giant steps.
 constexpr u64 kDefaultInfraMinHeight = 100000000ull;
 // Giant-step batches: a batch's dictionaries are resident, so a batch holds
@@ -254,7 +254,7 @@ extern "C" void eis_config_default(eis_config *cfg)
 }
 
 // Autotuner cache: a small JSON object written by eis_tune,
-//   {"arch": "gfx950", "bins": [{"b": 12, "method": 0, "window_scale": 3.5, ...}, ...]}
+//   {"arch": "gfx950", "bins": [{"b": 12, "method": 0, "window_scale": 2.0, ...}, ...]}
 // read back by scanning for the three keys of every bin.
 static void load_tune_cache(eis_ctx *c)
 {
@@ -1351,7 +1351,7 @@ extern "C" int eis_tune(eis_ctx *c)
     if (!c) return EIS_EINVAL;
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    const double scales[] = {1.0, 1.5, 2.5, 3.5, 5.0, 7.0};
+    const double scales[] = {1.0, 1.5, 2.0, 2.5, 3.5, 5.0};
     const u32 n = 1u << 23;  // candidates per sample: half a full pass
     int method[kTuneBins];
     double wsc[kTuneBins], plain_ms[kTuneBins], giant_ms[kTuneBins];
@@ -1363,7 +1363,7 @@ extern "C" int eis_tune(eis_ctx *c)
     float ms = 0.f;
     // one untimed pass of each method allocates every buffer
     int rc = time_pass(c, 1000000005ull, n, 0, kDefaultWindowScale, ms);
-    if (rc == EIS_OK) rc = time_pass(c, 1000000005ull, n, 1, 7.0, ms);
+    if (rc == EIS_OK) rc = time_pass(c, 1000000005ull, n, 1, 5.0, ms);
     if (rc != EIS_OK) return rc;
     // bins from 10^6 up, each sampled from its geometric middle: the last
     // sample, at 10^11.75, ends below 10^12

@@ -12,7 +12,7 @@ import paper_2507_06579_amd as eis
 
 pytestmark = pytest.mark.gpu
 
-SCALES = {1.0, 1.5, 2.5, 3.5, 5.0, 7.0}
+SCALES = {1.0, 1.5, 2.0, 2.5, 3.5, 5.0}
 
 
 def _say(msg):
@@ -46,15 +46,15 @@ def test_tune_choices_cache_and_bits(tmp_path):
     with eis.Context(tune_cache_path=path) as c:
         assert [c.eis_tuned_choice(d) for d in heights] == choices
     # an explicit method and scale win over the tuned choice
-    with eis.Context(tune_cache_path=path, method=eis.Method.INFRA, window_scale=2.0) as c:
-        assert c.eis_tuned_choice(10**11) == (eis.Method.INFRA, 2.0)
+    with eis.Context(tune_cache_path=path, method=eis.Method.INFRA, window_scale=2.75) as c:
+        assert c.eis_tuned_choice(10**11) == (eis.Method.INFRA, 2.75)
 
 
 def test_untuned_defaults():
     with eis.Context() as c:
         assert c.eis_tuned_choice(10**6)[0] == eis.Method.BABY
         assert c.eis_tuned_choice(10**11)[0] == eis.Method.INFRA
-        assert c.eis_tuned_choice(10**11)[1] == 3.5
+        assert c.eis_tuned_choice(10**11)[1] == 2.0
 
 
 def test_tune_cache_rejects_partial_file(tmp_path):
@@ -62,7 +62,7 @@ def test_tune_cache_rejects_partial_file(tmp_path):
     path.write_text('{"arch": "gfx950", "bins": [{"b": 12, "method": 1, "window_scale": 2.5}]}')
     with eis.Context(tune_cache_path=str(path)) as c:
         # not every bin present: defaults stay in force
-        assert c.eis_tuned_choice(10**6) == (eis.Method.BABY, 3.5)
+        assert c.eis_tuned_choice(10**6) == (eis.Method.BABY, 2.0)
 
 
 def test_kernel_times_and_step_counts():
