@@ -42,6 +42,21 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # nearly every step (1 - (15/16)^64 = 0.98), and the window-end tests once
 # per two steps: 28 slots.
 VALU_SLOTS_PER_STEP = {"walk_plain": 10.0, "walk_handoff": 10.0, "walk_window": 28.0}
+# Giant-step walk: VALU issue slots per unit of its work, counted the same
+# way in the gfx950 code of the built kernel (per-lane path; a branch that a
+# lane does not take is not counted for it), the units being counted by the
+# kernel itself (eis_stats giant_*):
+#   composition, fixed part: the two ideal forms, NUCOMP on its common path
+#     (gcd dividing s, partial Euclid with z != 0), the residue of gamma, the
+#     set-up and final checks of the reduction, the kernel's bookkeeping: 330;
+#   NUCOMP's gcd branch, when taken (H, l and their reductions mod H): 126;
+#   Euclid step (extended or partial Euclid, two per loop iteration): 15;
+#   reduction step after a composition (fp64, with its checks): 47;
+#   walk step towards the next distinguished ideal (the step, the test): 11;
+#   lookup of a distinguished ideal and its conjugate (hashes, first probe,
+#     the extra step for the conjugate's key): 67.
+GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 126.0, "euclid_steps": 15.0,
+               "reduce_steps": 47.0, "walk_steps": 11.0, "lookups": 67.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the
@@ -202,21 +217,54 @@ def main():
             kernels[name] = {"ms_per_step": round(kms[k] / args.steps, 3),
                              "launches_per_step": kl[k] / args.steps,
                              "rho_steps_per_step": ks[k] // args.steps}
-    # dominant kernel among the walks with an instruction count per step
-    dom = max(VALU_SLOTS_PER_STEP, key=lambda name: kms[eis.KERNELS.index(name)])
+    # dominant kernel: the walk kernel with the largest share of the step
+    # (the other kernels of a pass take a few percent of it)
+    walks = list(VALU_SLOTS_PER_STEP) + ["walk_giant"]
+
+    def slot_model(name):
+        """(VALU slots, units of work, unit name, model details) of the
+        timed launches of a walk kernel."""
+        k = eis.KERNELS.index(name)
+        if name != "walk_giant":
+            return VALU_SLOTS_PER_STEP[name] * ks[k], ks[k], "rho step", None
+        work = {key: st["giant_" + key] - base["giant_" + key]
+                for key in ("compositions", "gcd_branches", "euclid_steps", "reduce_steps",
+                            "lookups")}
+        work["walk_steps"] = ks[k]
+        slots = sum(GIANT_SLOTS[key] * v for key, v in work.items())
+        return (slots, work["compositions"],
+                "giant step (composition, reduction, walk to a distinguished ideal, lookup)",
+                {"slots": GIANT_SLOTS,
+                 "work_per_launch": {key: int(v / kl[k]) for key, v in work.items()}})
+
+    dom = max(walks, key=lambda name: kms[eis.KERNELS.index(name)])
     kd = eis.KERNELS.index(dom)
     avg_launch_s = kms[kd] / kl[kd] / 1e3
-    units_per_launch = ks[kd] / kl[kd]
-    achieved = VALU_SLOTS_PER_STEP[dom] * units_per_launch / avg_launch_s
+    slots, units, unit_of_work, model = slot_model(dom)
+    achieved = slots / kl[kd] / avg_launch_s
+    kernel_name = {"walk_plain": "k_walk_baby", "walk_handoff": "k_walk_baby",
+                   "walk_window": "k_walk_window", "walk_giant": "k_walk_giant"}[dom]
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-slots/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4),
                 "traffic": None,
-                "kernel": "k_walk_baby" if dom != "walk_window" else "k_walk_window",
-                "ops_per_unit": VALU_SLOTS_PER_STEP[dom], "unit_of_work": "rho step",
-                "units_per_launch": int(units_per_launch),
+                "kernel": kernel_name,
+                "ops_per_unit": round(slots / max(1, units), 1), "unit_of_work": unit_of_work,
+                "units_per_launch": int(units / kl[kd]),
                 "avg_launch_ms": round(avg_launch_s * 1e3, 3),
                 "share_of_step_time": round(kms[kd] / (1e3 * elapsed), 3)}
+    if model:
+        roofline["model"] = model
+    # the other walk kernels of the step, on the same model
+    others = {}
+    for name in walks:
+        k = eis.KERNELS.index(name)
+        if name == dom or not kl[k] or not ks[k]:
+            continue
+        sl, _, _, _ = slot_model(name)
+        a_k = sl / (kms[k] / 1e3)
+        others[name] = {"achieved": round(a_k / 1e12, 3), "frac": round(a_k / PEAK_LANE_OPS, 4),
+                        "ms_per_step": round(kms[k] / args.steps, 3)}
     roofline["traffic"] = measured_traffic(roofline["kernel"], f"large:{chosen.name.lower()}")
     out = {
         "metric": METRIC,
@@ -240,6 +288,7 @@ def main():
         "giant_steps_per_s": round(giant / elapsed, 1),
         "kernels": kernels,
         "roofline": roofline,
+        "roofline_other_walks": others,
     }
     if not args.no_serving:
         from paper_2507_06579_amd import serve

@@ -128,6 +128,15 @@ typedef struct {
      * their summed device time */
     uint64_t kernel_launches[EIS_K_COUNT];
     double kernel_ms[EIS_K_COUNT];
+    /* work of the giant-step walk (the operation counts of its instruction
+     * model): NUCOMP compositions, the Euclid steps inside them (extended and
+     * partial Euclid), the reduction steps after them, the compositions that
+     * took NUCOMP's gcd branch, and the dictionary lookups (pairs of keys) */
+    uint64_t giant_compositions;
+    uint64_t giant_euclid_steps;
+    uint64_t giant_reduce_steps;
+    uint64_t giant_gcd_branches;
+    uint64_t giant_lookups;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */

@@ -76,6 +76,11 @@ class EisStats(ctypes.Structure):
         ("kernel_steps", ctypes.c_uint64 * len(KERNELS)),
         ("kernel_launches", ctypes.c_uint64 * len(KERNELS)),
         ("kernel_ms", ctypes.c_double * len(KERNELS)),
+        ("giant_compositions", ctypes.c_uint64),
+        ("giant_euclid_steps", ctypes.c_uint64),
+        ("giant_reduce_steps", ctypes.c_uint64),
+        ("giant_gcd_branches", ctypes.c_uint64),
+        ("giant_lookups", ctypes.c_uint64),
     ]
 
     def as_dict(self):

@@ -91,28 +91,43 @@ __device__ __forceinline__ float fl_div32(float a, float b, float &r)
     return q - over;
 }
 
+// Work counts of one composition (for the instruction model of the giant
+// walk): Euclid steps of the extended and partial Euclid loops, reduction
+// steps after the composition, and whether NUCOMP took its gcd branch.
+struct GiantWork {
+    u32 euclid = 0, reduce = 0, gcd_branch = 0;
+};
+
 // Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for integers
-// |a|, |b| < 2^21 (then |x|, |y| < 2^21 too): exact in fp32.
-__device__ __forceinline__ void xgcd(double ad, double bd, double &x, double &y, double &g)
+// |a|, |b| < 2^21 (then |x|, |y| < 2^21 too): exact in fp32.  Invariants:
+// x0 A + y0 B = a and x1 A + y1 B = b for the inputs A = |a|, B = |b|; the
+// loop ends when one of a, b is 0, and the other is the gcd.  Two division
+// steps per iteration, the second with the roles of (a, x0, y0) and
+// (b, x1, y1) exchanged and applied only if the first left a != 0 (a
+// select, not a branch), so that no step moves registers around.
+__device__ __forceinline__ void xgcd(double ad, double bd, double &x, double &y, double &g,
+                                     GiantWork &wk)
 {
     const float sa = ad < 0.0 ? -1.f : 1.f, sb = bd < 0.0 ? -1.f : 1.f;
     float a = (float)fabs(ad), b = (float)fabs(bd);
     float x0 = 1.f, x1 = 0.f, y0 = 0.f, y1 = 1.f;
-    while (b != 0.f) {
+    while (a != 0.f && b != 0.f) {
         float r;
-        const float q = fl_div32(a, b, r);
-        a = b;
-        b = r;
-        float t = fmaf(-q, x1, x0);
-        x0 = x1;
-        x1 = t;
-        t = fmaf(-q, y1, y0);
-        y0 = y1;
-        y1 = t;
+        float q = fl_div32(a, b, r);
+        a = r;
+        x0 = fmaf(-q, x1, x0);
+        y0 = fmaf(-q, y1, y0);
+        const bool go = a != 0.f;
+        q = fl_div32(b, go ? a : 1.f, r);
+        b = go ? r : b;
+        x1 = go ? fmaf(-q, x0, x1) : x1;
+        y1 = go ? fmaf(-q, y0, y1) : y1;
+        wk.euclid += go ? 2u : 1u;
     }
-    g = (double)a;
-    x = (double)(x0 * sa);
-    y = (double)(y0 * sb);
+    const bool az = a == 0.f;
+    g = (double)(az ? b : a);
+    x = (double)((az ? x1 : x0) * sa);
+    y = (double)((az ? y1 : y0) * sb);
 }
 
 struct Form {
@@ -126,24 +141,37 @@ struct Gamma {
 
 // Partial Euclid shared by NUCOMP and NUDUPL: run while |b_y| > L and b_x != 0
 // (both stay non-negative), then flip the signs of b_y and y when the number
-// of steps z is odd.  0 <= b_x < b_y < 2^21, so the loop runs in fp32.
+// of steps z is odd.  0 <= b_x < b_y < 2^21, so the loop runs in fp32.  A
+// step takes q = floor(b_y / b_x) and maps (b_x, b_y, x, y) to
+// (b_y - q b_x, b_x, y - q x, x).  Two steps per iteration, the second on
+// the exchanged roles (u, v, X, Y) -> (v, u, Y, X) and applied only if the
+// loop condition holds after the first (a select, not a branch), so that no
+// step moves registers around.
 __device__ __forceinline__ void partial_euclid(double &bxd, double &byd, double &x, double &y,
                                                int &z, double L)
 {
-    float bx = (float)bxd, by = (float)byd, xf = 1.f, yf = 0.f;
+    float u = (float)bxd, v = (float)byd, X = 1.f, Y = 0.f;  // (b_x, b_y, x, y)
     const float Lf = (float)L;
-    z = 0;
-    while (by > Lf && bx != 0.f) {
-        float t;
-        const float q = fl_div32(by, bx, t);
-        by = bx;
-        bx = t;
-        const float t2 = fmaf(-q, xf, yf);
-        yf = xf;
-        xf = t2;
-        z++;
+    bool odd = false;  // after an odd step count the roles stay exchanged
+    int n = 0;
+    bool run = v > Lf && u != 0.f;
+    while (run) {
+        float r;
+        float q = fl_div32(v, u, r);
+        v = r;
+        Y = fmaf(-q, X, Y);
+        // now (b_x, b_y, x, y) = (v, u, Y, X)
+        const bool go = u > Lf && v != 0.f;
+        q = fl_div32(u, go ? v : 1.f, r);
+        u = go ? r : u;
+        X = go ? fmaf(-q, Y, X) : X;
+        n += go ? 2 : 1;
+        odd = !go;
+        run = go && v > Lf && u != 0.f;
     }
-    if (z & 1) {
+    z = n;
+    float bx = odd ? v : u, by = odd ? u : v, xf = odd ? Y : X, yf = odd ? X : Y;
+    if (n & 1) {
         by = -by;
         yf = -yf;
     }
@@ -155,7 +183,7 @@ __device__ __forceinline__ void partial_euclid(double &bxd, double &byd, double 
 
 // Algorithm NUCOMP: phi3 = (1/gamma) phi1 phi2, partially reduced with bound L.
 __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gamma &g,
-                                       Chk &bad)
+                                       Chk &bad, GiantWork &wk)
 {
     if (f1.w < f2.w) {
         const Form t = f1;
@@ -165,7 +193,7 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
     const double s = ex_div(f1.v + f2.v, 2.0, bad);
     const double m = f2.v - s;
     double b, c, F;
-    xgcd(f2.u, f1.u, b, c, F);  // b u2 + c u1 = F
+    xgcd(f2.u, f1.u, b, c, F, wk);  // b u2 + c u1 = F
     double G, Bx, By, Cy, Dy;
     if (nn_mod(s, F) == 0.0) {
         G = F;
@@ -176,7 +204,8 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
         Dy = ex_div(s, G, bad);
     } else {
         double x2, y2;
-        xgcd(F, s, x2, y2, G);  // x2 F + y2 s = G
+        wk.gcd_branch = 1;
+        xgcd(F, s, x2, y2, G, wk);  // x2 F + y2 s = G
         const double H = ex_div(F, G, bad);
         By = ex_div(f1.u, G, bad);
         Cy = ex_div(f2.u, G, bad);
@@ -194,6 +223,7 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
     double bx = nn_mod(Bx, By), by = By, x, y;
     int z;
     partial_euclid(bx, by, x, y, z, L);
+    wk.euclid += (u32)z;
     const double ax = G * x, ay = G * y;
     double u3, v3, w3;
     if (z != 0) {
@@ -257,10 +287,11 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
 }
 
 // Algorithm NUDUPL: phi3 = (1/gamma) phi^2, partially reduced with bound L.
-__device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk &bad)
+__device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk &bad,
+                                       GiantWork &wk)
 {
     double x0, y0, G;
-    xgcd(f.u, f.v, x0, y0, G);  // x0 u + y0 v = G
+    xgcd(f.u, f.v, x0, y0, G, wk);  // x0 u + y0 v = G
     const double By = ex_div(f.u, G, bad);
     const double Dy = ex_div(f.v, G, bad);
     // B_x = y0 w mod B_y, reduced factor by factor
@@ -268,6 +299,7 @@ __device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk
     double bx = Bx, by = By, x, y;
     int z;
     partial_euclid(bx, by, x, y, z, L);
+    wk.euclid += (u32)z;
     const double ax = G * x, ay = G * y;
     double u3, v3, w3;
     if (z == 0) {
@@ -370,16 +402,17 @@ __device__ __forceinline__ Form ideal_form(double u, double v, double d, Chk &ba
 // cycle ideals with d up to 10^12), so a caller whose lanes mix squares and
 // products may send both through NUCOMP and keep every lane on one path.
 __device__ __forceinline__ void square_ideal(double u, double v, double d, double L, Form &f3,
-                                             Gamma &g, Chk &bad)
+                                             Gamma &g, Chk &bad, GiantWork &wk)
 {
-    nudupl(ideal_form(u, v, d, bad), L, f3, g, bad);
+    nudupl(ideal_form(u, v, d, bad), L, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }
 
 __device__ __forceinline__ void compose_ideals(double u1, double v1, double u2, double v2,
-                                               double d, double L, Form &f3, Gamma &g, Chk &bad)
+                                               double d, double L, Form &f3, Gamma &g, Chk &bad,
+                                               GiantWork &wk)
 {
-    nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), L, f3, g, bad);
+    nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), L, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }
 
@@ -402,7 +435,7 @@ __device__ __forceinline__ bool is_reduced(double Q, double P, double s)
 }
 
 __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, double &Q,
-                                           double &P, double &Qp, Chk &bad)
+                                           double &P, double &Qp, Chk &bad, GiantWork &wk)
 {
     Q = fabs(2.0 * f.u);
     P = -f.v;
@@ -413,6 +446,7 @@ __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, do
     // vanished (then the final checks fail).
     while (!is_reduced(Q, P, s) && it < kMaxReduce && Q != 0.0 && bad.mx < kExactLimit) {
         it++;
+        wk.reduce++;
         const double num = (Q > 0.0) ? P + s : -P - s - 1.0;
         const double q = fl_div(num, fabs(Q));
         const double qQ = q * Q;

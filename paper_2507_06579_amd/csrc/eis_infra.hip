@@ -469,11 +469,12 @@ __global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
     Form f3;
     Gamma gm;
     Chk ck;
+    GiantWork wk;
     square_ideal(4.0 * (double)__uint_as_float((u32)(m1 >> 32)), 4.0 * (double)__uint_as_float((u32)m1),
-                 dd, L, f3, gm, ck);
+                 dd, L, f3, gm, ck, wk);
     const u32 lg = gamma_log(gm, ck);
     double Qk, Pk, Qpk;
-    const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck);
+    const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
     GiantStart g;
     g.Q4 = (float)Qk * 0.25f;
     g.P4 = (float)Pk * 0.25f;
@@ -561,6 +562,9 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     bool active = false;
     u32 my_giants = 0;
     u64 my_steps = 0;
+    // work counts for the instruction model: compositions, their Euclid and
+    // reduction steps, gcd branches, lookups
+    u32 my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
     // the lane's next batch position and its records, loaded one refill
     // ahead so that the loads complete during the giant walk
     u32 npos = n;
@@ -629,11 +633,16 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                 Form f3;
                 Gamma gm;
                 Chk ck;
+                GiantWork wk;
                 compose_ideals(4.0 * (double)m1Q, 4.0 * (double)m1P, 4.0 * (double)cQ,
-                               4.0 * (double)cP, dd, (double)L, f3, gm, ck);
+                               4.0 * (double)cP, dd, (double)L, f3, gm, ck, wk);
                 const u32 lg = gamma_log(gm, ck);
                 double Qk, Pk, Qpk;
-                const u32 Sr = reduce_form(f3, dd, 4.0 * (double)sq, Qk, Pk, Qpk, ck);
+                const u32 Sr = reduce_form(f3, dd, 4.0 * (double)sq, Qk, Pk, Qpk, ck, wk);
+                my_comps++;
+                my_eu += wk.euclid;
+                my_red += wk.reduce;
+                my_gcdb += wk.gcd_branch;
                 const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
                 bad = ck.bad();
                 if (!bad) {
@@ -683,6 +692,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     const u32 *lrs = p.lres + (u64)pos * p.emax;
                     u32 ed, ec;
                     dict_find2(tbl, lst, mask, p.tsize, qb, pa, pc, ed, ec);
+                    my_looks++;
                     if (ed != kNoEntry && ng > 1) {
                         const u32 St = (lrs[ed] >> 1) % 3u;
                         flag = ((Sw + 3u - St) % 3u) == 0u;
@@ -710,14 +720,20 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             }
         }
     }
-    u64 my_giants64 = my_giants;
+    u64 sums[6] = {my_giants, my_comps, my_eu, my_red, my_gcdb, my_looks};
     for (int off = 32; off > 0; off >>= 1) {
         my_steps += __shfl_down(my_steps, off, 64);
-        my_giants64 += __shfl_down(my_giants64, off, 64);
+#pragma unroll
+        for (int k = 0; k < 6; k++) sums[k] += __shfl_down(sums[k], off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&p.ctr->chunk_steps, (unsigned long long)my_steps);
-        atomicAdd(&p.ctr->giant_steps, (unsigned long long)my_giants64);
+        atomicAdd(&p.ctr->giant_steps, (unsigned long long)sums[0]);
+        atomicAdd(&p.ctr->giant_comps, (unsigned long long)sums[1]);
+        atomicAdd(&p.ctr->giant_euclid, (unsigned long long)sums[2]);
+        atomicAdd(&p.ctr->giant_reduce, (unsigned long long)sums[3]);
+        atomicAdd(&p.ctr->giant_gcd_branch, (unsigned long long)sums[4]);
+        atomicAdd(&p.ctr->giant_lookups, (unsigned long long)sums[5]);
     }
 }
 

@@ -67,7 +67,9 @@ struct PassCounters {
     unsigned long long refills;
     unsigned long long giant_steps;
     unsigned long long chunk_steps;  // rho steps inside the giant-step walk
-    u64 pad3[4];
+    // work of the giant walk's compositions (see GiantWork)
+    unsigned long long giant_comps, giant_euclid, giant_reduce, giant_lookups, giant_gcd_branch;
+    u64 pad3[3];
 };
 
 // The fields of a segment that the walk kernels need, kept in LDS.
