@@ -69,7 +69,7 @@ __device__ __forceinline__ bool is_dp(float Q4) { return __builtin_amdgcn_fractf
 
 constexpr u32 kTableMax = 1024;     // largest table (slots) per d
 constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
-constexpr u32 kWalkChunk = 24;      // of which one iteration of the giant walk takes at most this many
+constexpr u32 kWalkChunk = 32;      // of which one iteration of the giant walk takes at most this many
 constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
 constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
 
