@@ -432,9 +432,12 @@ hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t strea
 
 // ---------------------------------------------------------------------------
 // k_giant_square: one lane per batch position whose window left entries: the
-// giant step g = reduce(mu_1^2) by NUDUPL, with its residue.  Every lane runs
-// the same squaring (only the Euclid loops' lengths differ), which keeps
-// NUDUPL out of the giant walk, whose lanes are at different giant steps.
+// giant step g = reduce(mu_1^2) and the second giant ideal g2 = reduce(g^2),
+// both by NUDUPL, with their residues.  Every lane runs the same squarings
+// (only the Euclid loops' lengths differ).  This keeps squarings out of the
+// giant walk, whose lanes are at different giant steps: composed by NUCOMP,
+// the square g g would take NUCOMP's gcd branch with the full norm as gcd,
+// whose long extended Euclid the whole wave would wait for.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double isqrt_f64(double x)
 {
@@ -466,21 +469,32 @@ __global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
     first_step(d, s, P1, Q1, S1);
     const double dd = (double)d;
     const double L = isqrt_f64(s);
-    Form f3;
-    Gamma gm;
+    GiantStart out;
     Chk ck;
     GiantWork wk;
-    square_ideal(4.0 * (double)__uint_as_float((u32)(m1 >> 32)), 4.0 * (double)__uint_as_float((u32)m1),
-                 dd, L, f3, gm, ck, wk);
-    const u32 lg = gamma_log(gm, ck);
-    double Qk, Pk, Qpk;
-    const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
-    GiantStart g;
-    g.Q4 = (float)Qk * 0.25f;
-    g.P4 = (float)Pk * 0.25f;
-    g.Qp4 = (float)Qpk * 0.25f;
-    g.S = ck.bad() ? kSquareBad : (2u * m1S + 3u - lg + Sr) % 3u;
-    p.gstart[pos] = g;
+    // g = reduce(mu_1^2), then g2 = reduce(g^2): log g = 2 log mu_1 - log gamma
+    // + the residues of the reduction steps, and likewise for g2
+    double uQ = 4.0 * (double)__uint_as_float((u32)(m1 >> 32)), uP = 4.0 * (double)__uint_as_float((u32)m1);
+    u32 uS = m1S;
+#pragma unroll 1
+    for (int k = 0; k < 2; k++) {
+        Form f3;
+        Gamma gm;
+        square_ideal(uQ, uP, dd, L, f3, gm, ck, wk);
+        const u32 lg = gamma_log(gm, ck);
+        double Qk, Pk, Qpk;
+        const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
+        GiantIdeal &gi = (k == 0) ? out.g : out.g2;
+        gi.Q4 = (float)Qk * 0.25f;
+        gi.P4 = (float)Pk * 0.25f;
+        gi.Qp4 = (float)Qpk * 0.25f;
+        gi.S = (2u * uS + 3u - lg + Sr) % 3u;
+        uQ = Qk;
+        uP = Pk;
+        uS = gi.S;
+    }
+    if (ck.bad()) out.g.S = kSquareBad;
+    p.gstart[pos] = out;
 }
 
 hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream)
@@ -554,6 +568,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     float L = 0.f;
     float m1Q = 0.f, m1P = 0.f, cQ = 0.f, cP = 0.f;
     u32 m1S = 0, cS = 0;
+    GiantIdeal g2 = {0.f, 0.f, 0.f, 0u};  // the second giant ideal
     float sq = 0.f, sqc = 0.f;
     float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state, quarter units
     u32 Sw = 0, w = 0;
@@ -565,15 +580,15 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     // work counts for the instruction model: compositions, their Euclid and
     // reduction steps, gcd branches, lookups
     u32 my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
-    // the lane's next batch position and its records, loaded one refill
-    // ahead so that the loads complete during the giant walk
+    // the lane's next batch position, its window record and its g, loaded
+    // one refill ahead so that the loads complete during the giant walk
     u32 npos = n;
     wave_take(p.giant_next, n, true, npos, cbase, cend);
     WindowState nst = {0u, 0u, 0u, 0u};
-    GiantStart ngs = {0.f, 0.f, 0.f, 0u};
+    GiantIdeal ngs = {0.f, 0.f, 0.f, 0u};  // its g
     if (npos < n) {
         nst = p.state[npos];
-        ngs = p.gstart[npos];
+        ngs = p.gstart[npos].g;
     }
 
     for (;;) {
@@ -585,11 +600,11 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
             if (want) {
                 pos = npos;
                 const WindowState st = nst;
-                const GiantStart gs = ngs;
+                const GiantIdeal gs = ngs;
                 npos = g;
                 if (g < n) {
                     nst = p.state[g];
-                    ngs = p.gstart[g];
+                    ngs = p.gstart[g].g;
                 }
                 // positions whose flag is out or that went plain are skipped
                 if (st.count != 0u && gs.S == kSquareBad) {
@@ -611,6 +626,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     m1Q = gs.Q4;
                     m1P = gs.P4;
                     m1S = gs.S;
+                    g2 = p.gstart[pos].g2;  // needed a walk later
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;
@@ -629,7 +645,19 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 
         if (active) {
             bool bad = false, done = false, flag = false;
-            if (!walking && ng < p.max_giants) {
+            if (!walking && ng == 1) {
+                // the second giant ideal, squared beforehand
+                Qw = g2.Q4;
+                Pw = g2.P4;
+                Qpw = g2.Qp4;
+                cQ = Qw;
+                cP = Pw;
+                cS = g2.S;
+                Sw = g2.S;
+                w = 0;
+                walking = true;
+                ng++;
+            } else if (!walking && ng < p.max_giants) {
                 Form f3;
                 Gamma gm;
                 Chk ck;

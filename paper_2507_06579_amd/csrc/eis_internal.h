@@ -111,12 +111,16 @@ struct WindowState {
 };
 
 // Per-d start of the giant walk, written by the squaring kernel: the giant
-// step g = reduce(mu_1^2) as a reduced ideal (Q/4, P/4 in fp32, Qp/4 its rho
-// predecessor) and its residue S in Z/3; S = kSquareBad when a check of the
-// squaring failed (the d then goes to the plain walk).
-struct GiantStart {
+// step g = reduce(mu_1^2) and the second giant ideal g2 = reduce(g^2), each
+// as a reduced ideal (Q/4, P/4 in fp32, Qp/4 its rho predecessor) and its
+// residue S in Z/3; S = kSquareBad when a check of the squarings failed (the
+// d then goes to the plain walk).
+struct GiantIdeal {
     float Q4, P4, Qp4;
     u32 S;
+};
+struct GiantStart {
+    GiantIdeal g, g2;
 };
 constexpr u32 kSquareBad = ~0u;
 

@@ -75,12 +75,22 @@ def test_kernel_times_and_step_counts():
         assert sum(ks) == st["baby_steps"] > 0
         k = eis.KERNELS
         assert kl[k.index("sieve")] == 1 and kl[k.index("popcount")] == 1
+        gw = [st[f] for f in ("giant_compositions", "giant_euclid_steps", "giant_reduce_steps",
+                              "giant_gcd_branches", "giant_lookups")]
         if method == eis.Method.BABY:
             assert kl[k.index("walk_plain")] == 1 and kl[k.index("walk_window")] == 0
             assert ks[k.index("walk_plain")] == st["baby_steps"]
+            assert gw == [0, 0, 0, 0, 0]
         else:
             assert kl[k.index("walk_window")] >= 1 and kl[k.index("walk_giant")] >= 1
+            assert kl[k.index("giant_square")] == kl[k.index("walk_giant")]
             assert ks[k.index("walk_window")] > 0 and st["giant_steps"] > 0
+            comps, euclid, red, gcdb, looks = gw
+            # every giant ideal (g, g2 and each composition) is looked up
+            # once, unless a check fails first; every composition runs at
+            # least one Euclid step, and some take NUCOMP's gcd branch
+            assert 0 < comps < st["giant_steps"] and 0 < looks <= st["giant_steps"]
+            assert looks >= comps and euclid > comps and 0 <= gcdb < comps and red >= 0
         assert all(x >= 0 for x in kms)
         assert 0 < sum(kms) <= st["last_total_ms"] * 1.05 + 0.5
     # without the flag nothing is timed
