@@ -250,3 +250,26 @@ def test_window_scale_does_not_change_bits(scale):
         st = ci.eis_get_stats()
     assert np.array_equal(ref[1], got[1]) and ref[3] == got[3]
     _say(f"scale {scale}: giant steps {st['giant_steps']} fallbacks {st['fallbacks']}")
+
+
+def test_small_memory_budget_runs_many_giant_batches():
+    # a budget that leaves room for about 2^16 dictionaries forces the
+    # giant-step method through many batches of one pass; bits and counts
+    # must not depend on that
+    a, b = 4 * 10**10, 4 * 10**10 + 10**7
+    with eis.Context(method=eis.Method.BABY) as cb:
+        ref = cb.eis_classify(a, b)
+    with eis.Context(method=eis.Method.INFRA, mem_budget_bytes=300 << 20,
+                     flags=eis.EIS_FLAG_KERNEL_TIMES) as ci:
+        _say("infra with a 300 MiB budget")
+        got = ci.eis_classify(a, b)
+        st = ci.eis_get_stats()
+    launches = st["kernel_launches"][eis.KERNELS.index("walk_giant")]
+    _say(f"giant-walk launches {launches}")
+    assert launches > 4
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+    assert ref[2:] == got[2:]
+    # a budget below the pass buffers is refused, not crashed
+    with pytest.raises(eis.EisError):
+        with eis.Context(method=eis.Method.INFRA, mem_budget_bytes=64 << 20) as ct:
+            ct.eis_count(a, a + 10**6)
