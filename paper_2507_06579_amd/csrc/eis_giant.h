@@ -393,18 +393,29 @@ __device__ __forceinline__ Form ideal_form(double u, double v, double d, Chk &ba
     return Form{0.5 * u, -v, ex_div(fma(v, v, -d), 2.0 * u, bad)};
 }
 
-// NUCOMPchoose without the small-norm branch, split by its two cases: the
-// form (u3, v3, w3) and gamma with [|2 u3|/2, (-v3 + sqrt d)/2] =
-// (1/gamma) I_1 I_2.  square_ideal is the I_1 = I_2 case (NUDUPL);
-// compose_ideals runs NUCOMP for any pair.  NUCOMP is the general
-// composition and handles I_1 = I_2 through its gcd step: on equal inputs
-// it returns exactly what NUDUPL returns (checked on 6 * 10^4 squares of
-// cycle ideals with d up to 10^12), so a caller whose lanes mix squares and
-// products may send both through NUCOMP and keep every lane on one path.
+// NUCOMPchoose: the form (u3, v3, w3) and gamma with
+// [|2 u3|/2, (-v3 + sqrt d)/2] = (1/gamma) I_1 I_2, split by its cases.
+// square_ideal is the I_1 = I_2 case (NUDUPL); compose_ideals runs NUCOMP for
+// any pair.  NUCOMP is the general composition and handles I_1 = I_2 through
+// its gcd step: on equal inputs it returns exactly what NUDUPL returns
+// (checked on 6 * 10^4 squares of cycle ideals with d up to 10^12), so a
+// caller whose lanes mix squares and products may send both through NUCOMP
+// and keep every lane on one path.
+//
+// The small-norm case (a norm u_k <= 50) takes the plain ideal product,
+// I_1 I_2 = S [u/2, (v + sqrt d)/2] with gamma = S: that is NUCOMP / NUDUPL
+// with the partial reduction switched off (no partial Euclid step, so
+// x = 1, y = 0 and gamma = G, the gcd of the norms and s), here obtained by
+// an infinite bound L.  S is odd (2 is inert, so primitive ideals have odd
+// norm u/2), a 2-unit of residue 0.  The caller's reduction then starts from
+// the unreduced product.
+constexpr double kSmallNorm = 50.0;
+
 __device__ __forceinline__ void square_ideal(double u, double v, double d, double L, Form &f3,
                                              Gamma &g, Chk &bad, GiantWork &wk)
 {
-    nudupl(ideal_form(u, v, d, bad), L, f3, g, bad, wk);
+    const double Lk = (fabs(u) <= kSmallNorm) ? __builtin_inf() : L;
+    nudupl(ideal_form(u, v, d, bad), Lk, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }
 
@@ -412,7 +423,8 @@ __device__ __forceinline__ void compose_ideals(double u1, double v1, double u2, 
                                                double d, double L, Form &f3, Gamma &g, Chk &bad,
                                                GiantWork &wk)
 {
-    nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), L, f3, g, bad, wk);
+    const double Lk = (fabs(u1) <= kSmallNorm || fabs(u2) <= kSmallNorm) ? __builtin_inf() : L;
+    nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), Lk, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }
 
