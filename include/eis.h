@@ -96,7 +96,7 @@ typedef enum {
     EIS_K_WALK_GIANT = 5,    /* giant-step method: giant steps with lookups */
     EIS_K_WALK_HANDOFF = 6,  /* plain walk of the d's the giant-step method handed off */
     EIS_K_POPCOUNT = 7,      /* per-segment counts */
-    EIS_K_GIANT_SQUARE = 8,  /* giant-step method: the giant step g = mu_1^2 (NUDUPL) */
+    EIS_K_GIANT_SQUARE = 8,  /* giant-step method: g = mu_1^2 and g^2 (NUDUPL) */
     EIS_K_COUNT = 9
 } eis_kernel;
 

@@ -1,34 +1,36 @@
 // eis_infra.hip -- the infrastructure method of Appendix A on gfx950.
 //
 // Algorithm "Infrastructure" with the generators carried in
-// (O_K/2O_K)^* ~ Z/3, split into three kernels so that every lane of a wave
+// (O_K/2O_K)^* ~ Z/3, split into four kernels so that every lane of a wave
 // runs the same phase:
 //
 //   k_walk_window  one d per lane: reduction steps from (1), with the
 //                  half-period symmetry exit; the "distinguished" ideals of
 //                  the walk (Q = 2 mod 64, about one in 16) are appended to
 //                  the d's dictionary list (the ideal's (Q/4, P/4) as fp32
-//                  bits, and twice its residue sum beside it).  mu_1 is the n-th distinguished
-//                  ideal (n = wscale * d^(1/4) / 16, at least 16); the
-//                  window ends at the first distinguished ideal at least six
-//                  steps after mu_1 (the two extra ideals of the algorithm,
-//                  with margin), and that extension must stay within
-//                  mu_1's own step count.
+//                  bits, and twice its residue sum beside it).  mu_1 is the
+//                  n-th distinguished ideal (n = wscale * d^(1/4) / 16, at
+//                  least 16); the window ends at the first distinguished
+//                  ideal at least six steps after mu_1 (the two extra ideals
+//                  of the algorithm, with margin), and that extension must
+//                  stay within mu_1's own step count.
 //   k_build_tables one wave per d: the list is indexed by an open-addressed
 //                  hash table of 16-bit slots (9-bit list index + 7-bit
 //                  fingerprint; a fingerprint match is confirmed against the
 //                  list entry), built in LDS and written out whole.
-//   k_walk_giant   one d per lane, lanes refilled from a queue: the giant
-//                  step is g = reduce(mu_1^2) (NUDUPL), then g_k =
-//                  reduce(g * g_{k-1}) (NUCOMP), the residue updated with
-//                  log g + log g_{k-1} - log gamma + the residues of the
-//                  reduction steps; then reduction steps forward to the first
-//                  distinguished ideal, which is looked up twice: itself (a
-//                  hit means one period past a window ideal: log eps =
-//                  log(ideal) - log(window ideal)) and its conjugate (one
-//                  period short of a window ideal: log eps = log(ideal) +
-//                  log(window ideal)).  The dictionary thus covers distances
-//                  on both sides of (1), and the giant step can be twice mu_1.
+//   k_giant_square one lane per d: the giant step g = reduce(mu_1^2) and the
+//                  second giant ideal reduce(g^2), by NUDUPL.
+//   k_walk_giant   one d per lane, lanes refilled from a queue: starting
+//                  from g and g^2, the giant ideals g_k = reduce(g * g_{k-1})
+//                  (NUCOMP), the residue updated with log g + log g_{k-1} -
+//                  log gamma + the residues of the reduction steps; after
+//                  each, reduction steps forward to the first distinguished
+//                  ideal, which is looked up twice: itself (a hit means one
+//                  period past a window ideal: log eps = log(ideal) -
+//                  log(window ideal)) and its conjugate (one period short of
+//                  a window ideal: log eps = log(ideal) + log(window ideal)).
+//                  The dictionary thus covers distances on both sides of
+//                  (1), and the giant step can be twice mu_1.
 //
 // Why the distinguished ideals: a dictionary with every window ideal would
 // cost one scattered 8-byte store per reduction step.  With only every 16th
