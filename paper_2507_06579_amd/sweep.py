@@ -204,6 +204,7 @@ def run(xmax: int, width: int, checkpoint: str, per_call: int = 8, ctx=None, log
     if own:
         ctx = eis.Context()
     t0 = time.perf_counter()
+    st0 = ctx.eis_get_stats()
     try:
         for i in range(0, len(todo), per_call):
             part = todo[i:i + per_call]
@@ -213,11 +214,17 @@ def run(xmax: int, width: int, checkpoint: str, per_call: int = 8, ctx=None, log
             save_checkpoint(checkpoint, xmax, width, done, which)
             log(f"[sweep] up to {part[-1][1]:.3e}: {len(done)} segments, "
                 f"{time.perf_counter() - t0:.1f} s")
+        st1 = ctx.eis_get_stats()
     finally:
         if own:
             ctx.close()
     out = summarise(done, xmax, which)
     out["seconds"] = round(time.perf_counter() - t0, 2)
+    # work of this run (segments restored from a checkpoint are not in it):
+    # members of D classified, reduction steps, giant steps, and the d's the
+    # giant-step method handed to the plain walk
+    out["work"] = {k: st1[k] - st0[k] for k in ("discriminants", "baby_steps", "giant_steps",
+                                                 "fallbacks")}
     return out
 
 

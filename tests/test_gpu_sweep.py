@@ -24,6 +24,8 @@ def test_sweep_to_1e8_and_resume(tmp_path):
     _say("sweep to 1e8")
     full = sweep.run(10**8, 10**9, cp, per_call=3, log=_say)
     assert full["pi_E"] == TABLE1_FIRST
+    # a fresh run classifies every member of D once
+    assert full["work"]["discriminants"] == full["pi_D"]
     pw = {p["x"]: p for p in full["powers_of_ten"]}
     for k in range(1, 7):
         ref = oracle.classify_range(0, 10**k, want_bits=False)
