@@ -192,7 +192,7 @@ def summarise(done: dict, xmax: int, which: str = "squarefree"):
 
 
 def run(xmax: int, width: int, checkpoint: str, per_call: int = 8, ctx=None, log=print,
-        which: str = "squarefree"):
+        which: str = "squarefree", tune: bool = False):
     from . import _lib as eis
     if which not in SETS:
         raise ValueError(f"set must be one of {SETS}")
@@ -204,6 +204,10 @@ def run(xmax: int, width: int, checkpoint: str, per_call: int = 8, ctx=None, log
     if own:
         ctx = eis.Context()
     t0 = time.perf_counter()
+    if tune:
+        # method and window scale per half-decade of height (timed below)
+        ctx.eis_tune()
+        log(f"[sweep] autotuner: {time.perf_counter() - t0:.1f} s")
     st0 = ctx.eis_get_stats()
     try:
         for i in range(0, len(todo), per_call):
@@ -236,11 +240,14 @@ def main(argv=None):
     ap.add_argument("--out", default="", help="write the summary here (JSON)")
     ap.add_argument("--per-call", type=int, default=8, help="segments per eis_count_batch")
     ap.add_argument("--primes", action="store_true", help="sweep the prime subsequence")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner first (about 1.5 s; the untuned defaults are as fast "
+                         "on this sweep)")
     args = ap.parse_args(argv)
     xmax, width = int(args.max), int(args.width)
     res = run(xmax, width, args.checkpoint, args.per_call,
               log=lambda m: print(m, file=sys.stderr, flush=True),
-              which="prime" if args.primes else "squarefree")
+              which="prime" if args.primes else "squarefree", tune=args.tune)
     text = json.dumps(res)
     if args.out:
         with open(args.out, "w") as f:
