@@ -142,9 +142,10 @@ def main():
     ap.add_argument("--serve-n", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the per-d walks "
-                                   "are independent, and sharding ranges across GPUs is "
-                                   "described in DESIGN.md but not run"}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the per-d walks "
+                                   "are independent, so a range would shard into blocks of "
+                                   "equal estimated cost, one per GPU, whose two counts are "
+                                   "summed; that sharding is not run here"}), flush=True)
         sys.exit(2)
 
     import torch
