@@ -117,10 +117,28 @@ def cpu_baseline(a: int, b: int, target_s: float = 15.0):
     t = time.perf_counter()
     _, steps = oracle.classify_list(sample, nthreads=cores)
     dt = time.perf_counter() - t
+    # one thread, on a sample sized for about 3 s
+    k1 = max(1, min(sample.size, int(sample.size * 3.0 / (dt * cores))))
+    t = time.perf_counter()
+    oracle.classify_list(sample[:k1], nthreads=1)
+    rate1 = k1 / (time.perf_counter() - t)
     return {"value": round(sample.size / dt, 2), "unit": "discriminants/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{sample.size} random members of D in [{a}, {b}), full-period walk "
-                      f"({steps} rho steps, {dt:.1f} s on {cores} threads)"}
+                      f"({steps} rho steps, {dt:.1f} s on {cores} threads of {cpu_model()}); "
+                      f"one thread: {rate1:.1f} discriminants/s on {k1} of them"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or 'unknown CPU'."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def main():
