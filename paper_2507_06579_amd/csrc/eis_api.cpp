@@ -54,6 +54,9 @@ constexpr u64 kDefaultInfraMinHeight = 100000000ull;
 constexpr u64 kInfraBatchMin = u64(1) << 16;
 constexpr u64 kPrimeLimit = 1000000;  // isqrt(EIS_MAX_D - 1) = 999999
 constexpr u32 kPassWords = (u32)(kPassCandidates / 32) + kMaxSegments;
+// queue heads of the giant-step method (three cache lines) and the task
+// counts of its cost buckets (one line each), in 32-bit words
+constexpr u32 kQueueWords = (3 + kCostBuckets) * 16;
 constexpr u32 kDefaultServeSlots = 64;
 // serving: candidates of one request per pass (a larger request advances a
 // chunk per pass, so that requests behind it are not held up)
@@ -155,7 +158,8 @@ struct eis_ctx {
     u64 counts_cap = 0;              // pairs
     unsigned long long *h_counts = nullptr;  // pinned
     u64 h_counts_cap = 0;
-    u32 *d_q = nullptr;              // giant-step queue heads (3 cache lines)
+    u32 *d_q = nullptr;              // giant-step queue heads (3 cache lines), then the task
+                                     // counts of the cost buckets (one line each)
     bool pass_ready = false;
     bool uncollected = false;            // a pass whose counters nobody has read yet
     hipStream_t pending_stream = nullptr;  // the stream it runs on
@@ -168,7 +172,7 @@ struct eis_ctx {
 
     // giant-step scratch
     WindowState *d_state = nullptr;
-    GiantStart *d_gstart = nullptr;
+    GiantTask *d_tasks = nullptr;  // kCostBuckets buckets of infra_batch_cap tasks
     unsigned long long *d_lists = nullptr;
     u32 *d_lres = nullptr;
     u16 *d_tables = nullptr;
@@ -294,12 +298,12 @@ static void load_tune_cache(eis_ctx *c)
 static void free_infra(eis_ctx *c)
 {
     (void)hipFree(c->d_state);
-    (void)hipFree(c->d_gstart);
+    (void)hipFree(c->d_tasks);
     (void)hipFree(c->d_lists);
     (void)hipFree(c->d_lres);
     (void)hipFree(c->d_tables);
     c->d_state = nullptr;
-    c->d_gstart = nullptr;
+    c->d_tasks = nullptr;
     c->d_lists = nullptr;
     c->d_lres = nullptr;
     c->d_tables = nullptr;
@@ -452,7 +456,7 @@ static int ensure_pass_buffers(eis_ctx *c)
 {
     if (c->pass_ready) return EIS_OK;
     const u64 need = kMaxSegments * sizeof(SegInfo) + 2ull * kPassWords * 4 +
-                     3ull * kPassCandidates * 4 + 3 * sizeof(PassCounters) + 3 * 64;
+                     3ull * kPassCandidates * 4 + 3 * sizeof(PassCounters) + kQueueWords * 4;
     if (c->bytes_held + need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_segs), kMaxSegments * sizeof(SegInfo),
@@ -463,7 +467,7 @@ static int ensure_pass_buffers(eis_ctx *c)
         hipMalloc(&c->d_list_giant, kPassCandidates * 4) != hipSuccess ||
         hipMalloc(&c->d_fb_list, kPassCandidates * 4) != hipSuccess ||
         hipMalloc(&c->d_ctrs, 3 * sizeof(PassCounters)) != hipSuccess ||
-        hipMalloc(&c->d_q, 3 * 64) != hipSuccess)
+        hipMalloc(&c->d_q, kQueueWords * 4) != hipSuccess)
         return EIS_ENOMEM;
     c->bytes_held += need;
     c->pass_ready = true;
@@ -507,6 +511,14 @@ static int ensure_counts(eis_ctx *c, u64 pairs)
     return EIS_OK;
 }
 
+// Device bytes per d of the giant-step method: the list (8-byte keys and
+// 4-byte residue sums), the table, the window record and a task slot in
+// every cost bucket.
+static u64 infra_bytes_per_d(u32 emax, u32 tsize)
+{
+    return (u64)emax * 12 + (u64)tsize * 2 + sizeof(WindowState) + kCostBuckets * sizeof(GiantTask);
+}
+
 // Scratch of the giant-step method: `batch` d's (whole tiles of 64), `emax`
 // list entries and `tsize` table slots each.
 static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
@@ -517,13 +529,13 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * ((u64)emax * 12 + (u64)tsize * 2 + sizeof(WindowState) + sizeof(GiantStart));
+    const u64 bytes = cap * infra_bytes_per_d(emax, tsize);
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
         hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
         hipMalloc(&c->d_tables, cap * tsize * 2) != hipSuccess ||
         hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
-        hipMalloc(&c->d_gstart, cap * sizeof(GiantStart)) != hipSuccess) {
+        hipMalloc(&c->d_tasks, cap * kCostBuckets * sizeof(GiantTask)) != hipSuccess) {
         free_infra(c);
         return EIS_ENOMEM;
     }
@@ -644,7 +656,7 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     pl.grid_fb = (u32)c->num_cu;
     if (pl.giant_cand) {
         infra_geometry(nmax_giant, pl.emax, pl.tsize);
-        const u64 per_d = (u64)pl.emax * 12 + (u64)pl.tsize * 2 + sizeof(WindowState) + sizeof(GiantStart);
+        const u64 per_d = infra_bytes_per_d(pl.emax, pl.tsize);
         const u64 held = c->bytes_held - c->infra_bytes;  // other buffers of the context
         const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
         const u64 fit = std::max<u64>(avail / per_d / kInfraBatchMin * kInfraBatchMin, kInfraBatchMin);
@@ -747,7 +759,9 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.fb_list = c->d_fb_list;
         ip.fb_ctr = ctr_fb;
         ip.state = c->d_state;
-        ip.gstart = c->d_gstart;
+        ip.tasks = c->d_tasks;
+        ip.task_cap = (u32)c->infra_batch_cap;
+        ip.gbuckets = c->d_q + 3 * 16;
         ip.lists = c->d_lists;
         ip.lres = c->d_lres;
         ip.tables = c->d_tables;
@@ -758,7 +772,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.eis_words = c->d_eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
-            HIP_TRY(launch_zero_u32(c->d_q, 3 * 16, st));
+            HIP_TRY(launch_zero_u32(c->d_q, kQueueWords, st));
             KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, st));
             KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, pl.grid_tables, st));
             KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, st));

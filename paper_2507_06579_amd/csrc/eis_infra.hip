@@ -433,13 +433,14 @@ hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t strea
 }
 
 // ---------------------------------------------------------------------------
-// k_giant_square: one lane per batch position whose window left entries: the
+// k_giant_square: for each batch position whose window left entries, the
 // giant step g = reduce(mu_1^2) and the second giant ideal g2 = reduce(g^2),
 // both by NUDUPL, with their residues.  Every lane runs the same squarings
 // (only the Euclid loops' lengths differ).  This keeps squarings out of the
 // giant walk, whose lanes are at different giant steps: composed by NUCOMP,
 // the square g g would take NUCOMP's gcd branch with the full norm as gcd,
-// whose long extended Euclid the whole wave would wait for.
+// whose long extended Euclid the whole wave would wait for.  The d's task
+// (position, item, g, g2) goes into its cost bucket (below).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double isqrt_f64(double x)
 {
@@ -452,57 +453,152 @@ __device__ __forceinline__ double isqrt_f64(double x)
     return r;
 }
 
+// Cost order.  A d's giant walk is about R / log g giant steps long, R its
+// regulator, and by the analytic class number formula h R = sqrt(d)
+// L(1, chi_d) / 2.  In a persistent walk that takes the d's in list order,
+// the long walks that start late leave most lanes idle at the end.  The
+// estimate below orders the d's by L(1, chi_d) / h instead: the Euler
+// factors p / (p - chi(p)) of L at the odd primes up to 97 (chi(p) the
+// Legendre symbol (d/p)) and a factor 1/2 for each of these primes that
+// divides d (each prime factor of d beyond the first adds one to the 2-rank
+// of the narrow class group, by genus theory).  Its distribution over D
+// depends only on d modulo these primes, so it is the same at every height;
+// the bucket edges are its eighths over D (log scale).  The estimate only
+// orders the work: every order gives the same results.
+constexpr u32 kCostPrimes[24] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41,
+                                 43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97};
+struct QrMasks {
+    u64 m[24][2];  // bit r set iff r is a nonzero square mod the prime
+};
+constexpr QrMasks make_qr_masks()
+{
+    QrMasks t{};
+    for (int i = 0; i < 24; i++) {
+        const u32 pr = kCostPrimes[i];
+        for (u32 x = 1; x < pr; x++) {
+            const u32 r = x * x % pr;
+            t.m[i][r >> 6] |= 1ull << (r & 63);
+        }
+    }
+    return t;
+}
+constexpr QrMasks kQrMasks = make_qr_masks();
+constexpr float kCostEdges[kCostBuckets - 1] = {0.236f, -0.124f, -0.400f, -0.660f,
+                                                 -0.930f, -1.237f, -1.674f};
+
+__device__ __forceinline__ u32 cost_bucket(u64 d)
+{
+    const double dd = (double)d;  // d < 2^53: exact
+    float f = 1.f;
+#pragma unroll
+    for (int i = 0; i < 24; i++) {
+        const double pr = (double)kCostPrimes[i];
+        const double q = floor(dd * (1.0 / pr));
+        double r = fma(-q, pr, dd);  // exact; within one p of d mod p
+        r = (r < 0.0) ? r + pr : r;
+        r = (r >= pr) ? r - pr : r;
+        const u32 ri = (u32)r;
+        const u64 lo = kQrMasks.m[i][0], hi = kQrMasks.m[i][1];  // immediates
+        const u64 mw = (ri < 64) ? lo : hi;
+        const bool sq = (mw >> (ri & 63)) & 1ull;
+        const float up = (float)(pr / (pr - 1.0)), down = (float)(pr / (pr + 1.0));
+        f *= (ri == 0) ? 0.5f : (sq ? up : down);
+    }
+    const float e = __logf(f);
+    u32 b = 0;
+#pragma unroll
+    for (u32 k = 0; k < kCostBuckets - 1; k++) b += (e < kCostEdges[k]) ? 1u : 0u;
+    return b;
+}
+
+// Positions per thread.  A workgroup handles 256 kSquarePerThread positions
+// and reserves its tasks' slots with one atomic per bucket: device-wide
+// atomics on the same counter are serialised, so one reservation per 256
+// positions would cost more than the squarings.
+constexpr u32 kSquarePerThread = 4;
+
 __global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
 {
     __shared__ SegLds segs[kMaxSegments];
-    load_segs(segs, p.segs, p.nseg);
+    __shared__ u32 bcount[kCostBuckets], bbase[kCostBuckets];
+    if (threadIdx.x < kCostBuckets) bcount[threadIdx.x] = 0u;
+    load_segs(segs, p.segs, p.nseg);  // ends with a barrier
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
-    const u32 pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= n) return;
-    const WindowState st = p.state[pos];
-    if (st.count == 0u) return;
-    const u32 e1 = st.emain - 1;
-    const unsigned long long m1 = p.lists[(u64)pos * p.emax + e1];
-    const u32 m1S = (p.lres[(u64)pos * p.emax + e1] >> 1) % 3u;
-    const u64 d = item_d(segs, st.item);
-    double s, P1, Q1;
-    u32 S1;
-    first_step(d, s, P1, Q1, S1);
-    const double dd = (double)d;
-    const double L = isqrt_f64(s);
-    GiantStart out;
-    Chk ck;
-    GiantWork wk;
-    // g = reduce(mu_1^2), then g2 = reduce(g^2): log g = 2 log mu_1 - log gamma
-    // + the residues of the reduction steps, and likewise for g2
-    double uQ = 4.0 * (double)__uint_as_float((u32)(m1 >> 32)), uP = 4.0 * (double)__uint_as_float((u32)m1);
-    u32 uS = m1S;
-#pragma unroll 1
-    for (int k = 0; k < 2; k++) {
-        Form f3;
-        Gamma gm;
-        square_ideal(uQ, uP, dd, L, f3, gm, ck, wk);
-        const u32 lg = gamma_log(gm, ck);
-        double Qk, Pk, Qpk;
-        const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
-        GiantIdeal &gi = (k == 0) ? out.g : out.g2;
-        gi.Q4 = (float)Qk * 0.25f;
-        gi.P4 = (float)Pk * 0.25f;
-        gi.Qp4 = (float)Qpk * 0.25f;
-        gi.S = (2u * uS + 3u - lg + Sr) % 3u;
-        uQ = Qk;
-        uP = Pk;
-        uS = gi.S;
+    const u32 pos0 = blockIdx.x * (256u * kSquarePerThread) + threadIdx.x;
+    // Phase 1: the bucket of each position that takes giant steps and its
+    // rank there within the workgroup (packed: rank << 8 | bucket; 0xff =
+    // no task); then one reservation per bucket.
+    u32 slot[kSquarePerThread];
+#pragma unroll
+    for (u32 j = 0; j < kSquarePerThread; j++) {
+        const u32 pos = pos0 + 256u * j;
+        slot[j] = 0xffu;
+        if (pos < n) {
+            const WindowState st = p.state[pos];
+            if (st.count != 0u) {
+                const u32 b = cost_bucket(item_d(segs, st.item));
+                slot[j] = (atomicAdd(&bcount[b], 1u) << 8) | b;
+            }
+        }
     }
-    if (ck.bad()) out.g.S = kSquareBad;
-    p.gstart[pos] = out;
+    __syncthreads();
+    if (threadIdx.x < kCostBuckets)
+        bbase[threadIdx.x] = bcount[threadIdx.x] ? atomicAdd(&p.gbuckets[16 * threadIdx.x], bcount[threadIdx.x]) : 0u;
+    __syncthreads();
+    // Phase 2: the squarings, each task written to its slot.  A failed check
+    // leaves the task in its bucket; the walk hands it to the plain walk.
+#pragma unroll 1
+    for (u32 j = 0; j < kSquarePerThread; j++) {
+        if (slot[j] == 0xffu) continue;
+        const u32 pos = pos0 + 256u * j;
+        const WindowState st = p.state[pos];
+        const u32 e1 = st.emain - 1;
+        const unsigned long long m1 = p.lists[(u64)pos * p.emax + e1];
+        const u32 m1S = (p.lres[(u64)pos * p.emax + e1] >> 1) % 3u;
+        const u64 d = item_d(segs, st.item);
+        double s, P1, Q1;
+        u32 S1;
+        first_step(d, s, P1, Q1, S1);
+        const double dd = (double)d;
+        const double L = isqrt_f64(s);
+        GiantTask out;
+        Chk ck;
+        GiantWork wk;
+        // g = reduce(mu_1^2), then g2 = reduce(g^2): log g = 2 log mu_1 - log
+        // gamma + the residues of the reduction steps, and likewise for g2
+        double uQ = 4.0 * (double)__uint_as_float((u32)(m1 >> 32)), uP = 4.0 * (double)__uint_as_float((u32)m1);
+        u32 uS = m1S;
+#pragma unroll 1
+        for (int k = 0; k < 2; k++) {
+            Form f3;
+            Gamma gm;
+            square_ideal(uQ, uP, dd, L, f3, gm, ck, wk);
+            const u32 lg = gamma_log(gm, ck);
+            double Qk, Pk, Qpk;
+            const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
+            GiantIdeal &gi = (k == 0) ? out.g : out.g2;
+            gi.Q4 = (float)Qk * 0.25f;
+            gi.P4 = (float)Pk * 0.25f;
+            gi.Qp4 = (float)Qpk * 0.25f;
+            gi.S = (2u * uS + 3u - lg + Sr) % 3u;
+            uQ = Qk;
+            uP = Pk;
+            uS = gi.S;
+        }
+        out.pos = pos;
+        out.item = st.item;
+        if (ck.bad()) out.g.S = kSquareBad;
+        const u32 b = slot[j] & 0xffu;
+        p.tasks[(u64)b * p.task_cap + bbase[b] + (slot[j] >> 8)] = out;
+    }
 }
 
 hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream)
 {
     if (p.batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_giant_square, dim3((p.batch + 255) / 256), dim3(256), 0, stream, p);
+    const u32 per_block = 256u * kSquarePerThread;
+    hipLaunchKernelGGL(k_giant_square, dim3((p.batch + per_block - 1) / per_block), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -549,8 +645,9 @@ __device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long l
     }
 }
 
-// One d per lane, lanes refilled from a queue; a lane starts at g (from the
-// squaring kernel).  Two phases per iteration: a lane that is not walking
+// One d per lane, lanes refilled from a queue over the squaring kernel's
+// tasks, bucket 0 (longest estimated walks) first; a lane starts at g.  Two
+// phases per iteration: a lane that is not walking
 // composes (and reduces) its next giant ideal c_{k+1} = reduce(g c_k) by
 // NUCOMP; then every walking lane takes up to kWalkChunk reduction steps
 // towards the next distinguished ideal and, on reaching it, looks it up.  A
@@ -559,9 +656,24 @@ __device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long l
 __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
 {
     __shared__ SegLds segs[kMaxSegments];
-    load_segs(segs, p.segs, p.nseg);
-    const u32 total = p.list_ctr->list_len;
-    const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
+    __shared__ u32 bstart[kCostBuckets + 1];  // queue index of each bucket's first task
+    if (threadIdx.x == 0) {
+        u32 acc = 0;
+        for (u32 b = 0; b < kCostBuckets; b++) {
+            bstart[b] = acc;
+            acc += p.gbuckets[16 * b];
+        }
+        bstart[kCostBuckets] = acc;
+    }
+    load_segs(segs, p.segs, p.nseg);  // ends with a barrier
+    const u32 n = bstart[kCostBuckets];
+    // the task of queue index q < n
+    auto task_of = [&](u32 q) -> const GiantTask * {
+        u32 b = 0;
+#pragma unroll
+        for (u32 k = 1; k < kCostBuckets; k++) b += (q >= bstart[k]) ? 1u : 0u;
+        return p.tasks + (u64)b * p.task_cap + (q - bstart[b]);
+    };
     const u32 mask = p.tsize - 1;
     // per-lane state; the giant step g and the current giant ideal c are
     // reduced ideals, kept like the walk in fp32 quarter units (exact)
@@ -582,39 +694,42 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     // work counts for the instruction model: compositions, their Euclid and
     // reduction steps, gcd branches, lookups
     u32 my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
-    // the lane's next batch position, its window record and its g, loaded
-    // one refill ahead so that the loads complete during the giant walk
-    u32 npos = n;
-    wave_take(p.giant_next, n, true, npos, cbase, cend);
-    WindowState nst = {0u, 0u, 0u, 0u};
+    // the lane's next task (queue index nq) and its position, item and g,
+    // loaded one refill ahead so that the loads complete during the giant walk
+    u32 nq = n;
+    wave_take(p.giant_next, n, true, nq, cbase, cend);
+    u32 npos = 0, nitem = 0;
     GiantIdeal ngs = {0.f, 0.f, 0.f, 0u};  // its g
-    if (npos < n) {
-        nst = p.state[npos];
-        ngs = p.gstart[npos].g;
+    if (nq < n) {
+        const GiantTask *t = task_of(nq);
+        npos = t->pos;
+        nitem = t->item;
+        ngs = t->g;
     }
 
     for (;;) {
         for (;;) {
-            const bool want = !active && npos < n;
+            const bool want = !active && nq < n;
             if (!__any(want)) break;
             u32 g = n;
             wave_take(p.giant_next, n, want, g, cbase, cend);
             if (want) {
+                const GiantTask *cur = task_of(nq);
                 pos = npos;
-                const WindowState st = nst;
+                item = nitem;
                 const GiantIdeal gs = ngs;
-                npos = g;
+                nq = g;
                 if (g < n) {
-                    nst = p.state[g];
-                    ngs = p.gstart[g].g;
+                    const GiantTask *t = task_of(g);
+                    npos = t->pos;
+                    nitem = t->item;
+                    ngs = t->g;
                 }
-                // positions whose flag is out or that went plain are skipped
-                if (st.count != 0u && gs.S == kSquareBad) {
+                if (gs.S == kSquareBad) {
                     const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                    p.fb_list[f] = st.item;
+                    p.fb_list[f] = item;
                     my_giants += 1;
-                } else if (st.count != 0u) {
-                    item = st.item;
+                } else {
                     idx = item_bit(segs, item);
                     const u64 d = item_d(segs, item);
                     double s64, P1, Q1;
@@ -628,7 +743,7 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
                     m1Q = gs.Q4;
                     m1P = gs.P4;
                     m1S = gs.S;
-                    g2 = p.gstart[pos].g2;  // needed a walk later
+                    g2 = cur->g2;  // needed a walk later
                     cQ = m1Q;
                     cP = m1P;
                     cS = m1S;

@@ -110,19 +110,25 @@ struct WindowState {
     u32 pad;
 };
 
-// Per-d start of the giant walk, written by the squaring kernel: the giant
-// step g = reduce(mu_1^2) and the second giant ideal g2 = reduce(g^2), each
-// as a reduced ideal (Q/4, P/4 in fp32, Qp/4 its rho predecessor) and its
-// residue S in Z/3; S = kSquareBad when a check of the squarings failed (the
-// d then goes to the plain walk).
+// Per-d task of the giant walk, written by the squaring kernel: the d's
+// batch position and work item, the giant step g = reduce(mu_1^2) and the
+// second giant ideal g2 = reduce(g^2), each as a reduced ideal (Q/4, P/4 in
+// fp32, Qp/4 its rho predecessor) and its residue S in Z/3; g.S = kSquareBad
+// when a check of the squarings failed (the d then goes to the plain walk).
 struct GiantIdeal {
     float Q4, P4, Qp4;
     u32 S;
 };
-struct GiantStart {
+struct GiantTask {
+    u32 pos, item;
     GiantIdeal g, g2;
 };
 constexpr u32 kSquareBad = ~0u;
+
+// The squaring kernel sorts the tasks into kCostBuckets buckets by estimated
+// walk length (bucket 0 longest), each bucket an array of task_cap tasks; the
+// giant walk takes bucket 0 first.  Bucket b's task count is gbuckets[16 b].
+constexpr u32 kCostBuckets = 8;
 
 struct InfraParams {
     const SegInfo *segs;        // segment table of the pass
@@ -136,7 +142,9 @@ struct InfraParams {
     u32 *fb_list;               // items handed to the plain walk
     PassCounters *fb_ctr;       // fb_ctr->list_len counts fb_list
     WindowState *state;         // per batch position
-    GiantStart *gstart;         // per batch position (d's with count > 0)
+    GiantTask *tasks;           // kCostBuckets buckets of task_cap tasks
+    u32 task_cap;               // tasks per bucket (>= batch)
+    u32 *gbuckets;              // task counts of the buckets (one cache line each)
     unsigned long long *lists;  // window lists: entry e of batch position k at
                                 // k * emax + e; an entry is the ideal's
                                 // (Q/4, P/4) as fp32 bits
