@@ -280,10 +280,15 @@ def main():
         k = eis.KERNELS.index(name)
         if name == dom or not kl[k] or not ks[k]:
             continue
-        sl, _, _, _ = slot_model(name)
+        sl, un, uw, md = slot_model(name)
         a_k = sl / (kms[k] / 1e3)
         others[name] = {"achieved": round(a_k / 1e12, 3), "frac": round(a_k / PEAK_LANE_OPS, 4),
-                        "ms_per_step": round(kms[k] / args.steps, 3)}
+                        "ms_per_step": round(kms[k] / args.steps, 3),
+                        "avg_launch_ms": round(kms[k] / kl[k], 3),
+                        "ops_per_unit": round(sl / max(1, un), 1), "unit_of_work": uw,
+                        "units_per_launch": int(un / kl[k])}
+        if md:
+            others[name]["model"] = md
     roofline["traffic"] = measured_traffic(roofline["kernel"], f"large:{chosen.name.lower()}")
     out = {
         "metric": METRIC,
