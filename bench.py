@@ -35,13 +35,17 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # another VALU instruction of the same quad-cycle (no slot of their own).
 # Plain walk: 11 VALU + rcp: the biased quotient (fma, mul, floor), the
 # overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma) and
-# two exit tests -> 11 + 1 - 2 = 10 slots.  Window walk: the same step plus
-# the distinguished-ideal test (mul, fract, cmp): 12 slots, the list append
-# (15 VALU for the LDS staging, count, residue sum and mu_1 bookkeeping),
-# which runs for the wave whenever any of its 64 lanes appends, i.e. at
-# nearly every step (1 - (15/16)^64 = 0.98), and the window-end tests once
-# per two steps: 28 slots.
-VALU_SLOTS_PER_STEP = {"walk_plain": 10.0, "walk_handoff": 10.0, "walk_window": 28.0}
+# two exit tests -> 11 + 2 (rcp) - 2 (floor, fract) = 11 slots.
+VALU_SLOTS_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0}
+# Window walk, per lane path like the giant walk's model: per rho step the
+# same step (11), the distinguished-ideal test (mul, fract, cmp: 2) and the
+# window-end tests (2 per pair: 1); per distinguished ideal
+# appended (counted by the kernel, eis_stats.window_entries) the append: the
+# selection of the pair's first distinguished ideal, LDS staging, count,
+# residue sum and mu_1 bookkeeping (18 VALU) and an eighth of a chunk
+# write-out (3 VALU).  The wave runs the append whenever any of its lanes
+# appends; the lanes that do not append are not counted.
+WINDOW_SLOTS = {"rho_steps": 14.0, "entries": 18.375}
 # Giant-step walk: VALU issue slots per unit of its work, counted the same
 # way in the gfx950 code of the built kernel (per-lane path; a branch that a
 # lane does not take is not counted for it), the units being counted by the
@@ -238,12 +242,18 @@ def main():
                              "rho_steps_per_step": ks[k] // args.steps}
     # dominant kernel: the walk kernel with the largest share of the step
     # (the other kernels of a pass take a few percent of it)
-    walks = list(VALU_SLOTS_PER_STEP) + ["walk_giant"]
+    walks = list(VALU_SLOTS_PER_STEP) + ["walk_window", "walk_giant"]
 
     def slot_model(name):
         """(VALU slots, units of work, unit name, model details) of the
         timed launches of a walk kernel."""
         k = eis.KERNELS.index(name)
+        if name == "walk_window":
+            work = {"rho_steps": ks[k], "entries": st["window_entries"] - base["window_entries"]}
+            slots = sum(WINDOW_SLOTS[key] * v for key, v in work.items())
+            return (slots, ks[k], "rho step",
+                    {"slots": WINDOW_SLOTS,
+                     "work_per_launch": {key: int(v / kl[k]) for key, v in work.items()}})
         if name != "walk_giant":
             return VALU_SLOTS_PER_STEP[name] * ks[k], ks[k], "rho step", None
         work = {key: st["giant_" + key] - base["giant_" + key]

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 4
+#define EIS_ABI_VERSION 5
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -137,6 +137,9 @@ typedef struct {
     uint64_t giant_reduce_steps;
     uint64_t giant_gcd_branches;
     uint64_t giant_lookups;
+    /* distinguished ideals the window walk appended to the dictionary lists
+     * (the operation count of its list-append path) */
+    uint64_t window_entries;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */

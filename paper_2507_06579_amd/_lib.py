@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
-ABI_VERSION = 4  # must match EIS_ABI_VERSION of include/eis.h
+ABI_VERSION = 5  # must match EIS_ABI_VERSION of include/eis.h
 EIS_SET_SQUAREFREE = 0
 EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
@@ -81,6 +81,7 @@ class EisStats(ctypes.Structure):
         ("giant_reduce_steps", ctypes.c_uint64),
         ("giant_gcd_branches", ctypes.c_uint64),
         ("giant_lookups", ctypes.c_uint64),
+        ("window_entries", ctypes.c_uint64),
     ]
 
     def as_dict(self):

@@ -886,6 +886,7 @@ static int collect_pass(eis_ctx *c)
     c->stats.giant_reduce_steps += h[1].giant_reduce;
     c->stats.giant_gcd_branches += h[1].giant_gcd_branch;
     c->stats.giant_lookups += h[1].giant_lookups;
+    c->stats.window_entries += h[1].window_entries;
     c->stats.refills += h[0].refills + h[1].refills + h[2].refills;
     c->stats.fallbacks += h[2].list_len;
     return (h[0].err_count | h[1].err_count | h[2].err_count) ? EIS_EINTERNAL : EIS_OK;

@@ -120,27 +120,29 @@ __device__ __forceinline__ void ring_flush(const WindowRing &rg, u32 lane, unsig
         *reinterpret_cast<uint4 *>(rb + base + e) = make_uint4(r[e], r[e + 1], r[e + 2], r[e + 3]);
 }
 
-// Window bookkeeping of one reduction step that landed on (Q, P) (quarter
-// units): stage a distinguished ideal as entry cnt of the lane's list (its
-// key and twice its residue sum, S2k + acc), write out a full chunk, and
-// note the step jc = jb + k of the last entry and, for mu_1 (the emain-th
-// entry), the step from which an entry ends the window (jc + kExtraSteps).
 // `hit` is the distinguished-ideal test value (see is_dp); idle lanes get
 // one that never matches.
-__device__ __forceinline__ void window_insert(WindowRing &rg, u32 lane, unsigned long long *lb,
-                                              u32 *rb, float Q, float P, float hit, u32 S2k,
-                                              float acc, u32 jb, u32 k, u32 emain, u32 &cnt,
-                                              u32 &j1e, u32 &jlast)
+__device__ __forceinline__ bool window_hit(float Q, float hit)
 {
-    if (__builtin_amdgcn_fractf(Q * kDpScale) == hit) {
-        const u32 slot = cnt % kRing;
-        rg.key[slot][lane] = entry_of(Q, P);
-        rg.res[slot][lane] = S2k + (u32)acc;
-        cnt++;
-        if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
-        jlast = jb + k;
-        j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
-    }
+    return __builtin_amdgcn_fractf(Q * kDpScale) == hit;
+}
+
+// Window bookkeeping of a distinguished ideal (Q, P) (quarter units) reached
+// at step jc: stage it as entry cnt of the lane's list (its key and twice its
+// residue sum, S2k + acc), write out a full chunk, and note the step jc of
+// the last entry and, for mu_1 (the emain-th entry), the step from which an
+// entry ends the window (jc + kExtraSteps).
+__device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned long long *lb,
+                                              u32 *rb, float Q, float P, u32 S2k, float acc,
+                                              u32 jc, u32 emain, u32 &cnt, u32 &j1e, u32 &jlast)
+{
+    const u32 slot = cnt % kRing;
+    rg.key[slot][lane] = entry_of(Q, P);
+    rg.res[slot][lane] = S2k + (u32)acc;
+    cnt++;
+    if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
+    jlast = jc;
+    j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
 }
 
 __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
     u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool live = false;
-    u64 my_steps = 0, my_refills = 0;
+    u64 my_steps = 0, my_refills = 0, my_entries = 0;
     // the lane's next batch position and its work item, loaded one refill ahead
     u32 npos = nb;
     wave_take(p.win_next, nb, true, npos, cbase, cend);
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                     jlast = 0;
                     const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
                     emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
-                    window_insert(rg, lane, lb, rb, Q, P, hit, S2, 0.f, 1, 0, emain, cnt, j1e, jlast);
+                    if (window_hit(Q, hit))
+                        window_append(rg, lane, lb, rb, Q, P, S2, 0.f, 1, emain, cnt, j1e, jlast);
                     live = true;
                 }
             }
@@ -241,12 +244,20 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
             float P2, Q2;
             rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
             const u64 mA = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-            window_insert(rg, lane, lb, rb, Q1, P1, hit, S2 + 2 * it + 1, acc, j + 1, 2 * it, emain,
-                          cnt, j1e, jlast);
+            const float accA = acc;
             rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
             const u64 mB = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
-            window_insert(rg, lane, lb, rb, Q2, P2, hit, S2 + 2 * it + 2, acc, j + 2, 2 * it, emain,
-                          cnt, j1e, jlast);
+            // The pair's distinguished ideals, in walk order: one append for
+            // the first, which the wave runs at almost every pair, and a
+            // second for a lane whose two ideals are both distinguished (one
+            // lane-pair in 256), instead of an append per step.
+            const bool dA = window_hit(Q1, hit), dB = window_hit(Q2, hit);
+            if (dA || dB)
+                window_append(rg, lane, lb, rb, dA ? Q1 : Q2, dA ? P1 : P2, S2 + 2 * it + (dA ? 1u : 2u),
+                              dA ? accA : acc, j + 2 * it + (dA ? 1u : 2u), emain, cnt, j1e, jlast);
+            if (dA && dB)
+                window_append(rg, lane, lb, rb, Q2, P2, S2 + 2 * it + 2, acc, j + 2 * it + 2, emain, cnt,
+                              j1e, jlast);
             const u64 ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) | __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
             const u64 ev = (mA | mB | ms) & lm;
             if (ev) {
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                     if (exA || exB) {
                         // half-period symmetry: the unit is found without giant steps
                         const u32 kx = 2 * it + (exA ? 1u : 2u);
-                        const float accx = exA ? fmaf(__builtin_amdgcn_fractf(P2), -4.f, acc) : acc;
+                        const float accx = exA ? accA : acc;
                         const float Pj = exA ? P1 : P2;
                         const bool qrule = exA ? (Q1 == Q) : (Q2 == Q1);
                         const u32 S = (S2 + kx + (u32)accx) >> 1;
@@ -282,6 +293,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                         my_steps += j + 2 * it + 1;
                     }
                     p.state[pos] = st;
+                    my_entries += cnt - 1;  // appends after the entry of (1)
                     hit = -1.f;
                     j1e = ~0u;
                     cnt = 0;
@@ -305,6 +317,7 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                 const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
                 p.fb_list[f] = item;
                 my_steps += j - 1;
+                my_entries += cnt - 1;
                 hit = -1.f;
                 j1e = ~0u;
                 cnt = 0;
@@ -315,10 +328,12 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
     for (int off = 32; off > 0; off >>= 1) {
         my_steps += __shfl_down(my_steps, off, 64);
         my_refills += __shfl_down(my_refills, off, 64);
+        my_entries += __shfl_down(my_entries, off, 64);
     }
     if (lane == 0) {
         atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
         atomicAdd(&p.ctr->refills, (unsigned long long)my_refills);
+        atomicAdd(&p.ctr->window_entries, (unsigned long long)my_entries);
     }
 }
 

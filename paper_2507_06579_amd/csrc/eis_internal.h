@@ -69,7 +69,8 @@ struct PassCounters {
     unsigned long long chunk_steps;  // rho steps inside the giant-step walk
     // work of the giant walk's compositions (see GiantWork)
     unsigned long long giant_comps, giant_euclid, giant_reduce, giant_lookups, giant_gcd_branch;
-    u64 pad3[3];
+    unsigned long long window_entries;  // list appends of the window walk
+    u64 pad3[2];
 };
 
 // The fields of a segment that the walk kernels need, kept in LDS.
