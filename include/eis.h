@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 5
+#define EIS_ABI_VERSION 6
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -97,7 +97,9 @@ typedef enum {
     EIS_K_WALK_HANDOFF = 6,  /* plain walk of the d's the giant-step method handed off */
     EIS_K_POPCOUNT = 7,      /* per-segment counts */
     EIS_K_GIANT_SQUARE = 8,  /* giant-step method: g = mu_1^2 and g^2 (NUDUPL) */
-    EIS_K_COUNT = 9
+    EIS_K_GIANT_RETRY = 9,   /* giant-step method again, with a later mu_1, for the d's
+                                the first round handed off (its four kernels together) */
+    EIS_K_COUNT = 10
 } eis_kernel;
 
 typedef struct {
@@ -140,6 +142,10 @@ typedef struct {
     /* distinguished ideals the window walk appended to the dictionary lists
      * (the operation count of its list-append path) */
     uint64_t window_entries;
+    /* d's the giant-step method handed off and ran again with mu_1 four
+     * distinguished ideals later; `fallbacks` counts those it handed off
+     * again, which the plain walk classifies */
+    uint64_t giant_retries;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */

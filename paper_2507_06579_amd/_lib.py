@@ -13,14 +13,14 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
-ABI_VERSION = 5  # must match EIS_ABI_VERSION of include/eis.h
+ABI_VERSION = 6  # must match EIS_ABI_VERSION of include/eis.h
 EIS_SET_SQUAREFREE = 0
 EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
 EIS_FLAG_KERNEL_TIMES = 2
 # eis_kernel: index of the per-kernel entries of the stats
 KERNELS = ["prime_offsets", "sieve", "walk_plain", "walk_window", "build_tables", "walk_giant",
-           "walk_handoff", "popcount", "giant_square"]
+           "walk_handoff", "popcount", "giant_square", "giant_retry"]
 
 EXPORTED_SYMBOLS = [
     "eis_config_default", "eis_create", "eis_destroy", "eis_num_candidates",
@@ -82,6 +82,7 @@ class EisStats(ctypes.Structure):
         ("giant_gcd_branches", ctypes.c_uint64),
         ("giant_lookups", ctypes.c_uint64),
         ("window_entries", ctypes.c_uint64),
+        ("giant_retries", ctypes.c_uint64),
     ]
 
     def as_dict(self):

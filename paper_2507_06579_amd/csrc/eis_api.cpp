@@ -57,6 +57,11 @@ constexpr u32 kPassWords = (u32)(kPassCandidates / 32) + kMaxSegments;
 // queue heads of the giant-step method (three cache lines) and the task
 // counts of its cost buckets (one line each), in 32-bit words
 constexpr u32 kQueueWords = (3 + kCostBuckets) * 16;
+// counter sets of a pass: plain walk, giant steps, hand-offs, the retry
+// round's hand-offs
+constexpr u32 kPassCounterSets = 4;
+// the retry round takes mu_1 this many distinguished ideals later
+constexpr u32 kRetryShift = 4;
 constexpr u32 kDefaultServeSlots = 64;
 // serving: candidates of one request per pass (a larger request advances a
 // chunk per pass, so that requests behind it are not held up)
@@ -153,7 +158,8 @@ struct eis_ctx {
     u32 *d_list_plain = nullptr;
     u32 *d_list_giant = nullptr;
     u32 *d_fb_list = nullptr;
-    PassCounters *d_ctrs = nullptr;  // [0] plain walk, [1] giant steps, [2] hand-offs
+    PassCounters *d_ctrs = nullptr;  // [0] plain walk, [1] giant steps, [2] hand-offs,
+                                     // [3] hand-offs of the retry round
     unsigned long long *d_counts = nullptr;
     u64 counts_cap = 0;              // pairs
     unsigned long long *h_counts = nullptr;  // pinned
@@ -163,6 +169,7 @@ struct eis_ctx {
     bool pass_ready = false;
     bool uncollected = false;            // a pass whose counters nobody has read yet
     hipStream_t pending_stream = nullptr;  // the stream it runs on
+    bool pending_retry = false;          // it has the retry round
 
     // per-kernel timing (EIS_FLAG_KERNEL_TIMES): event pairs of this pass
     bool kernel_times = false;
@@ -456,7 +463,7 @@ static int ensure_pass_buffers(eis_ctx *c)
 {
     if (c->pass_ready) return EIS_OK;
     const u64 need = kMaxSegments * sizeof(SegInfo) + 2ull * kPassWords * 4 +
-                     3ull * kPassCandidates * 4 + 3 * sizeof(PassCounters) + kQueueWords * 4;
+                     3ull * kPassCandidates * 4 + kPassCounterSets * sizeof(PassCounters) + kQueueWords * 4;
     if (c->bytes_held + need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
     if (hipMalloc(&c->d_segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_segs), kMaxSegments * sizeof(SegInfo),
@@ -466,7 +473,7 @@ static int ensure_pass_buffers(eis_ctx *c)
         hipMalloc(&c->d_list_plain, kPassCandidates * 4) != hipSuccess ||
         hipMalloc(&c->d_list_giant, kPassCandidates * 4) != hipSuccess ||
         hipMalloc(&c->d_fb_list, kPassCandidates * 4) != hipSuccess ||
-        hipMalloc(&c->d_ctrs, 3 * sizeof(PassCounters)) != hipSuccess ||
+        hipMalloc(&c->d_ctrs, kPassCounterSets * sizeof(PassCounters)) != hipSuccess ||
         hipMalloc(&c->d_q, kQueueWords * 4) != hipSuccess)
         return EIS_ENOMEM;
     c->bytes_held += need;
@@ -725,9 +732,11 @@ static int kt_end(eis_ctx *c, hipStream_t st)
 // upload).  Captured into graphs by shape.
 static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, bool timed)
 {
-    PassCounters *ctr_plain = c->d_ctrs, *ctr_giant = c->d_ctrs + 1, *ctr_fb = c->d_ctrs + 2;
+    PassCounters *ctr_plain = c->d_ctrs, *ctr_giant = c->d_ctrs + 1, *ctr_fb = c->d_ctrs + 2,
+                 *ctr_fb2 = c->d_ctrs + 3;
     const bool kt = timed && c->kernel_times;
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctrs), 3 * sizeof(PassCounters) / 4, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctrs),
+                            kPassCounterSets * sizeof(PassCounters) / 4, st));
     HIP_TRY(launch_zero_u32(c->d_eis_words, pl.words, st));
     KLAUNCH(EIS_K_PRIME_OFFSETS,
             launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
@@ -769,18 +778,52 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         ip.tsize = pl.tsize;
         ip.max_steps = (u32)c->cfg.max_steps_per_d;
         ip.max_giants = 1u << 20;
+        ip.emain_shift = 0;
         ip.eis_words = c->d_eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
             HIP_TRY(launch_zero_u32(c->d_q, kQueueWords, st));
-            KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, st));
-            KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, pl.grid_tables, st));
-            KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, st));
-            KLAUNCH(EIS_K_WALK_GIANT, launch_walk_giant(ip, pl.grid_giant, st));
+            KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, false, st));
+            KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, pl.grid_tables, false, st));
+            KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, false, st));
+            KLAUNCH(EIS_K_WALK_GIANT, launch_walk_giant(ip, pl.grid_giant, false, st));
         }
-        // d's handed off by the giant-step method: the plain walk, exact for all d
+        // The d's handed off, once more with mu_1 kRetryShift distinguished
+        // ideals later: a hand-off comes from a composition whose magnitudes
+        // pass 2^52 (one of the ideals has a small norm, at heights near
+        // 10^12) or from another check, and a different mu_1 gives other
+        // giant ideals.  With one batch per pass the hand-offs fit the batch
+        // buffers; the plain walk then takes what the retry hands off.  Its
+        // kernels exit at once when there is nothing to retry.
         wp.list = c->d_fb_list;
         wp.ctr = ctr_fb;
+        if (pl.nbatches == 1) {
+            InfraParams rp = ip;
+            rp.list = c->d_fb_list;
+            rp.list_ctr = ctr_fb;
+            rp.k0 = 0;
+            // its hand-offs go to the plain walk's list, which that walk,
+            // earlier on the stream, no longer needs
+            rp.fb_list = c->d_list_plain;
+            rp.fb_ctr = ctr_fb2;
+            rp.emain_shift = kRetryShift;
+            if (kt) {
+                int r = kt_begin(c, st, EIS_K_GIANT_RETRY);
+                if (r != EIS_OK) return r;
+            }
+            HIP_TRY(launch_zero_u32(c->d_q, kQueueWords, st));
+            HIP_TRY(launch_walk_window(rp, c->num_cu, true, st));
+            HIP_TRY(launch_build_tables(rp, c->num_cu, true, st));
+            HIP_TRY(launch_giant_square(rp, true, st));
+            HIP_TRY(launch_walk_giant(rp, c->num_cu, true, st));
+            if (kt) {
+                int r = kt_end(c, st);
+                if (r != EIS_OK) return r;
+            }
+            wp.list = c->d_list_plain;
+            wp.ctr = ctr_fb2;
+        }
+        // the rest: the plain walk, exact for all d
         KLAUNCH(EIS_K_WALK_HANDOFF, launch_walk_baby(wp, pl.grid_fb, st));
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk1, st));
@@ -816,7 +859,7 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
         if (rc != EIS_OK) return rc;
     }
     HIP_TRY(hipMemcpyAsync(c->d_segs, c->h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
-    u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches : 0);
+    u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches + (pl.nbatches == 1 ? 5 : 0) : 0);
     if (graph && c->use_graphs && st == c->stream) {
         const std::vector<u64> key = plan_key(c, pl);
         auto it = c->graphs.find(key);
@@ -846,6 +889,7 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
     }
     c->uncollected = true;
     c->pending_stream = st;
+    c->pending_retry = pl.giant_cand && pl.nbatches == 1;
     std::lock_guard<std::mutex> lk(c->stats_mu);
     c->stats.launches += launches;
     return EIS_OK;
@@ -855,7 +899,7 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
 static int collect_pass(eis_ctx *c)
 {
     c->uncollected = false;
-    PassCounters h[3];
+    PassCounters h[kPassCounterSets];
     if (hipMemcpy(h, c->d_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
@@ -875,11 +919,13 @@ static int collect_pass(eis_ctx *c)
     }
     c->kev_used = 0;
     c->stats.discriminants += (u64)h[0].list_len + h[1].list_len;
-    c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[1].chunk_steps + h[2].baby_steps;
+    // the hand-off walk ran on the retry round's list when there was one
+    const PassCounters &hf = c->pending_retry ? h[3] : h[2];
+    c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[1].chunk_steps + hf.baby_steps;
     c->stats.kernel_steps[EIS_K_WALK_PLAIN] += h[0].baby_steps;
     c->stats.kernel_steps[EIS_K_WALK_WINDOW] += h[1].baby_steps;
     c->stats.kernel_steps[EIS_K_WALK_GIANT] += h[1].chunk_steps;
-    c->stats.kernel_steps[EIS_K_WALK_HANDOFF] += h[2].baby_steps;
+    c->stats.kernel_steps[EIS_K_WALK_HANDOFF] += hf.baby_steps;
     c->stats.giant_steps += h[1].giant_steps;
     c->stats.giant_compositions += h[1].giant_comps;
     c->stats.giant_euclid_steps += h[1].giant_euclid;
@@ -887,9 +933,10 @@ static int collect_pass(eis_ctx *c)
     c->stats.giant_gcd_branches += h[1].giant_gcd_branch;
     c->stats.giant_lookups += h[1].giant_lookups;
     c->stats.window_entries += h[1].window_entries;
-    c->stats.refills += h[0].refills + h[1].refills + h[2].refills;
-    c->stats.fallbacks += h[2].list_len;
-    return (h[0].err_count | h[1].err_count | h[2].err_count) ? EIS_EINTERNAL : EIS_OK;
+    c->stats.refills += h[0].refills + h[1].refills + hf.refills;
+    c->stats.fallbacks += hf.list_len;
+    if (c->pending_retry) c->stats.giant_retries += h[2].list_len;
+    return (h[0].err_count | h[1].err_count | hf.err_count) ? EIS_EINTERNAL : EIS_OK;
 }
 
 static int check_range(uint64_t a, uint64_t b)

@@ -55,8 +55,11 @@
 // exactly when log eps is, so a hit at two regulators gives the same flag.
 //
 // Any arithmetic check that fails (fp64 exactness, exact divisions, step or
-// walk budgets, table overflow) sends the d to the plain walk, which is exact
-// for every d below 10^12.
+// walk budgets, table overflow) hands the d off.  The four kernels have a
+// second set of entry points (k_retry_*) for a round that runs the hand-offs
+// again with mu_1 emain_shift distinguished ideals later, so that the giant
+// ideals differ; what that round hands off goes to the plain walk, which is
+// exact for every d below 10^12.
 #include "eis_giant.h"
 #include "eis_internal.h"
 #include "eis_walk.h"
@@ -145,8 +148,9 @@ __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned
     j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
 }
 
-__global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
+__device__ __forceinline__ void walk_window_body(InfraParams p)
 {
+    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
     __shared__ SegLds segs[kMaxSegments];
     __shared__ WindowRing rings[4];
     load_segs(segs, p.segs, p.nseg);
@@ -218,7 +222,8 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
                     j1e = ~0u;
                     jlast = 0;
                     const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
-                    emain = (u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8));
+                    emain = min((u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8)) + p.emain_shift,
+                                p.emax - 8);
                     if (window_hit(Q, hit))
                         window_append(rg, lane, lb, rb, Q, P, S2, 0.f, 1, emain, cnt, j1e, jlast);
                     live = true;
@@ -337,10 +342,13 @@ __global__ __launch_bounds__(256) void k_walk_window(InfraParams p)
     }
 }
 
-hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream)
+__global__ __launch_bounds__(256) void k_walk_window(InfraParams p) { walk_window_body(p); }
+__global__ __launch_bounds__(256) void k_retry_window(InfraParams p) { walk_window_body(p); }
+
+hipError_t launch_walk_window(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk_window, dim3(grid), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(retry ? k_retry_window : k_walk_window, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -381,7 +389,7 @@ __device__ __forceinline__ void load_entries(const InfraParams &p, u32 pos, u32 
     }
 }
 
-__global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
+__device__ __forceinline__ void build_tables_body(InfraParams p)
 {
     __shared__ u32 tab[4][kTableMax];
     const u32 nblk = gridDim.x, b = blockIdx.x;
@@ -439,11 +447,14 @@ __global__ __launch_bounds__(256) void k_build_tables(InfraParams p)
     }
 }
 
-hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t stream)
+__global__ __launch_bounds__(256) void k_build_tables(InfraParams p) { build_tables_body(p); }
+__global__ __launch_bounds__(256) void k_retry_tables(InfraParams p) { build_tables_body(p); }
+
+hipError_t launch_build_tables(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (p.batch == 0 || grid == 0) return hipSuccess;
     if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_build_tables, dim3(grid), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(retry ? k_retry_tables : k_build_tables, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -532,8 +543,12 @@ __device__ __forceinline__ u32 cost_bucket(u64 d)
 // positions would cost more than the squarings.
 constexpr u32 kSquarePerThread = 4;
 
-__global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
+__device__ __forceinline__ void giant_square_body(InfraParams p)
 {
+    {
+        const u32 total = p.list_ctr->list_len;  // workgroups past the batch's end leave
+        if (p.k0 >= total || blockIdx.x * (256u * kSquarePerThread) >= total - p.k0) return;
+    }
     __shared__ SegLds segs[kMaxSegments];
     __shared__ u32 bcount[kCostBuckets], bbase[kCostBuckets];
     if (threadIdx.x < kCostBuckets) bcount[threadIdx.x] = 0u;
@@ -609,11 +624,15 @@ __global__ __launch_bounds__(256) void k_giant_square(InfraParams p)
     }
 }
 
-hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream)
+__global__ __launch_bounds__(256) void k_giant_square(InfraParams p) { giant_square_body(p); }
+__global__ __launch_bounds__(256) void k_retry_square(InfraParams p) { giant_square_body(p); }
+
+hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t stream)
 {
     if (p.batch == 0) return hipSuccess;
     const u32 per_block = 256u * kSquarePerThread;
-    hipLaunchKernelGGL(k_giant_square, dim3((p.batch + per_block - 1) / per_block), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(retry ? k_retry_square : k_giant_square, dim3((p.batch + per_block - 1) / per_block),
+                       dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -668,8 +687,9 @@ __device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long l
 // towards the next distinguished ideal and, on reaching it, looks it up.  A
 // lane with a long walk continues it in the next iteration instead of
 // holding up the other lanes.
-__global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
+__device__ __forceinline__ void walk_giant_body(InfraParams p)
 {
+    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
     __shared__ SegLds segs[kMaxSegments];
     __shared__ u32 bstart[kCostBuckets + 1];  // queue index of each bucket's first task
     if (threadIdx.x == 0) {
@@ -897,10 +917,13 @@ __global__ __launch_bounds__(256) void k_walk_giant(InfraParams p)
     }
 }
 
-hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream)
+__global__ __launch_bounds__(256) void k_walk_giant(InfraParams p) { walk_giant_body(p); }
+__global__ __launch_bounds__(256) void k_retry_giant(InfraParams p) { walk_giant_body(p); }
+
+hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(retry ? k_retry_giant : k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
 

@@ -155,6 +155,7 @@ struct InfraParams {
     u32 tsize;                  // table slots per d (power of two)
     u32 max_steps;              // per-d budget of reduction steps (window)
     u32 max_giants;             // per-d budget of giant steps
+    u32 emain_shift;            // mu_1 this many entries later (the retry round)
     u32 *eis_words;             // output bitmaps of the pass
 };
 
@@ -172,10 +173,12 @@ hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const
                                 u32 nseg, u32 words_max, unsigned long long *counts,
                                 hipStream_t stream);
 
-hipError_t launch_walk_window(const InfraParams &p, u32 grid, hipStream_t stream);
-hipError_t launch_build_tables(const InfraParams &p, u32 grid, hipStream_t stream);
-hipError_t launch_giant_square(const InfraParams &p, hipStream_t stream);
-hipError_t launch_walk_giant(const InfraParams &p, u32 grid, hipStream_t stream);
+// `retry`: the same kernels under their own names (k_retry_*), for the round
+// that runs the first round's hand-offs again with another mu_1.
+hipError_t launch_walk_window(const InfraParams &p, u32 grid, bool retry, hipStream_t stream);
+hipError_t launch_build_tables(const InfraParams &p, u32 grid, bool retry, hipStream_t stream);
+hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t stream);
+hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStream_t stream);
 int walk_window_blocks_per_cu();
 int walk_giant_blocks_per_cu();
 
