@@ -388,10 +388,18 @@ __device__ __forceinline__ void load_entries(const InfraParams &p, u32 pos, u32 
     }
 }
 
+// Each wave builds its d's table in its own LDS region, so the phases of a
+// table (clear, insert, write out) need only the wave's own LDS operations
+// to be complete and visible to its lanes, not a workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Short lists: kLoads list entries per lane (64 kLoads >= emax).  Persistent: the block
-// takes groups of four positions (one per wave), the same number of groups
-// for all four waves, so that the barriers below are reached by the whole
-// block.  A position's entries are loaded kAhead groups ahead and its entry
+// takes groups of four positions (one per wave); each wave works on its own
+// table, so its phases are ordered by wave_lds_sync alone.  A position's entries are loaded kAhead groups ahead and its entry
 // count one group earlier still, so that the loads overlap the insertions
 // of the groups in between.  With short lists (64 kLoads = 128 entries at
 // most) a wave issues two loads per lane instead of eight mostly idle ones
@@ -421,7 +429,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
     for (u32 g = lb; 4 * g < n; g += nblk) {
         const u32 pos = 4 * g + wv;
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoads; k++) {
             const u32 e = lane + 64 * k;
@@ -437,13 +445,13 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (cnt[0] != 0u) {
             // two slots per 32-bit store
             u32 *tbl = reinterpret_cast<u32 *>(p.tables + (u64)pos * p.tsize);
             for (u32 t = lane; t < p.tsize / 2; t += 64) tbl[t] = tab[wv][2 * t] | (tab[wv][2 * t + 1] << 16);
         }
-        __syncthreads();
+        wave_lds_sync();
         // advance the pipeline by one group
 #pragma unroll
         for (u32 i = 0; i < kAhead; i++) {
@@ -481,7 +489,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
         const u32 cnt2 = count_of(g + 2 * nblk);
         load_entries<kLoadsLong>(p, pos + 4 * nblk, cnt1, ent1);
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoadsLong; k++) {
             const u32 e = lane + 64 * k;
@@ -497,13 +505,13 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (cnt0 != 0u) {
             // two slots per 32-bit store
             u32 *tbl = reinterpret_cast<u32 *>(p.tables + (u64)pos * p.tsize);
             for (u32 t = lane; t < p.tsize / 2; t += 64) tbl[t] = tab[wv][2 * t] | (tab[wv][2 * t + 1] << 16);
         }
-        __syncthreads();
+        wave_lds_sync();
         cnt0 = cnt1;
         cnt1 = cnt2;
 #pragma unroll
