@@ -397,9 +397,10 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Short lists: kLoads list entries per lane (64 kLoads >= emax).  Persistent: the block
-// takes groups of four positions (one per wave); each wave works on its own
-// table, so its phases are ordered by wave_lds_sync alone.  A position's entries are loaded kAhead groups ahead and its entry
+// Short lists: kLoads list entries per lane (64 kLoads >= emax).
+// Persistent: the block takes groups of four positions (one per wave); each
+// wave works on its own table, so its phases are ordered by wave_lds_sync
+// alone.  A position's entries are loaded kAhead groups ahead and its entry
 // count one group earlier still, so that the loads overlap the insertions
 // of the groups in between.  With short lists (64 kLoads = 128 entries at
 // most) a wave issues two loads per lane instead of eight mostly idle ones
