@@ -151,7 +151,9 @@ __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned
 __device__ __forceinline__ void walk_window_body(InfraParams p)
 {
     if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
-    __shared__ SegLds segs[kMaxSegments];
+    // The segment table is sized at launch (p.nseg entries): with one segment
+    // the rings alone bound the workgroups per CU (six instead of five).
+    extern __shared__ SegLds segs[];
     __shared__ WindowRing rings[4];
     load_segs(segs, p.segs, p.nseg);
     const u32 lane = __lane_id();
@@ -348,7 +350,8 @@ __global__ __launch_bounds__(256) void k_retry_window(InfraParams p) { walk_wind
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(retry ? k_retry_window : k_walk_window, dim3(grid), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(retry ? k_retry_window : k_walk_window, dim3(grid), dim3(256),
+                       p.nseg * sizeof(SegLds), stream, p);
     return hipGetLastError();
 }
 
