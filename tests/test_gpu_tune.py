@@ -80,7 +80,7 @@ def test_kernel_times_and_step_counts():
         if method == eis.Method.BABY:
             assert kl[k.index("walk_plain")] == 1 and kl[k.index("walk_window")] == 0
             assert ks[k.index("walk_plain")] == st["baby_steps"]
-            assert gw == [0, 0, 0, 0, 0]
+            assert gw == [0, 0, 0, 0, 0] and st["window_entries"] == 0
         else:
             assert kl[k.index("walk_window")] >= 1 and kl[k.index("walk_giant")] >= 1
             assert kl[k.index("giant_square")] == kl[k.index("walk_giant")]
@@ -91,6 +91,10 @@ def test_kernel_times_and_step_counts():
             # least one Euclid step, and some take NUCOMP's gcd branch
             assert 0 < comps < st["giant_steps"] and 0 < looks <= st["giant_steps"]
             assert looks >= comps and euclid > comps and 0 <= gcdb < comps and red >= 0
+            # the window walk appends its distinguished ideals (Q = 2 mod 64):
+            # about one reduction step in 16
+            ent = st["window_entries"]
+            assert 0.04 < ent / ks[k.index("walk_window")] < 0.09
         assert all(x >= 0 for x in kms)
         assert 0 < sum(kms) <= st["last_total_ms"] * 1.05 + 0.5
     # without the flag nothing is timed
