@@ -18,9 +18,11 @@
 //                  hash table of 16-bit slots (9-bit list index + 7-bit
 //                  fingerprint; a fingerprint match is confirmed against the
 //                  list entry), built in LDS and written out whole.
-//   k_giant_square one lane per d: the giant step g = reduce(mu_1^2) and the
-//                  second giant ideal reduce(g^2), by NUDUPL.
-//   k_walk_giant   one d per lane, lanes refilled from a queue: starting
+//   k_giant_square four d's per lane: the giant step g = reduce(mu_1^2) and
+//                  the second giant ideal reduce(g^2), by NUDUPL; each d's
+//                  task goes into a bucket by its estimated walk length.
+//   k_walk_giant   one d per lane, lanes refilled from a queue over the
+//                  buckets, longest estimated walks first: starting
 //                  from g and g^2, the giant ideals g_k = reduce(g * g_{k-1})
 //                  (NUCOMP), the residue updated with log g + log g_{k-1} -
 //                  log gamma + the residues of the reduction steps; after
