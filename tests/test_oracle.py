@@ -146,6 +146,30 @@ def test_small_non_eisenstein():
         assert not oracle.walk_mod2(d)[0]
 
 
+def richaud_degert_members(nmax):
+    """Members of D of the forms n^2 + 4 and n^2 - 4, n odd, n < nmax."""
+    ds = [n * n + 4 for n in range(1, nmax, 2)] + [n * n - 4 for n in range(5, nmax, 2)]
+    return sorted(d for d in ds if oracle.in_D_trial(d))
+
+
+def test_richaud_degert_families_are_not_eisenstein():
+    # For d = n^2 +- 4 with n odd, u = (n + sqrt d)/2 is a unit (norm -+1),
+    # u = (n - 1)/2 + omega with omega = (1 + sqrt d)/2, so u is not 1 mod
+    # 2 O_K.  u = eps^k for some k >= 1, and eps = 1 mod 2 O_K would give
+    # u = 1: so eps is not 1 either, and no such d is in E (whether or not u
+    # is fundamental).  A closed form for a whole family, at every height.
+    ds = richaud_degert_members(3001)
+    assert len(ds) > 1500
+    flags, _ = oracle.classify_list(ds)
+    assert not flags.any()
+    # and (Richaud-Degert) u is the fundamental unit itself: eps_d = (n + sqrt d)/2
+    for d in ds[:60] + ds[-20:]:
+        r = math.isqrt(d - 4)
+        n = r if r * r == d - 4 else math.isqrt(d + 4)  # 5 = 1 + 4 = 9 - 4: n = 1
+        flag, x0, y0 = oracle.unit_bigint(d)[:3]
+        assert not flag and (x0, y0) == (n, 1), d
+
+
 # --------------------------------------------------------------------------
 # Class numbers (Lemma 1.1 (4), narrow form)
 # --------------------------------------------------------------------------
