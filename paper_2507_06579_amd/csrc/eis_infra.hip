@@ -705,6 +705,8 @@ __device__ __forceinline__ void giant_square_body(InfraParams p)
         }
         out.pos = pos;
         out.item = st.item;
+        out.s4 = (float)s * 0.25f;
+        out.L = (float)L;
         if (ck.bad()) out.g.S = kSquareBad;
         const u32 b = slot[j] & 0xffu;
         p.tasks[(u64)b * p.task_cap + bbase[b] + (slot[j] >> 8)] = out;
@@ -853,14 +855,10 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                     my_giants += 1;
                 } else {
                     idx = item_bit(segs, item);
-                    const u64 d = item_d(segs, item);
-                    double s64, P1, Q1;
-                    u32 S1;
-                    first_step(d, s64, P1, Q1, S1);
-                    dd = (double)d;
-                    sq = (float)s64 * 0.25f;
+                    dd = (double)item_d(segs, item);
+                    sq = cur->s4;
                     sqc = sq * kQuotBias;
-                    L = (float)isqrt_f64(s64);
+                    L = cur->L;
                     // g = reduce(mu_1^2) is the first giant ideal and the step
                     m1Q = gs.Q4;
                     m1P = gs.P4;

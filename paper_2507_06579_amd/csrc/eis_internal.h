@@ -114,8 +114,10 @@ struct WindowState {
 // Per-d task of the giant walk, written by the squaring kernel: the d's
 // batch position and work item, the giant step g = reduce(mu_1^2) and the
 // second giant ideal g2 = reduce(g^2), each as a reduced ideal (Q/4, P/4 in
-// fp32, Qp/4 its rho predecessor) and its residue S in Z/3; g.S = kSquareBad
-// when a check of the squarings failed (the d then goes to the plain walk).
+// fp32, Qp/4 its rho predecessor) and its residue S in Z/3 (g.S = kSquareBad
+// when a check of the squarings failed: the d is handed off), and
+// s = isqrt(d) (as s/4) and L = isqrt(s), which the squaring kernel has
+// computed already (exact in fp32 for d < 2^48).
 struct GiantIdeal {
     float Q4, P4, Qp4;
     u32 S;
@@ -123,6 +125,7 @@ struct GiantIdeal {
 struct GiantTask {
     u32 pos, item;
     GiantIdeal g, g2;
+    float s4, L;
 };
 constexpr u32 kSquareBad = ~0u;
 
