@@ -77,7 +77,7 @@ typedef enum {
 } eis_method;
 
 /* Candidate sets (the *_set calls): D itself, or the primes in D (the
- * prime subsequence of Section 4; a prime d = 5 mod 8 is squarefree). */
+ * prime subsequence of Section 3.2; a prime d = 5 mod 8 is squarefree). */
 #define EIS_SET_SQUAREFREE 0
 #define EIS_SET_PRIME 1
 
@@ -90,7 +90,9 @@ typedef enum {
 typedef enum {
     EIS_K_PRIME_OFFSETS = 0, /* first multiple of every p^2 in each segment */
     EIS_K_SIEVE = 1,         /* squarefree sieve and work-list compaction */
-    EIS_K_WALK_PLAIN = 2,    /* rho walk to the half-period exit (Section 3.1) */
+    EIS_K_WALK_PLAIN = 2,    /* rho walk (Appendix A) to the half-period exit of Algorithm
+                                Infrastructure; the exit rule is derived here from the
+                                symmetry of the cycle under conjugation */
     EIS_K_WALK_WINDOW = 3,   /* giant-step method: baby window and dictionary */
     EIS_K_BUILD_TABLES = 4,  /* giant-step method: dictionary hash tables */
     EIS_K_WALK_GIANT = 5,    /* giant-step method: giant steps with lookups */
@@ -207,7 +209,7 @@ int eis_count_batch(eis_ctx *ctx, const uint64_t *a, const uint64_t *b, size_t n
 
 /* Counts over a candidate set: *n_set = #(S n [a,b)) and *n_eis =
  * #(E n S n [a,b)) for S = D (EIS_SET_SQUAREFREE, same as eis_count) or
- * S = D n P, the primes p = 5 (mod 8) (EIS_SET_PRIME; Section 4, the prime
+ * S = D n P, the primes p = 5 (mod 8) (EIS_SET_PRIME; Section 3.2, the prime
  * subsequence pi_{E n P}).  The prime set is sieved by every odd prime up
  * to sqrt(b) and only its members are walked.  EIS_EINVAL for another set. */
 int eis_count_set(eis_ctx *ctx, int set, uint64_t a, uint64_t b, uint64_t *n_set,
@@ -229,7 +231,9 @@ int eis_submit(eis_ctx *ctx, uint64_t a, uint64_t b, uint64_t *ticket);
 
 /* Wait up to timeout_us microseconds (< 0 = forever) for a ticket.  On
  * EIS_OK the counts are written and the ticket is retired.  EIS_ETIMEDOUT
- * leaves it pending; EIS_ECANCELED / EIS_EINTERNAL retire it. */
+ * leaves it pending; EIS_ECANCELED / EIS_EINTERNAL retire it.  An unknown
+ * or retired ticket gives EIS_EINVAL, also when another thread's eis_wait
+ * retires it during the wait. */
 int eis_wait(eis_ctx *ctx, uint64_t ticket, int64_t timeout_us, uint64_t *n_sqfree,
              uint64_t *n_eis);
 

@@ -197,7 +197,7 @@ def count_primes_trial(lo: int, hi: int) -> int:
 
 
 def classify_primes(a: int, b: int, nthreads: int | None = None):
-    """The prime subsequence of [a, b) (Section 4): primes p = 5 (mod 8),
+    """The prime subsequence of [a, b) (Section 3.2): primes p = 5 (mod 8),
     found by trial division, and how many of them lie in E (the full-period
     walk).  Returns (n_primes, n_eis)."""
     d0 = first_candidate(a)

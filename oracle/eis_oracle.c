@@ -111,7 +111,7 @@ int orc_in_D_trial(uint64_t d)
 
 /* ------------------------------------------------------------------ */
 /* Primality by trial division (the definition of a prime), for the prime */
-/* subsequence of Section 4.                                              */
+/* subsequence of Section 3.2.                                           */
 /* ------------------------------------------------------------------ */
 int orc_is_prime_trial(uint64_t n)
 {

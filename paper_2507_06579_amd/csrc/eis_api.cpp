@@ -1338,17 +1338,23 @@ extern "C" int eis_wait(eis_ctx *c, uint64_t ticket, int64_t timeout_us, uint64_
 {
     if (!c) return EIS_EINVAL;
     std::unique_lock<std::mutex> lk(c->smu);
-    auto it = c->reqs.find(ticket);
-    if (it == c->reqs.end()) return EIS_EINVAL;
-    auto ready = [&] { return c->reqs[ticket].finished || c->stop; };
+    if (c->reqs.find(ticket) == c->reqs.end()) return EIS_EINVAL;
+    // A ticket that disappears while we wait was retired by another waiter:
+    // stop waiting (it is reported as unknown below), never re-create it.
+    auto ready = [&] {
+        auto f = c->reqs.find(ticket);
+        return f == c->reqs.end() || f->second.finished || c->stop;
+    };
     if (timeout_us < 0) {
         c->dcv.wait(lk, ready);
     } else if (!c->dcv.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
         return EIS_ETIMEDOUT;
     }
-    Request r = c->reqs[ticket];
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return EIS_EINVAL;
+    Request r = it->second;
     if (!r.finished) return EIS_ETIMEDOUT;
-    c->reqs.erase(ticket);
+    c->reqs.erase(it);
     if (r.cancelled) return EIS_ECANCELED;
     if (r.status != EIS_OK) return r.status;
     if (n_sqfree) *n_sqfree = r.n_sq;

@@ -1,5 +1,5 @@
-"""Paper-scale sweep: pi_D(x) and pi_E(x) for x up to 10^11 (Section 4), and
-the same counts over the prime subsequence (Section 4, prime subsequence).
+"""Paper-scale sweep: pi_D(x) and pi_E(x) for x up to 10^11 (Section 3.1), and
+the same counts over the prime subsequence (Section 3.2, prime subsequence).
 
 The range [0, X) is cut into segments whose ends include every power of ten;
 segments go to the GPU through eis_count_batch a few at a time, and after
@@ -38,10 +38,10 @@ import os
 import sys
 import time
 
-PAPER_C56 = -0.024       # Section 4, the fitted coefficient of x^(5/6)
-PAPER_DENSITY_B = 0.201  # Section 4, P(E | D) ~ 1/3 - b / d^(1/6)
-PAPER_PRIME_C = -0.037   # Section 4, prime subsequence: coefficient of Li6(x)
-PAPER_PRIME_B = 0.148    # Section 4, prime subsequence: P(E | D cap P) ~ 1/3 - b / p^(1/6)
+PAPER_C56 = -0.024       # Section 3.1, the fitted coefficient of x^(5/6)
+PAPER_DENSITY_B = 0.201  # Section 3.1, P(E | D) ~ 1/3 - b / d^(1/6)
+PAPER_PRIME_C = -0.037   # Section 3.2, prime subsequence: coefficient of Li6(x)
+PAPER_PRIME_B = 0.148    # Section 3.2, prime subsequence: P(E | D cap P) ~ 1/3 - b / p^(1/6)
 
 SETS = ("squarefree", "prime")
 

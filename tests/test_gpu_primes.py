@@ -1,4 +1,4 @@
-"""GPU tests of the prime subsequence (Section 4): the prime sieve and the
+"""GPU tests of the prime subsequence (Section 3.2): the prime sieve and the
 walks over primes only, against the oracle's trial division and full-period
 walk.  Counts are integers: every comparison is exact."""
 import sys

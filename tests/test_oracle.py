@@ -270,7 +270,7 @@ def test_planted_mistake_is_caught(which):
         assert not _pins_pass()
 
 
-# ---- prime subsequence (Section 4) ----------------------------------------
+# ---- prime subsequence (Section 3.2) --------------------------------------
 
 # pi(x), the number of primes below x: classical values
 PRIME_COUNTS = {100: 25, 1000: 168, 10**4: 1229, 10**5: 9592, 10**6: 78498}
