@@ -120,6 +120,34 @@ struct Request {
 
 }  // namespace
 
+// Device buffers one pass runs on: the context's own (allocated on first
+// use and kept) or views into the no-allocation scratch.
+struct PassBufs {
+    SegInfo *segs = nullptr;    // segment table
+    SegInfo *h_segs = nullptr;  // pinned staging of the table (null: a kernel stores it)
+    u64 *roff = nullptr;        // prime offsets
+    u64 roff_cap = 0;
+    u32 *sq_words = nullptr, *eis_words = nullptr;  // pass bitmaps
+    u32 *list_plain = nullptr, *list_giant = nullptr, *fb_list = nullptr;
+    PassCounters *ctrs = nullptr;  // [0] plain walk, [1] giant steps, [2] hand-offs,
+                                   // [3] hand-offs of the retry round
+    u32 *q = nullptr;              // giant-step queue heads (3 cache lines), then the task
+                                   // counts of the cost buckets (one line each)
+    unsigned long long *counts = nullptr;  // (pi_D, pi_E) per count slot
+    u64 counts_cap = 0;                    // pairs
+    // giant-step scratch
+    WindowState *state = nullptr;
+    GiantTask *tasks = nullptr;  // kCostBuckets buckets of infra_batch_cap tasks
+    unsigned long long *lists = nullptr;
+    u32 *lres = nullptr;
+    u16 *tables = nullptr;
+    u64 infra_bytes = 0;
+    u64 infra_batch_cap = 0;
+    u32 infra_emax_cap = 0;
+    u32 infra_tsize_cap = 0;
+    bool ready = false;
+};
+
 // Autotuner height bins: bin b holds 10^(b/2) <= d < 10^((b+1)/2), b < 25.
 constexpr int kTuneBins = 25;
 constexpr int kTuneFirstBin = 12;  // below 10^6 the plain walk, untimed
@@ -148,27 +176,13 @@ struct eis_ctx {
     u32 nsmall = 0;    // primes with p^2 < 4096
     u32 nsmall_p = 0;  // primes with p < 4096
 
-    // pass buffers
-    SegInfo *d_segs = nullptr;
-    SegInfo *h_segs = nullptr;      // pinned staging
-    u64 *d_roff = nullptr;
-    u64 roff_cap = 0;
-    u32 *d_sq_words = nullptr;
-    u32 *d_eis_words = nullptr;
-    u32 *d_list_plain = nullptr;
-    u32 *d_list_giant = nullptr;
-    u32 *d_fb_list = nullptr;
-    PassCounters *d_ctrs = nullptr;  // [0] plain walk, [1] giant steps, [2] hand-offs,
-                                     // [3] hand-offs of the retry round
-    unsigned long long *d_counts = nullptr;
-    u64 counts_cap = 0;              // pairs
+    // pass buffers (the context's own, allocated on first use)
+    PassBufs pb;
     unsigned long long *h_counts = nullptr;  // pinned
     u64 h_counts_cap = 0;
-    u32 *d_q = nullptr;              // giant-step queue heads (3 cache lines), then the task
-                                     // counts of the cost buckets (one line each)
-    bool pass_ready = false;
     bool uncollected = false;            // a pass whose counters nobody has read yet
     hipStream_t pending_stream = nullptr;  // the stream it runs on
+    PassCounters *pending_ctrs = nullptr;  // its counters
     bool pending_retry = false;          // it has the retry round
 
     // per-kernel timing (EIS_FLAG_KERNEL_TIMES): event pairs of this pass
@@ -176,17 +190,6 @@ struct eis_ctx {
     std::vector<hipEvent_t> kev;
     std::vector<int> kev_kind;
     u32 kev_used = 0;
-
-    // giant-step scratch
-    WindowState *d_state = nullptr;
-    GiantTask *d_tasks = nullptr;  // kCostBuckets buckets of infra_batch_cap tasks
-    unsigned long long *d_lists = nullptr;
-    u32 *d_lres = nullptr;
-    u16 *d_tables = nullptr;
-    u64 infra_bytes = 0;
-    u64 infra_batch_cap = 0;
-    u32 infra_emax_cap = 0;
-    u32 infra_tsize_cap = 0;
     u64 bytes_held = 0;
 
     // captured pass sequences, by shape
@@ -304,20 +307,20 @@ static void load_tune_cache(eis_ctx *c)
 
 static void free_infra(eis_ctx *c)
 {
-    (void)hipFree(c->d_state);
-    (void)hipFree(c->d_tasks);
-    (void)hipFree(c->d_lists);
-    (void)hipFree(c->d_lres);
-    (void)hipFree(c->d_tables);
-    c->d_state = nullptr;
-    c->d_tasks = nullptr;
-    c->d_lists = nullptr;
-    c->d_lres = nullptr;
-    c->d_tables = nullptr;
-    c->bytes_held -= c->infra_bytes;
-    c->infra_bytes = 0;
-    c->infra_batch_cap = 0;
-    c->infra_emax_cap = c->infra_tsize_cap = 0;
+    (void)hipFree(c->pb.state);
+    (void)hipFree(c->pb.tasks);
+    (void)hipFree(c->pb.lists);
+    (void)hipFree(c->pb.lres);
+    (void)hipFree(c->pb.tables);
+    c->pb.state = nullptr;
+    c->pb.tasks = nullptr;
+    c->pb.lists = nullptr;
+    c->pb.lres = nullptr;
+    c->pb.tables = nullptr;
+    c->bytes_held -= c->pb.infra_bytes;
+    c->pb.infra_bytes = 0;
+    c->pb.infra_batch_cap = 0;
+    c->pb.infra_emax_cap = c->pb.infra_tsize_cap = 0;
 }
 
 static void drop_graphs(eis_ctx *c)
@@ -346,17 +349,17 @@ extern "C" void eis_destroy(eis_ctx *c)
     drop_graphs(c);
     free_infra(c);
     (void)hipFree(c->d_primes);
-    (void)hipFree(c->d_segs);
-    (void)hipFree(c->d_roff);
-    (void)hipFree(c->d_sq_words);
-    (void)hipFree(c->d_eis_words);
-    (void)hipFree(c->d_list_plain);
-    (void)hipFree(c->d_list_giant);
-    (void)hipFree(c->d_fb_list);
-    (void)hipFree(c->d_ctrs);
-    (void)hipFree(c->d_counts);
-    (void)hipFree(c->d_q);
-    if (c->h_segs) (void)hipHostFree(c->h_segs);
+    (void)hipFree(c->pb.segs);
+    (void)hipFree(c->pb.roff);
+    (void)hipFree(c->pb.sq_words);
+    (void)hipFree(c->pb.eis_words);
+    (void)hipFree(c->pb.list_plain);
+    (void)hipFree(c->pb.list_giant);
+    (void)hipFree(c->pb.fb_list);
+    (void)hipFree(c->pb.ctrs);
+    (void)hipFree(c->pb.counts);
+    (void)hipFree(c->pb.q);
+    if (c->pb.h_segs) (void)hipHostFree(c->pb.h_segs);
     if (c->h_counts) (void)hipHostFree(c->h_counts);
     if (c->ev_walk0) (void)hipEventDestroy(c->ev_walk0);
     if (c->ev_walk1) (void)hipEventDestroy(c->ev_walk1);
@@ -461,48 +464,48 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
 
 static int ensure_pass_buffers(eis_ctx *c)
 {
-    if (c->pass_ready) return EIS_OK;
+    if (c->pb.ready) return EIS_OK;
     const u64 need = kMaxSegments * sizeof(SegInfo) + 2ull * kPassWords * 4 +
                      3ull * kPassCandidates * 4 + kPassCounterSets * sizeof(PassCounters) + kQueueWords * 4;
     if (c->bytes_held + need > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
-    if (hipMalloc(&c->d_segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&c->h_segs), kMaxSegments * sizeof(SegInfo),
+    if (hipMalloc(&c->pb.segs, kMaxSegments * sizeof(SegInfo)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->pb.h_segs), kMaxSegments * sizeof(SegInfo),
                       hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&c->d_sq_words, (u64)kPassWords * 4) != hipSuccess ||
-        hipMalloc(&c->d_eis_words, (u64)kPassWords * 4) != hipSuccess ||
-        hipMalloc(&c->d_list_plain, kPassCandidates * 4) != hipSuccess ||
-        hipMalloc(&c->d_list_giant, kPassCandidates * 4) != hipSuccess ||
-        hipMalloc(&c->d_fb_list, kPassCandidates * 4) != hipSuccess ||
-        hipMalloc(&c->d_ctrs, kPassCounterSets * sizeof(PassCounters)) != hipSuccess ||
-        hipMalloc(&c->d_q, kQueueWords * 4) != hipSuccess)
+        hipMalloc(&c->pb.sq_words, (u64)kPassWords * 4) != hipSuccess ||
+        hipMalloc(&c->pb.eis_words, (u64)kPassWords * 4) != hipSuccess ||
+        hipMalloc(&c->pb.list_plain, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->pb.list_giant, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->pb.fb_list, kPassCandidates * 4) != hipSuccess ||
+        hipMalloc(&c->pb.ctrs, kPassCounterSets * sizeof(PassCounters)) != hipSuccess ||
+        hipMalloc(&c->pb.q, kQueueWords * 4) != hipSuccess)
         return EIS_ENOMEM;
     c->bytes_held += need;
-    c->pass_ready = true;
+    c->pb.ready = true;
     return EIS_OK;
 }
 
 static int ensure_roff(eis_ctx *c, u64 n)
 {
-    if (c->roff_cap >= n) return EIS_OK;
-    (void)hipFree(c->d_roff);
-    c->d_roff = nullptr;
-    c->roff_cap = 0;
-    if (hipMalloc(&c->d_roff, n * sizeof(u64)) != hipSuccess) return EIS_ENOMEM;
-    c->roff_cap = n;
+    if (c->pb.roff_cap >= n) return EIS_OK;
+    (void)hipFree(c->pb.roff);
+    c->pb.roff = nullptr;
+    c->pb.roff_cap = 0;
+    if (hipMalloc(&c->pb.roff, n * sizeof(u64)) != hipSuccess) return EIS_ENOMEM;
+    c->pb.roff_cap = n;
     drop_graphs(c);  // captured sequences hold the old pointer
     return EIS_OK;
 }
 
 static int ensure_counts(eis_ctx *c, u64 pairs)
 {
-    if (c->counts_cap < pairs) {
-        (void)hipFree(c->d_counts);
-        c->d_counts = nullptr;
-        c->counts_cap = 0;
+    if (c->pb.counts_cap < pairs) {
+        (void)hipFree(c->pb.counts);
+        c->pb.counts = nullptr;
+        c->pb.counts_cap = 0;
         u64 cap = std::max<u64>(pairs, kMaxSegments);
-        if (hipMalloc(&c->d_counts, cap * 2 * sizeof(unsigned long long)) != hipSuccess)
+        if (hipMalloc(&c->pb.counts, cap * 2 * sizeof(unsigned long long)) != hipSuccess)
             return EIS_ENOMEM;
-        c->counts_cap = cap;
+        c->pb.counts_cap = cap;
         drop_graphs(c);
     }
     if (c->h_counts_cap < pairs) {
@@ -531,26 +534,26 @@ static u64 infra_bytes_per_d(u32 emax, u32 tsize)
 static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
 {
     const u64 cap = (batch + 63) / 64 * 64;
-    if (c->d_lists && c->infra_batch_cap >= cap && c->infra_emax_cap >= emax &&
-        c->infra_tsize_cap >= tsize)
+    if (c->pb.lists && c->pb.infra_batch_cap >= cap && c->pb.infra_emax_cap >= emax &&
+        c->pb.infra_tsize_cap >= tsize)
         return EIS_OK;
     free_infra(c);
     drop_graphs(c);
     const u64 bytes = cap * infra_bytes_per_d(emax, tsize);
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
-    if (hipMalloc(&c->d_lists, cap * emax * 8) != hipSuccess ||
-        hipMalloc(&c->d_lres, cap * emax * 4) != hipSuccess ||
-        hipMalloc(&c->d_tables, cap * tsize * 2) != hipSuccess ||
-        hipMalloc(&c->d_state, cap * sizeof(WindowState)) != hipSuccess ||
-        hipMalloc(&c->d_tasks, cap * kCostBuckets * sizeof(GiantTask)) != hipSuccess) {
+    if (hipMalloc(&c->pb.lists, cap * emax * 8) != hipSuccess ||
+        hipMalloc(&c->pb.lres, cap * emax * 4) != hipSuccess ||
+        hipMalloc(&c->pb.tables, cap * tsize * 2) != hipSuccess ||
+        hipMalloc(&c->pb.state, cap * sizeof(WindowState)) != hipSuccess ||
+        hipMalloc(&c->pb.tasks, cap * kCostBuckets * sizeof(GiantTask)) != hipSuccess) {
         free_infra(c);
         return EIS_ENOMEM;
     }
-    c->infra_bytes = bytes;
+    c->pb.infra_bytes = bytes;
     c->bytes_held += bytes;
-    c->infra_batch_cap = cap;
-    c->infra_emax_cap = emax;
-    c->infra_tsize_cap = tsize;
+    c->pb.infra_batch_cap = cap;
+    c->pb.infra_emax_cap = emax;
+    c->pb.infra_tsize_cap = tsize;
     return EIS_OK;
 }
 
@@ -623,16 +626,17 @@ struct PassPlan {
 };
 
 // Fill the pinned segment table and the plan of a pass.
-static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl)
+static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u64 infra_avail,
+                      u64 batch_min, PassPlan &pl)
 {
     pl = PassPlan();
-    pl.nseg = (u32)segs.size();
+    pl.nseg = nseg;
     u32 word = 0, block = 0;
     u64 roff = 0;
     double nmax_giant = 0.0;  // largest wscale * d^(1/4) of the giant-step segments
     for (u32 s = 0; s < pl.nseg; s++) {
         const HostSeg &h = segs[s];
-        SegInfo &g = c->h_segs[s];
+        SegInfo &g = hs[s];
         g.d0 = h.d0;
         g.n = h.n;
         g.word_off = word;
@@ -664,9 +668,7 @@ static void plan_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl
     if (pl.giant_cand) {
         infra_geometry(nmax_giant, pl.emax, pl.tsize);
         const u64 per_d = infra_bytes_per_d(pl.emax, pl.tsize);
-        const u64 held = c->bytes_held - c->infra_bytes;  // other buffers of the context
-        const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
-        const u64 fit = std::max<u64>(avail / per_d / kInfraBatchMin * kInfraBatchMin, kInfraBatchMin);
+        const u64 fit = std::max<u64>(infra_avail / per_d / batch_min * batch_min, batch_min);
         pl.batch = std::min<u64>(pl.giant_cand, fit);
         pl.nbatches = (u32)((pl.giant_cand + pl.batch - 1) / pl.batch);
         const u64 max_win = (u64)c->num_cu * c->window_blocks_per_cu;
@@ -730,59 +732,60 @@ static int kt_end(eis_ctx *c, hipStream_t st)
 
 // Enqueue the launch sequence of a planned pass (after the segment table
 // upload).  Captured into graphs by shape.
-static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, bool timed)
+static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, const PassBufs &B, hipStream_t st,
+                             bool timed)
 {
-    PassCounters *ctr_plain = c->d_ctrs, *ctr_giant = c->d_ctrs + 1, *ctr_fb = c->d_ctrs + 2,
-                 *ctr_fb2 = c->d_ctrs + 3;
+    PassCounters *ctr_plain = B.ctrs, *ctr_giant = B.ctrs + 1, *ctr_fb = B.ctrs + 2,
+                 *ctr_fb2 = B.ctrs + 3;
     const bool kt = timed && c->kernel_times;
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_ctrs),
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(B.ctrs),
                             kPassCounterSets * sizeof(PassCounters) / 4, st));
-    HIP_TRY(launch_zero_u32(c->d_eis_words, pl.words, st));
+    HIP_TRY(launch_zero_u32(B.eis_words, pl.words, st));
     KLAUNCH(EIS_K_PRIME_OFFSETS,
-            launch_prime_offsets(c->d_primes, c->d_segs, pl.nseg, pl.np_max, c->d_roff, st));
-    KLAUNCH(EIS_K_SIEVE, launch_sieve(c->d_primes, c->d_roff, c->d_segs, pl.nseg, pl.nblocks,
-                                      c->nsmall, c->nsmall_p, c->d_sq_words, c->d_list_plain,
+            launch_prime_offsets(c->d_primes, B.segs, pl.nseg, pl.np_max, B.roff, st));
+    KLAUNCH(EIS_K_SIEVE, launch_sieve(c->d_primes, B.roff, B.segs, pl.nseg, pl.nblocks,
+                                      c->nsmall, c->nsmall_p, B.sq_words, B.list_plain,
                                       ctr_plain,
-                                      c->d_list_giant, ctr_giant, st));
+                                      B.list_giant, ctr_giant, st));
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk0, st));
     WalkParams wp;
-    wp.segs = c->d_segs;
+    wp.segs = B.segs;
     wp.nseg = pl.nseg;
-    wp.eis_words = c->d_eis_words;
+    wp.eis_words = B.eis_words;
     wp.max_steps = (u32)c->cfg.max_steps_per_d;
     if (pl.plain_cand) {
-        wp.list = c->d_list_plain;
+        wp.list = B.list_plain;
         wp.ctr = ctr_plain;
         KLAUNCH(EIS_K_WALK_PLAIN, launch_walk_baby(wp, pl.grid_plain, st));
     }
     if (pl.giant_cand) {
         InfraParams ip;
-        ip.segs = c->d_segs;
+        ip.segs = B.segs;
         ip.nseg = pl.nseg;
-        ip.list = c->d_list_giant;
+        ip.list = B.list_giant;
         ip.list_ctr = ctr_giant;
         ip.batch = (u32)pl.batch;
         ip.ctr = ctr_giant;
-        ip.win_next = c->d_q;
-        ip.giant_next = c->d_q + 16;
-        ip.fb_list = c->d_fb_list;
+        ip.win_next = B.q;
+        ip.giant_next = B.q + 16;
+        ip.fb_list = B.fb_list;
         ip.fb_ctr = ctr_fb;
-        ip.state = c->d_state;
-        ip.tasks = c->d_tasks;
-        ip.task_cap = (u32)c->infra_batch_cap;
-        ip.gbuckets = c->d_q + 3 * 16;
-        ip.lists = c->d_lists;
-        ip.lres = c->d_lres;
-        ip.tables = c->d_tables;
+        ip.state = B.state;
+        ip.tasks = B.tasks;
+        ip.task_cap = (u32)B.infra_batch_cap;
+        ip.gbuckets = B.q + 3 * 16;
+        ip.lists = B.lists;
+        ip.lres = B.lres;
+        ip.tables = B.tables;
         ip.emax = pl.emax;
         ip.tsize = pl.tsize;
         ip.max_steps = (u32)c->cfg.max_steps_per_d;
         ip.max_giants = 1u << 20;
         ip.emain_shift = 0;
-        ip.eis_words = c->d_eis_words;
+        ip.eis_words = B.eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
-            HIP_TRY(launch_zero_u32(c->d_q, kQueueWords, st));
+            HIP_TRY(launch_zero_u32(B.q, kQueueWords, st));
             KLAUNCH(EIS_K_WALK_WINDOW, launch_walk_window(ip, pl.grid_win, false, st));
             KLAUNCH(EIS_K_BUILD_TABLES, launch_build_tables(ip, pl.grid_tables, false, st));
             KLAUNCH(EIS_K_GIANT_SQUARE, launch_giant_square(ip, false, st));
@@ -795,23 +798,23 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
         // giant ideals.  With one batch per pass the hand-offs fit the batch
         // buffers; the plain walk then takes what the retry hands off.  Its
         // kernels exit at once when there is nothing to retry.
-        wp.list = c->d_fb_list;
+        wp.list = B.fb_list;
         wp.ctr = ctr_fb;
         if (pl.nbatches == 1) {
             InfraParams rp = ip;
-            rp.list = c->d_fb_list;
+            rp.list = B.fb_list;
             rp.list_ctr = ctr_fb;
             rp.k0 = 0;
             // its hand-offs go to the plain walk's list, which that walk,
             // earlier on the stream, no longer needs
-            rp.fb_list = c->d_list_plain;
+            rp.fb_list = B.list_plain;
             rp.fb_ctr = ctr_fb2;
             rp.emain_shift = kRetryShift;
             if (kt) {
                 int r = kt_begin(c, st, EIS_K_GIANT_RETRY);
                 if (r != EIS_OK) return r;
             }
-            HIP_TRY(launch_zero_u32(c->d_q, kQueueWords, st));
+            HIP_TRY(launch_zero_u32(B.q, kQueueWords, st));
             HIP_TRY(launch_walk_window(rp, c->num_cu, true, st));
             HIP_TRY(launch_build_tables(rp, c->num_cu, true, st));
             HIP_TRY(launch_giant_square(rp, true, st));
@@ -820,7 +823,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
                 int r = kt_end(c, st);
                 if (r != EIS_OK) return r;
             }
-            wp.list = c->d_list_plain;
+            wp.list = B.list_plain;
             wp.ctr = ctr_fb2;
         }
         // the rest: the plain walk, exact for all d
@@ -828,8 +831,8 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, hipStream_t st, boo
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev_walk1, st));
     KLAUNCH(EIS_K_POPCOUNT,
-            launch_popcount_segs(c->d_sq_words, c->d_eis_words, c->d_segs, pl.nseg,
-                                 (u32)((kPassCandidates + 31) / 32), c->d_counts, st));
+            launch_popcount_segs(B.sq_words, B.eis_words, B.segs, pl.nseg,
+                                 (u32)((kPassCandidates + 31) / 32), B.counts, st));
     return EIS_OK;
 }
 
@@ -840,33 +843,21 @@ static std::vector<u64> plan_key(const eis_ctx *c, const PassPlan &pl)
             pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d};
 }
 
-// Run one pass of segments (counts are accumulated into d_counts, which the
-// caller zeroes).  Synchronous when `sync`.
-static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st, bool graph,
-                    PassPlan &pl)
+// Enqueue a planned pass on buffer set B, whose segment table is in place:
+// a graph replay when `graph` (captured on first use, keyed by the pass
+// shape and the buffer set), else launch by launch (with the per-kernel
+// events when `timed`).
+static int launch_pass(eis_ctx *c, const PassPlan &pl, const PassBufs &B, hipStream_t st,
+                       bool graph, bool timed)
 {
-    (void)hipGetLastError();  // launch checks below must not see an older error
-    int rc = settle_pending(c);
-    if (rc != EIS_OK) return rc;
-    c->kev_used = 0;
-    rc = ensure_pass_buffers(c);
-    if (rc != EIS_OK) return rc;
-    plan_pass(c, segs, pl);
-    rc = ensure_roff(c, std::max<u64>(pl.roff_total, 1));
-    if (rc != EIS_OK) return rc;
-    if (pl.giant_cand) {
-        rc = ensure_infra(c, pl.batch, pl.emax, pl.tsize);
-        if (rc != EIS_OK) return rc;
-    }
-    HIP_TRY(hipMemcpyAsync(c->d_segs, c->h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
-    u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches + (pl.nbatches == 1 ? 5 : 0) : 0);
     if (graph && c->use_graphs && st == c->stream) {
-        const std::vector<u64> key = plan_key(c, pl);
+        std::vector<u64> key = plan_key(c, pl);
+        key.push_back((u64)reinterpret_cast<uintptr_t>(B.ctrs));
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            int brc = enqueue_pass_body(c, pl, st, false);
+            int brc = enqueue_pass_body(c, pl, B, st, false);
             hipError_t e = hipStreamEndCapture(st, &g);
             if (brc != EIS_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -883,15 +874,48 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
         HIP_TRY(hipEventRecord(c->ev_walk0, st));
         HIP_TRY(hipGraphLaunch(it->second, st));
         HIP_TRY(hipEventRecord(c->ev_walk1, st));
-    } else {
-        rc = enqueue_pass_body(c, pl, st, true);
-        if (rc != EIS_OK) return rc;
+        return EIS_OK;
     }
+    return enqueue_pass_body(c, pl, B, st, timed);
+}
+
+// Record that a pass is in flight on `st` with counters `ctrs`.
+static void mark_pending(eis_ctx *c, const PassPlan &pl, PassCounters *ctrs, hipStream_t st)
+{
     c->uncollected = true;
     c->pending_stream = st;
+    c->pending_ctrs = ctrs;
     c->pending_retry = pl.giant_cand && pl.nbatches == 1;
+    const u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches + (pl.nbatches == 1 ? 5 : 0) : 0);
     std::lock_guard<std::mutex> lk(c->stats_mu);
     c->stats.launches += launches;
+}
+
+// Run one pass of segments on the context's buffers (counts are accumulated
+// into c->pb.counts, which the caller zeroes).  Asynchronous: the counters
+// are read by collect_pass once the stream has finished.
+static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st, bool graph,
+                    PassPlan &pl)
+{
+    (void)hipGetLastError();  // launch checks below must not see an older error
+    int rc = settle_pending(c);
+    if (rc != EIS_OK) return rc;
+    c->kev_used = 0;
+    rc = ensure_pass_buffers(c);
+    if (rc != EIS_OK) return rc;
+    const u64 held = c->bytes_held - c->pb.infra_bytes;  // other buffers of the context
+    const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
+    plan_pass(c, segs.data(), (u32)segs.size(), c->pb.h_segs, avail, kInfraBatchMin, pl);
+    rc = ensure_roff(c, std::max<u64>(pl.roff_total, 1));
+    if (rc != EIS_OK) return rc;
+    if (pl.giant_cand) {
+        rc = ensure_infra(c, pl.batch, pl.emax, pl.tsize);
+        if (rc != EIS_OK) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(c->pb.segs, c->pb.h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
+    rc = launch_pass(c, pl, c->pb, st, graph, true);
+    if (rc != EIS_OK) return rc;
+    mark_pending(c, pl, c->pb.ctrs, st);
     return EIS_OK;
 }
 
@@ -900,7 +924,7 @@ static int collect_pass(eis_ctx *c)
 {
     c->uncollected = false;
     PassCounters h[kPassCounterSets];
-    if (hipMemcpy(h, c->d_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
+    if (hipMemcpy(h, c->pending_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
     if (!have_ms) (void)hipGetLastError();
@@ -959,7 +983,7 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
     if (rc != EIS_OK) return rc;
     const u64 n = eis_num_candidates(a, b);
     const u64 d0 = eis_first_candidate(a);
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4, st));
     HIP_TRY(hipEventRecord(c->ev_all0, st));
     int status = EIS_OK;
     for (u64 off = 0; off < n; off += kPassCandidates) {
@@ -977,10 +1001,10 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
         if (rc != EIS_OK) return rc;
         const size_t bytes = (pn + 7) / 8;
         const size_t boff = off / 8;
-        if (h_sq) HIP_TRY(hipMemcpyAsync(h_sq + boff, c->d_sq_words, bytes, hipMemcpyDeviceToHost, st));
-        if (h_eis) HIP_TRY(hipMemcpyAsync(h_eis + boff, c->d_eis_words, bytes, hipMemcpyDeviceToHost, st));
-        if (d_sq) HIP_TRY(hipMemcpyAsync(d_sq + boff, c->d_sq_words, bytes, hipMemcpyDeviceToDevice, st));
-        if (d_eis) HIP_TRY(hipMemcpyAsync(d_eis + boff, c->d_eis_words, bytes, hipMemcpyDeviceToDevice, st));
+        if (h_sq) HIP_TRY(hipMemcpyAsync(h_sq + boff, c->pb.sq_words, bytes, hipMemcpyDeviceToHost, st));
+        if (h_eis) HIP_TRY(hipMemcpyAsync(h_eis + boff, c->pb.eis_words, bytes, hipMemcpyDeviceToHost, st));
+        if (d_sq) HIP_TRY(hipMemcpyAsync(d_sq + boff, c->pb.sq_words, bytes, hipMemcpyDeviceToDevice, st));
+        if (d_eis) HIP_TRY(hipMemcpyAsync(d_eis + boff, c->pb.eis_words, bytes, hipMemcpyDeviceToDevice, st));
         if (sync || off + kPassCandidates < n) {
             // the pass buffers are reused: wait before the next pass
             HIP_TRY(hipStreamSynchronize(st));
@@ -989,14 +1013,14 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
         }
     }
     if (d_counts_out) {
-        HIP_TRY(hipMemcpyAsync(d_counts_out, c->d_counts, 2 * sizeof(unsigned long long),
+        HIP_TRY(hipMemcpyAsync(d_counts_out, c->pb.counts, 2 * sizeof(unsigned long long),
                                hipMemcpyDeviceToDevice, st));
     }
     HIP_TRY(hipEventRecord(c->ev_all1, st));
     if (sync) {
         HIP_TRY(hipStreamSynchronize(st));
         unsigned long long hc[2] = {0, 0};
-        HIP_TRY(hipMemcpy(hc, c->d_counts, sizeof(hc), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hc, c->pb.counts, sizeof(hc), hipMemcpyDeviceToHost));
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, c->ev_all0, c->ev_all1) == hipSuccess) {
             std::lock_guard<std::mutex> lk(c->stats_mu);
@@ -1168,7 +1192,7 @@ extern "C" int eis_count_batch_set(eis_ctx *c, int set, const uint64_t *a, const
     if (rc == EIS_OK) rc = ensure_counts(c, std::max<u64>(n, 1));
     if (rc != EIS_OK) return rc;
     hipStream_t st = c->stream;
-    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * std::max<u64>(n, 1), st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4 * std::max<u64>(n, 1), st));
     HIP_TRY(hipEventRecord(c->ev_all0, st));
     int status = EIS_OK;
     for (const auto &segs : passes) {
@@ -1181,7 +1205,7 @@ extern "C" int eis_count_batch_set(eis_ctx *c, int set, const uint64_t *a, const
     }
     HIP_TRY(hipEventRecord(c->ev_all1, st));
     if (n) {
-        HIP_TRY(hipMemcpyAsync(c->h_counts, c->d_counts, 2 * n * sizeof(unsigned long long),
+        HIP_TRY(hipMemcpyAsync(c->h_counts, c->pb.counts, 2 * n * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -1262,12 +1286,12 @@ static void server_loop(eis_ctx *c)
             if (rc == EIS_OK) rc = ensure_counts(c, segs.size());
             if (rc == EIS_OK) {
                 hipStream_t st = c->stream;
-                if (launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4 * segs.size(), st) != hipSuccess)
+                if (launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4 * segs.size(), st) != hipSuccess)
                     rc = EIS_EDEVICE;
                 PassPlan pl;
                 if (rc == EIS_OK) rc = run_pass(c, segs, st, true, pl);
                 if (rc == EIS_OK &&
-                    hipMemcpyAsync(c->h_counts, c->d_counts, 2 * segs.size() * sizeof(unsigned long long),
+                    hipMemcpyAsync(c->h_counts, c->pb.counts, 2 * segs.size() * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, st) != hipSuccess)
                     rc = EIS_EDEVICE;
                 if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
@@ -1404,7 +1428,7 @@ static int time_pass(eis_ctx *c, u64 d0, u32 n, u32 method, double ws, float &ms
     hipStream_t st = c->stream;
     int rc = settle_pending(c);
     if (rc == EIS_OK) rc = ensure_counts(c, 1);
-    if (rc == EIS_OK && launch_zero_u32(reinterpret_cast<u32 *>(c->d_counts), 4, st) != hipSuccess)
+    if (rc == EIS_OK && launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4, st) != hipSuccess)
         rc = EIS_EDEVICE;
     PassPlan pl;
     if (rc == EIS_OK && hipEventRecord(c->ev_all0, st) != hipSuccess) rc = EIS_EDEVICE;
