@@ -190,6 +190,31 @@ int eis_classify(eis_ctx *ctx, uint64_t a, uint64_t b, uint8_t *sqfree_bits,
 int eis_classify_async(eis_ctx *ctx, uint64_t a, uint64_t b, void *d_sqfree_bits,
                        void *d_eis_bits, uint64_t *d_counts2, void *hip_stream);
 
+/* Largest range, in candidates, of one eis_classify_async_noalloc call, and
+ * the size of the device scratch that call works in. */
+#define EIS_NOALLOC_MAX_CANDIDATES (1ULL << 20)
+#define EIS_NOALLOC_SCRATCH_BYTES (256ULL << 20)
+
+/* eis_classify_async for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and error behaviour as
+ * eis_classify_async, but the call allocates nothing: every buffer its
+ * kernels use beyond the caller's outputs (segment table, prime offsets, work
+ * lists, counters, pass bitmaps and the giant-step lists, tables and tasks)
+ * lives in one file-scope device array of EIS_NOALLOC_SCRATCH_BYTES per
+ * device, which the loaded library holds until the process ends; its address
+ * is looked up once per device by eis_create.  The range is one pass of at
+ * most EIS_NOALLOC_MAX_CANDIDATES candidates: a larger one gives EIS_ENOMEM
+ * and nothing is enqueued.  Giant-step batches are sized to the scratch
+ * (about 8*10^4 d's near 10^12), so a range at that height takes several.
+ * Every call on one device shares that device's scratch, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one device -- on different streams, contexts or threads --
+ * race, while calls on one stream are ordered.  Results are valid once the
+ * stream reaches them; step-budget overruns are reported by eis_last_error. */
+int eis_classify_async_noalloc(eis_ctx *ctx, uint64_t a, uint64_t b, void *d_sqfree_bits,
+                               void *d_eis_bits, uint64_t *d_counts2, void *hip_stream);
+
 /* Status of the asynchronous calls since the last eis_last_error (EIS_OK,
  * or EIS_EINTERNAL if a walk of theirs overran its step budget).  Waits for
  * the last pass they left running, on the stream it was enqueued on (which

@@ -24,4 +24,5 @@ from ._lib import (  # noqa: F401
     eis_strerror,
     eis_abi_version,
     EXPORTED_SYMBOLS,
+    NOALLOC_MAX_CANDIDATES,
 )

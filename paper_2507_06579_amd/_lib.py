@@ -27,8 +27,10 @@ EXPORTED_SYMBOLS = [
     "eis_first_candidate", "eis_count", "eis_classify", "eis_classify_async",
     "eis_last_error", "eis_count_batch", "eis_submit", "eis_wait", "eis_cancel",
     "eis_get_stats", "eis_strerror", "eis_abi_version", "eis_tune", "eis_tuned_choice",
-    "eis_count_set", "eis_count_batch_set",
+    "eis_count_set", "eis_count_batch_set", "eis_classify_async_noalloc",
 ]
+# eis_classify_async_noalloc's limit (EIS_NOALLOC_MAX_CANDIDATES)
+NOALLOC_MAX_CANDIDATES = 1 << 20
 
 
 class Status(enum.IntEnum):
@@ -138,6 +140,8 @@ def lib():
     L.eis_classify.restype = c_int
     L.eis_classify_async.argtypes = [vp, u64, u64, vp, vp, vp, vp]
     L.eis_classify_async.restype = c_int
+    L.eis_classify_async_noalloc.argtypes = [vp, u64, u64, vp, vp, vp, vp]
+    L.eis_classify_async_noalloc.restype = c_int
     L.eis_last_error.argtypes = [vp]; L.eis_last_error.restype = c_int
     L.eis_count_batch.argtypes = [vp, vp, vp, sz, vp, vp]; L.eis_count_batch.restype = c_int
     L.eis_submit.argtypes = [vp, u64, u64, P(u64)]; L.eis_submit.restype = c_int
@@ -245,6 +249,15 @@ class Context:
         _check(lib().eis_classify_async(self._h, a, b, sq_ptr or None, eis_ptr or None,
                                         counts_ptr or None, stream or None),
                "eis_classify_async")
+
+    def eis_classify_async_noalloc(self, a: int, b: int, sq_ptr: int, eis_ptr: int,
+                                   counts_ptr: int, stream: int = 0):
+        """Like eis_classify_async, but the library allocates nothing (its
+        kernels work in a fixed device scratch; at most
+        EIS_NOALLOC_MAX_CANDIDATES candidates)."""
+        _check(lib().eis_classify_async_noalloc(self._h, a, b, sq_ptr or None, eis_ptr or None,
+                                                counts_ptr or None, stream or None),
+               "eis_classify_async_noalloc")
 
     def eis_last_error(self) -> int:
         return int(lib().eis_last_error(self._h))

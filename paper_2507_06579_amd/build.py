@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libeis.so")
 
-SOURCES = ["eis_api.cpp", "eis_kernels.hip", "eis_infra.hip"]
+SOURCES = ["eis_api.cpp", "eis_kernels.hip", "eis_infra.hip", "eis_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

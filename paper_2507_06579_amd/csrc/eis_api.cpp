@@ -448,6 +448,9 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
         c->walk_blocks_per_cu = walk_baby_blocks_per_cu();
         c->window_blocks_per_cu = walk_window_blocks_per_cu();
         c->giant_blocks_per_cu = walk_giant_blocks_per_cu();
+        // the no-allocation scratch of this device: its address is looked
+        // up here, once per device (a failure shows in that entry point)
+        (void)noalloc_scratch_init(c->device);
         if (!c->tune_path.empty()) load_tune_cache(c);
     } while (0);
     if (rc != EIS_OK) {
@@ -1106,6 +1109,111 @@ extern "C" int eis_classify_async(eis_ctx *c, uint64_t a, uint64_t b, void *d_sq
                    reinterpret_cast<unsigned long long *>(d_counts2), st, false);
     if (rc == EIS_EINTERNAL) c->async_status = rc;
     return rc;
+}
+
+// Buffers of one pass carved out of the no-allocation scratch at `base`:
+// the fixed part for a single segment of at most kNoAllocMaxCandidates
+// candidates, then the giant-step scratch of the planned batch.  Returns the
+// offset of the giant-step part, or the first byte past the end.
+static u64 carve_fixed(eis_ctx *c, unsigned char *base, PassBufs &B)
+{
+    u64 off = 0;
+    auto take = [&](u64 bytes) {
+        unsigned char *p = base + off;
+        off = (off + bytes + 255) / 256 * 256;
+        return p;
+    };
+    const u64 words = kNoAllocMaxCandidates / 32 + 1;
+    B = PassBufs();
+    B.segs = reinterpret_cast<SegInfo *>(take(sizeof(SegInfo)));
+    B.ctrs = reinterpret_cast<PassCounters *>(take(kPassCounterSets * sizeof(PassCounters)));
+    B.q = reinterpret_cast<u32 *>(take(kQueueWords * 4));
+    B.counts = reinterpret_cast<unsigned long long *>(take(2 * sizeof(unsigned long long)));
+    B.counts_cap = 1;
+    B.roff_cap = c->primes_host.size();
+    B.roff = reinterpret_cast<u64 *>(take(B.roff_cap * sizeof(u64)));
+    B.sq_words = reinterpret_cast<u32 *>(take(words * 4));
+    B.eis_words = reinterpret_cast<u32 *>(take(words * 4));
+    B.list_plain = reinterpret_cast<u32 *>(take(kNoAllocMaxCandidates * 4));
+    B.list_giant = reinterpret_cast<u32 *>(take(kNoAllocMaxCandidates * 4));
+    B.fb_list = reinterpret_cast<u32 *>(take(kNoAllocMaxCandidates * 4));
+    B.ready = true;
+    return off;
+}
+
+static bool carve_infra(unsigned char *base, u64 off, const PassPlan &pl, PassBufs &B)
+{
+    const u64 cap = (pl.batch + 63) / 64 * 64;
+    const u64 sizes[5] = {cap * pl.emax * 8, cap * pl.emax * 4, cap * pl.tsize * 2,
+                          cap * sizeof(WindowState), cap * kCostBuckets * sizeof(GiantTask)};
+    unsigned char *p[5];
+    for (int k = 0; k < 5; k++) {
+        p[k] = base + off;
+        off = (off + sizes[k] + 255) / 256 * 256;
+    }
+    if (off > kNoAllocScratchBytes) return false;
+    B.lists = reinterpret_cast<unsigned long long *>(p[0]);
+    B.lres = reinterpret_cast<u32 *>(p[1]);
+    B.tables = reinterpret_cast<u16 *>(p[2]);
+    B.state = reinterpret_cast<WindowState *>(p[3]);
+    B.tasks = reinterpret_cast<GiantTask *>(p[4]);
+    B.infra_batch_cap = cap;
+    B.infra_emax_cap = pl.emax;
+    B.infra_tsize_cap = pl.tsize;
+    return true;
+}
+
+extern "C" int eis_classify_async_noalloc(eis_ctx *c, uint64_t a, uint64_t b,
+                                          void *d_sqfree_bits, void *d_eis_bits,
+                                          uint64_t *d_counts2, void *hip_stream)
+{
+    if (!c) return EIS_EINVAL;
+    int rc = check_range(a, b);
+    if (rc != EIS_OK) return rc;
+    const u64 n = eis_num_candidates(a, b);
+    if (n > kNoAllocMaxCandidates) return EIS_ENOMEM;
+    hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : c->stream;
+    std::lock_guard<std::mutex> g(c->gpu_mu);
+    if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
+    if (n == 0) {
+        if (d_counts2) HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(d_counts2), 4, st));
+        return EIS_OK;
+    }
+    unsigned char *base = static_cast<unsigned char *>(noalloc_scratch(c->device));
+    if (!base) return EIS_EDEVICE;
+    (void)hipGetLastError();  // launch checks below must not see an older error
+    rc = settle_pending(c);
+    if (rc != EIS_OK) return rc;
+    c->kev_used = 0;
+    PassBufs B;
+    const u64 infra_off = carve_fixed(c, base, B);
+    HostSeg h;
+    h.d0 = eis_first_candidate(a);
+    h.n = (u32)n;
+    h.slot = 0;
+    h.method = method_for(c, h.d0);
+    h.wscale = (float)scale_for(c, h.d0);
+    h.dst_bit = 0;
+    SegInfo hs;
+    PassPlan pl;
+    // the giant-step part: five arrays, each rounded up to 256 bytes
+    plan_pass(c, &h, 1, &hs, kNoAllocScratchBytes - infra_off - 5 * 256, 64, pl);
+    if (pl.roff_total > B.roff_cap) return EIS_EINTERNAL;
+    if (pl.giant_cand && !carve_infra(base, infra_off, pl, B)) return EIS_ENOMEM;
+    HIP_TRY(launch_store_seg(hs, B.segs, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(B.counts), 4, st));
+    rc = launch_pass(c, pl, B, st, false, false);
+    if (rc != EIS_OK) return rc;
+    const size_t bytes = (n + 7) / 8;
+    if (d_sqfree_bits)
+        HIP_TRY(hipMemcpyAsync(d_sqfree_bits, B.sq_words, bytes, hipMemcpyDeviceToDevice, st));
+    if (d_eis_bits)
+        HIP_TRY(hipMemcpyAsync(d_eis_bits, B.eis_words, bytes, hipMemcpyDeviceToDevice, st));
+    if (d_counts2)
+        HIP_TRY(hipMemcpyAsync(d_counts2, B.counts, 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToDevice, st));
+    mark_pending(c, pl, B.ctrs, st);
+    return EIS_OK;
 }
 
 extern "C" int eis_last_error(eis_ctx *c)

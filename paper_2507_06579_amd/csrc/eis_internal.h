@@ -188,4 +188,16 @@ int walk_giant_blocks_per_cu();
 // Occupancy helper: resident 256-thread blocks per CU of the baby walk.
 int walk_baby_blocks_per_cu();
 
+// ---- no-allocation entry point (eis_noalloc.hip) ---------------------------
+// Size of the file-scope device scratch, and the largest range (in
+// candidates) one call may cover.
+constexpr u64 kNoAllocScratchBytes = u64(256) << 20;
+constexpr u64 kNoAllocMaxCandidates = u64(1) << 20;
+// Look up the scratch's device address on `device` (current) once.
+hipError_t noalloc_scratch_init(int device);
+// That address, or null when the lookup failed or has not run.
+void *noalloc_scratch(int device);
+// Store one segment-table entry on the device from a kernel argument.
+hipError_t launch_store_seg(const SegInfo &s, SegInfo *dst, hipStream_t stream);
+
 }  // namespace eis
