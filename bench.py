@@ -261,10 +261,17 @@ def main():
                             "lookups")}
         work["walk_steps"] = ks[k]
         slots = sum(GIANT_SLOTS[key] * v for key, v in work.items())
+        fill = {}
+        for ph in ("compose", "walk"):
+            nph = st[f"giant_{ph}_phases"] - base[f"giant_{ph}_phases"]
+            nln = st[f"giant_{ph}_lanes"] - base[f"giant_{ph}_lanes"]
+            fill[ph] = {"phases_per_launch": int(nph / kl[k]),
+                        "busy_lanes_per_phase": round(nln / max(1, nph), 2)}
         return (slots, work["compositions"],
                 "giant step (composition, reduction, walk to a distinguished ideal, lookup)",
                 {"slots": GIANT_SLOTS,
-                 "work_per_launch": {key: int(v / kl[k]) for key, v in work.items()}})
+                 "work_per_launch": {key: int(v / kl[k]) for key, v in work.items()},
+                 "phase_fill": fill})
 
     dom = max(walks, key=lambda name: kms[eis.KERNELS.index(name)])
     kd = eis.KERNELS.index(dom)

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 6
+#define EIS_ABI_VERSION 7
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -148,6 +148,13 @@ typedef struct {
      * distinguished ideals later; `fallbacks` counts those it handed off
      * again, which the plain walk classifies */
     uint64_t giant_retries;
+    /* how full the giant-step walk's phases ran: the phases that looked up
+     * and composed, the phases that walked to distinguished ideals, and the
+     * lanes each kind kept busy (64 per phase at most) */
+    uint64_t giant_compose_phases;
+    uint64_t giant_compose_lanes;
+    uint64_t giant_walk_phases;
+    uint64_t giant_walk_lanes;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */

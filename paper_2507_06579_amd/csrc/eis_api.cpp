@@ -960,6 +960,10 @@ static int collect_pass(eis_ctx *c)
     c->stats.giant_gcd_branches += h[1].giant_gcd_branch;
     c->stats.giant_lookups += h[1].giant_lookups;
     c->stats.window_entries += h[1].window_entries;
+    c->stats.giant_compose_phases += h[1].giant_phases[0];
+    c->stats.giant_compose_lanes += h[1].giant_lanes[0];
+    c->stats.giant_walk_phases += h[1].giant_phases[1];
+    c->stats.giant_walk_lanes += h[1].giant_lanes[1];
     c->stats.refills += h[0].refills + h[1].refills + hf.refills;
     c->stats.fallbacks += hf.list_len;
     if (c->pending_retry) c->stats.giant_retries += h[2].list_len;

@@ -730,27 +730,49 @@ hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t str
 // ---------------------------------------------------------------------------
 constexpr u32 kNoEntry = ~0u;
 
-// Indices of the window entries with keys (qb, pa) and (qb, pc) in a d's
-// table (open addressing, linear probing), or kNoEntry.  The two probe
-// chains advance together, so that their loads overlap; a slot's
-// fingerprint match is confirmed against the full key in the list.
-__device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long long *lst, u32 mask,
-                                           u32 tsize, u32 qb, u32 pa, u32 pc, u32 &ea, u32 &ec)
+// Lookup of the window entries with keys (qb, pa) and (qb, pc) in a d's
+// table (open addressing, linear probing): their indices, or kNoEntry.  The
+// two probe chains advance together, so that their loads overlap; a slot's
+// fingerprint match is confirmed against the full key in the list.  Split in
+// two so that the first probe's loads can be issued well before their
+// values are needed (their latency then hides behind other work).
+struct DictProbe {
+    unsigned long long ka, kc;  // the two keys
+    u32 fa, fc;                 // their fingerprints
+    u32 sa, sc;                 // their first slots
+    u32 va, vc;                 // the first slots' contents (loads in flight)
+};
+
+__device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 mask, u32 qb, u32 pa, u32 pc)
 {
-    const unsigned long long ka = ((unsigned long long)qb << 32) | pa;
-    const unsigned long long kc = ((unsigned long long)qb << 32) | pc;
+    DictProbe d;
+    d.ka = ((unsigned long long)qb << 32) | pa;
+    d.kc = ((unsigned long long)qb << 32) | pc;
     const u32 ha = dict_hash(qb, pa), hc = dict_hash(qb, pc);
-    const u32 fa = slot_fp(ha), fc = slot_fp(hc);
-    u32 sa = ha & mask, sc = hc & mask;
+    d.fa = slot_fp(ha);
+    d.fc = slot_fp(hc);
+    d.sa = ha & mask;
+    d.sc = hc & mask;
+    d.va = tbl[d.sa];
+    d.vc = tbl[d.sc];
+    return d;
+}
+
+__device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long long *lst, u32 mask,
+                                             u32 tsize, DictProbe d, u32 &ea, u32 &ec)
+{
     bool da = false, dc = false;
     ea = ec = kNoEntry;
+    u32 va = d.va, vc = d.vc, sa = d.sa, sc = d.sc;
     for (u32 probe = 0; probe < tsize && !(da && dc); probe++) {
-        const u32 va = da ? 0u : tbl[sa];
-        const u32 vc = dc ? 0u : tbl[sc];
+        if (probe > 0) {
+            va = da ? 0u : tbl[sa];
+            vc = dc ? 0u : tbl[sc];
+        }
         if (!da) {
             if (va == 0u) {
                 da = true;
-            } else if ((va >> kSlotIndexBits) == fa && lst[(va & kSlotIndexMask) - 1] == ka) {
+            } else if ((va >> kSlotIndexBits) == d.fa && lst[(va & kSlotIndexMask) - 1] == d.ka) {
                 ea = (va & kSlotIndexMask) - 1;
                 da = true;
             }
@@ -759,7 +781,7 @@ __device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long l
         if (!dc) {
             if (vc == 0u) {
                 dc = true;
-            } else if ((vc >> kSlotIndexBits) == fc && lst[(vc & kSlotIndexMask) - 1] == kc) {
+            } else if ((vc >> kSlotIndexBits) == d.fc && lst[(vc & kSlotIndexMask) - 1] == d.kc) {
                 ec = (vc & kSlotIndexMask) - 1;
                 dc = true;
             }
@@ -768,19 +790,58 @@ __device__ __forceinline__ void dict_find2(const u16 *tbl, const unsigned long l
     }
 }
 
-// One d per lane, lanes refilled from a queue over the squaring kernel's
-// tasks, bucket 0 (longest estimated walks) first; a lane starts at g.  Two
-// phases per iteration: a lane that is not walking
-// composes (and reduces) its next giant ideal c_{k+1} = reduce(g c_k) by
-// NUCOMP; then every walking lane takes up to kWalkChunk reduction steps
-// towards the next distinguished ideal and, on reaching it, looks it up.  A
-// lane with a long walk continues it in the next iteration instead of
-// holding up the other lanes.
+// The giant walk keeps a pool of kPoolSlots d's per wave in LDS and runs
+// them in phases that every lane of the wave takes part in, instead of one d
+// per lane with the lanes at different stages:
+//   compose phase  up to 64 d's whose walk stands at a distinguished ideal:
+//                  each lane looks that ideal up (itself and its
+//                  conjugate), and on a miss composes the d's next giant
+//                  ideal c_{k+1} = reduce(g c_k) by NUCOMP (or, after the
+//                  first lookup, takes the precomputed second giant ideal);
+//   walk phase     up to 64 walking d's: each lane takes at most kPoolChunk
+//                  reduction steps towards the next distinguished ideal.
+// A phase runs once 64 d's are ready for it (else the fuller queue runs), so
+// that NUCOMP, the costliest part, runs with every lane busy, and a long
+// walk holds up only its own lane for one chunk.  The d's move between
+// three rings of slot numbers (free, compose, walk) whose heads and tails
+// only this wave touches: no barrier, no LDS atomic.  Free slots are filled
+// from the queue over the squaring kernel's tasks, bucket 0 (longest
+// estimated walks) first.
+constexpr u32 kPoolSlots = 128;  // d's per wave (a power of two)
+constexpr u32 kPoolMask = kPoolSlots - 1;
+constexpr u32 kPoolChunk = 16;   // reduction steps per walk phase
+
+// Structure of arrays, indexed by slot: a walk phase touches only the walk
+// fields.  pk packs the residues (bits 0-1 of g, 2-3 of c_k, 4-5 of the walk,
+// 6-7 of g2) and the walk's step count (bits 8-20).
+struct GiantPool {
+    u32 pos[kPoolSlots], item[kPoolSlots], ng[kPoolSlots], pk[kPoolSlots];
+    float sq[kPoolSlots], L[kPoolSlots];
+    float m1Q[kPoolSlots], m1P[kPoolSlots];           // the giant step g
+    float cQ[kPoolSlots], cP[kPoolSlots];             // the current giant ideal c_k
+    float Qw[kPoolSlots], Pw[kPoolSlots], Qpw[kPoolSlots];  // the walk from it
+    float g2Q[kPoolSlots], g2P[kPoolSlots], g2Qp[kPoolSlots];  // the second giant ideal
+    unsigned char ring[3][kPoolSlots];               // free, compose, walk
+};
+constexpr u32 kRingFree = 0, kRingCompose = 1, kRingWalk = 2;
+
+__device__ __forceinline__ u32 pk_make(u32 m1S, u32 cS, u32 Sw, u32 g2S, u32 w)
+{
+    return m1S | (cS << 2) | (Sw << 4) | (g2S << 6) | (w << 8);
+}
+
+// number of lanes below this one in mask m
+__device__ __forceinline__ u32 lanes_below(u64 m)
+{
+    return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
+}
+
 __device__ __forceinline__ void walk_giant_body(InfraParams p)
 {
     if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
     __shared__ SegLds segs[kMaxSegments];
     __shared__ u32 bstart[kCostBuckets + 1];  // queue index of each bucket's first task
+    __shared__ GiantPool pools[4];
     if (threadIdx.x == 0) {
         u32 acc = 0;
         for (u32 b = 0; b < kCostBuckets; b++) {
@@ -791,198 +852,240 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
     }
     load_segs(segs, p.segs, p.nseg);  // ends with a barrier
     const u32 n = bstart[kCostBuckets];
-    // the task of queue index q < n
     auto task_of = [&](u32 q) -> const GiantTask * {
         u32 b = 0;
 #pragma unroll
         for (u32 k = 1; k < kCostBuckets; k++) b += (q >= bstart[k]) ? 1u : 0u;
         return p.tasks + (u64)b * p.task_cap + (q - bstart[b]);
     };
+    GiantPool &pl = pools[threadIdx.x >> 6];
+    const u32 lane = __lane_id();
     const u32 mask = p.tsize - 1;
-    // per-lane state; the giant step g and the current giant ideal c are
-    // reduced ideals, kept like the walk in fp32 quarter units (exact)
-    u32 idx = 0, item = 0, ng = 0, pos = 0;
-    double dd = 0.0;
-    float L = 0.f;
-    float m1Q = 0.f, m1P = 0.f, cQ = 0.f, cP = 0.f;
-    u32 m1S = 0, cS = 0;
-    GiantIdeal g2 = {0.f, 0.f, 0.f, 0u};  // the second giant ideal
-    float sq = 0.f, sqc = 0.f;
-    float Qw = 0.f, Pw = 0.f, Qpw = 0.f;  // walk state, quarter units
-    u32 Sw = 0, w = 0;
-    bool walking = false;
-    u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
-    bool active = false;
-    u32 my_giants = 0;
+    // ring heads and tails (wave-uniform); every slot starts free
+    u32 head[3] = {0u, 0u, 0u}, tail[3] = {kPoolSlots, 0u, 0u};
+    for (u32 s = lane; s < kPoolSlots; s += 64) pl.ring[kRingFree][s] = (unsigned char)s;
+    auto push = [&](u32 r, bool f, u32 slot) {
+        const u64 m = __builtin_amdgcn_ballot_w64(f);
+        if (f) pl.ring[r][(tail[r] + lanes_below(m)) & kPoolMask] = (unsigned char)slot;
+        tail[r] += (u32)__builtin_popcountll(m);
+    };
+    auto handoff = [&](u32 item) {
+        const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+        p.fb_list[f] = item;
+    };
+    bool drained = false;
+    u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the task queue
+    u32 my_giants = 0, my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
     u64 my_steps = 0;
-    // work counts for the instruction model: compositions, their Euclid and
-    // reduction steps, gcd branches, lookups
-    u32 my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
-    // the lane's next task (queue index nq) and its position, item and g,
-    // loaded one refill ahead so that the loads complete during the giant walk
-    u32 nq = n;
-    wave_take(p.giant_next, n, true, nq, cbase, cend);
-    u32 npos = 0, nitem = 0;
-    GiantIdeal ngs = {0.f, 0.f, 0.f, 0u};  // its g
-    if (nq < n) {
-        const GiantTask *t = task_of(nq);
-        npos = t->pos;
-        nitem = t->item;
-        ngs = t->g;
-    }
+    // phases run (compose, walk) and the lanes they kept busy (wave-uniform)
+    u32 phases[2] = {0u, 0u}, lanes_on[2] = {0u, 0u};
 
     for (;;) {
-        for (;;) {
-            const bool want = !active && nq < n;
-            if (!__any(want)) break;
-            u32 g = n;
-            wave_take(p.giant_next, n, want, g, cbase, cend);
-            if (want) {
-                const GiantTask *cur = task_of(nq);
-                pos = npos;
-                item = nitem;
-                const GiantIdeal gs = ngs;
-                nq = g;
-                if (g < n) {
-                    const GiantTask *t = task_of(g);
-                    npos = t->pos;
-                    nitem = t->item;
-                    ngs = t->g;
-                }
-                if (gs.S == kSquareBad) {
-                    const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                    p.fb_list[f] = item;
+        u32 nfree = tail[kRingFree] - head[kRingFree];
+        u32 nc = tail[kRingCompose] - head[kRingCompose];
+        u32 nw = tail[kRingWalk] - head[kRingWalk];
+        // ---- refill: new d's into free slots, each starting its walk at g
+        if (!drained && (nfree >= 64 || (nfree > 0 && nc < 64 && nw < 64))) {
+            const bool want = lane < nfree;
+            u32 q = n;
+            wave_take(p.giant_next, n, want, q, cbase, cend);
+            drained = __any(want && q >= n);
+            bool take = false;
+            GiantTask t;
+            if (q < n) {
+                t = *task_of(q);
+                if (t.g.S == kSquareBad) {
+                    handoff(t.item);
                     my_giants += 1;
                 } else {
-                    idx = item_bit(segs, item);
-                    dd = (double)item_d(segs, item);
-                    sq = cur->s4;
-                    sqc = sq * kQuotBias;
-                    L = cur->L;
-                    // g = reduce(mu_1^2) is the first giant ideal and the step
-                    m1Q = gs.Q4;
-                    m1P = gs.P4;
-                    m1S = gs.S;
-                    g2 = cur->g2;  // needed a walk later
-                    cQ = m1Q;
-                    cP = m1P;
-                    cS = m1S;
-                    Qw = gs.Q4;
-                    Pw = gs.P4;
-                    Qpw = gs.Qp4;
-                    Sw = gs.S;
-                    w = 0;
-                    ng = 1;
-                    walking = true;
-                    active = true;
+                    take = true;
                 }
             }
+            const u64 mt = __builtin_amdgcn_ballot_w64(take);
+            if (take) {
+                const u32 s = pl.ring[kRingFree][(head[kRingFree] + lanes_below(mt)) & kPoolMask];
+                pl.pos[s] = t.pos;
+                pl.item[s] = t.item;
+                pl.ng[s] = 1u;
+                pl.pk[s] = pk_make(t.g.S, t.g.S, t.g.S, t.g2.S, 0u);
+                pl.sq[s] = t.s4;
+                pl.L[s] = t.L;
+                pl.m1Q[s] = t.g.Q4;
+                pl.m1P[s] = t.g.P4;
+                pl.cQ[s] = t.g.Q4;
+                pl.cP[s] = t.g.P4;
+                pl.Qw[s] = t.g.Q4;
+                pl.Pw[s] = t.g.P4;
+                pl.Qpw[s] = t.g.Qp4;
+                pl.g2Q[s] = t.g2.Q4;
+                pl.g2P[s] = t.g2.P4;
+                pl.g2Qp[s] = t.g2.Qp4;
+                pl.ring[kRingWalk][(tail[kRingWalk] + lanes_below(mt)) & kPoolMask] = (unsigned char)s;
+            }
+            const u32 nt = (u32)__builtin_popcountll(mt);
+            head[kRingFree] += nt;
+            tail[kRingWalk] += nt;
+            nw += nt;
         }
-        if (!__any(active)) break;
-
-        if (active) {
-            bool bad = false, done = false, flag = false;
-            if (!walking && ng == 1) {
-                // the second giant ideal, squared beforehand
-                Qw = g2.Q4;
-                Pw = g2.P4;
-                Qpw = g2.Qp4;
-                cQ = Qw;
-                cP = Pw;
-                cS = g2.S;
-                Sw = g2.S;
-                w = 0;
-                walking = true;
-                ng++;
-            } else if (!walking && ng < p.max_giants) {
+        if (nc == 0 && nw == 0) {
+            if (drained) break;
+            continue;
+        }
+        const bool compose = nc >= 64 || (nw < 64 && nc >= nw);
+        if (compose) {
+            // ---- lookup + compose phase -------------------------------------
+            // Two lookups at once: the ideal (Q_m, P_m) itself -- a hit means
+            // one period past a window ideal -- and its conjugate (Q_m,
+            // P_{m+1}) -- a hit means as many ideals short of a period as the
+            // window ideal lies past (1) (conjugation reverses the cycle and
+            // acts as log -> -log, so log eps = S_m + S_i).  A direct hit at
+            // the first lookup (g itself) is skipped: g may lie inside the
+            // window (a "unit" of distance 0); if it was a true hit, a later
+            // one is at eps or eps^2, whose residues are both 0 or both not.
+            // The first probe's loads are issued before the composition,
+            // which is computed for every lane that may need it (a lane whose
+            // lookup then hits drops it), so that NUCOMP hides their latency.
+            const bool on = lane < nc;
+            u32 s = 0;
+            if (on) s = pl.ring[kRingCompose][(head[kRingCompose] + lane) & kPoolMask];
+            head[kRingCompose] += min(nc, 64u);
+            phases[0]++;
+            lanes_on[0] += min(nc, 64u);
+            u32 ng = 0, pk = 0, item = 0, pos = 0;
+            DictProbe dp;
+            if (on) {
+                ng = pl.ng[s];
+                pk = pl.pk[s];
+                item = pl.item[s];
+                pos = pl.pos[s];
+                const float sq = pl.sq[s], sqc = sq * kQuotBias;
+                const float Qw = pl.Qw[s], Pw = pl.Pw[s], Qpw = pl.Qpw[s];
+                float Pn, Qn, acc1 = 0.f;
+                rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
+                dp = dict_start2(p.tables + (u64)pos * p.tsize, mask, __float_as_uint(Qw),
+                                 __float_as_uint(Pw), __float_as_uint(Pn));
+            }
+            const bool comp = on && ng > 1 && ng < p.max_giants;
+            bool cbad = false;
+            GiantWork cwk;  // the composition's work, counted when it is used
+            float cQ4 = 0.f, cP4 = 0.f, cQp4 = 0.f;
+            u32 Sk = 0;
+            if (comp) {
                 Form f3;
                 Gamma gm;
                 Chk ck;
                 GiantWork wk;
-                compose_ideals(4.0 * (double)m1Q, 4.0 * (double)m1P, 4.0 * (double)cQ,
-                               4.0 * (double)cP, dd, (double)L, f3, gm, ck, wk);
+                const double dd = (double)item_d(segs, item);
+                const float sq = pl.sq[s];
+                compose_ideals(4.0 * (double)pl.m1Q[s], 4.0 * (double)pl.m1P[s], 4.0 * (double)pl.cQ[s],
+                               4.0 * (double)pl.cP[s], dd, (double)pl.L[s], f3, gm, ck, wk);
                 const u32 lg = gamma_log(gm, ck);
                 double Qk, Pk, Qpk;
                 const u32 Sr = reduce_form(f3, dd, 4.0 * (double)sq, Qk, Pk, Qpk, ck, wk);
-                my_comps++;
-                my_eu += wk.euclid;
-                my_red += wk.reduce;
-                my_gcdb += wk.gcd_branch;
-                const u32 Sk = (m1S + cS + 3u - lg + Sr) % 3u;
-                bad = ck.bad();
-                if (!bad) {
-                    Qw = (float)Qk * 0.25f;
-                    Pw = (float)Pk * 0.25f;
-                    Qpw = (float)Qpk * 0.25f;
-                    cQ = Qw;
-                    cP = Pw;
-                    cS = Sk;
-                    Sw = Sk;
-                    w = 0;
-                    walking = true;
-                }
-                ng++;
+                cwk = wk;
+                Sk = ((pk & 3u) + ((pk >> 2) & 3u) + 3u - lg + Sr) % 3u;
+                cbad = ck.bad();
+                cQ4 = (float)Qk * 0.25f;
+                cP4 = (float)Pk * 0.25f;
+                cQp4 = (float)Qpk * 0.25f;
             }
-            if (walking && !bad) {
+            bool gone = false, next_walk = false;
+            if (on) {
+                u32 ed, ec;
+                dict_finish2(p.tables + (u64)pos * p.tsize, p.lists + (u64)pos * p.emax, mask, p.tsize,
+                             dp, ed, ec);
+                my_looks++;
+                const u32 Sw = (pk >> 4) & 3u;
+                const u32 *lrs = p.lres + (u64)pos * p.emax;
+                bool done = false, flag = false;
+                if (ed != kNoEntry && ng > 1) {
+                    const u32 St = (lrs[ed] >> 1) % 3u;
+                    flag = ((Sw + 3u - St) % 3u) == 0u;
+                    done = true;
+                } else if (ec != kNoEntry) {
+                    const u32 St = (lrs[ec] >> 1) % 3u;
+                    flag = ((Sw + St) % 3u) == 0u;
+                    done = true;
+                }
+                if (done) {
+                    emit_flag(p.eis_words, item_bit(segs, item), flag);
+                    my_giants += ng;
+                    gone = true;
+                } else if (ng == 1) {
+                    // the second giant ideal, squared beforehand
+                    const float gQ = pl.g2Q[s], gP = pl.g2P[s];
+                    const u32 gS = (pk >> 6) & 3u;
+                    pl.cQ[s] = gQ;
+                    pl.cP[s] = gP;
+                    pl.Qw[s] = gQ;
+                    pl.Pw[s] = gP;
+                    pl.Qpw[s] = pl.g2Qp[s];
+                    pl.pk[s] = pk_make(pk & 3u, gS, gS, gS, 0u);
+                    pl.ng[s] = 2u;
+                    next_walk = true;
+                } else if (!comp || cbad) {
+                    // the giant-step budget is spent, or a check failed
+                    handoff(item);
+                    my_giants += ng;
+                    gone = true;
+                } else {
+                    my_comps++;
+                    my_eu += cwk.euclid;
+                    my_red += cwk.reduce;
+                    my_gcdb += cwk.gcd_branch;
+                    pl.cQ[s] = cQ4;
+                    pl.cP[s] = cP4;
+                    pl.Qw[s] = cQ4;
+                    pl.Pw[s] = cP4;
+                    pl.Qpw[s] = cQp4;
+                    pl.pk[s] = pk_make(pk & 3u, Sk, Sk, (pk >> 6) & 3u, 0u);
+                    pl.ng[s] = ng + 1u;
+                    next_walk = true;
+                }
+            }
+            push(kRingWalk, next_walk, s);
+            push(kRingFree, gone, s);
+        } else {
+            // ---- walk phase -------------------------------------------------
+            const bool on = lane < nw;
+            u32 s = 0;
+            if (on) s = pl.ring[kRingWalk][(head[kRingWalk] + lane) & kPoolMask];
+            head[kRingWalk] += min(nw, 64u);
+            phases[1]++;
+            lanes_on[1] += min(nw, 64u);
+            bool at_dp = false, gone = false, more = false;
+            if (on) {
+                const float sq = pl.sq[s], sqc = sq * kQuotBias;
+                float Qw = pl.Qw[s], Pw = pl.Pw[s], Qpw = pl.Qpw[s];
+                const u32 pk = pl.pk[s];
                 u32 u = 0;
                 float acc = 0.f;
-                for (; u < kWalkChunk && !is_dp(Qw); u++) {
+                for (; u < kPoolChunk && !is_dp(Qw); u++) {
                     float Pn, Qn;
                     rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc);
                     Qpw = Qw;
                     Qw = Qn;
                     Pw = Pn;
                 }
-                Sw += (u + (u32)acc) >> 1;
-                w += u;
+                const u32 Sw = (((pk >> 4) & 3u) + ((u + (u32)acc) >> 1)) % 3u;
+                const u32 w = (pk >> 8) + u;
                 my_steps += u;
-                if (is_dp(Qw)) {
-                    // Two lookups at once: the ideal (Q_m, P_m) itself -- a
-                    // hit means one period past a window ideal -- and its
-                    // conjugate (Q_m, P_{m+1}) -- a hit means as many ideals
-                    // short of a period as the window ideal lies past (1)
-                    // (conjugation reverses the cycle and acts as
-                    // log -> -log, so log eps = S_m + S_i).  A direct hit
-                    // at the first lookup (after g itself) is skipped: g may
-                    // lie inside the window (a "unit" of distance 0); if it
-                    // was a true hit, a later one is at eps or eps^2, whose
-                    // residues are both 0 or both not.
-                    walking = false;
-                    float Pn, Qn, acc1 = 0.f;
-                    rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
-                    const u32 qb = __float_as_uint(Qw), pa = __float_as_uint(Pw),
-                              pc = __float_as_uint(Pn);
-                    const u16 *tbl = p.tables + (u64)pos * p.tsize;
-                    const unsigned long long *lst = p.lists + (u64)pos * p.emax;
-                    const u32 *lrs = p.lres + (u64)pos * p.emax;
-                    u32 ed, ec;
-                    dict_find2(tbl, lst, mask, p.tsize, qb, pa, pc, ed, ec);
-                    my_looks++;
-                    if (ed != kNoEntry && ng > 1) {
-                        const u32 St = (lrs[ed] >> 1) % 3u;
-                        flag = ((Sw + 3u - St) % 3u) == 0u;
-                        done = true;
-                    } else if (ec != kNoEntry) {
-                        const u32 St = (lrs[ec] >> 1) % 3u;
-                        flag = ((Sw + St) % 3u) == 0u;
-                        done = true;
-                    }
-                } else if (w >= kWalkLimit) {
-                    bad = true;
+                at_dp = is_dp(Qw);
+                if (!at_dp && w >= kWalkLimit) {
+                    handoff(pl.item[s]);
+                    my_giants += pl.ng[s];
+                    gone = true;
+                } else {
+                    pl.Qw[s] = Qw;
+                    pl.Pw[s] = Pw;
+                    pl.Qpw[s] = Qpw;
+                    pl.pk[s] = (pk & 0xcfu) | (Sw << 4) | (w << 8);
+                    more = !at_dp;
                 }
             }
-            if (done) {
-                emit_flag(p.eis_words, idx, flag);
-                my_giants += ng;
-                active = false;
-                walking = false;
-            } else if (bad || (!walking && ng >= p.max_giants)) {
-                const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                p.fb_list[f] = item;
-                my_giants += ng;
-                active = false;
-                walking = false;
-            }
+            push(kRingCompose, at_dp, s);
+            push(kRingWalk, more, s);
+            push(kRingFree, gone, s);
         }
     }
     u64 sums[6] = {my_giants, my_comps, my_eu, my_red, my_gcdb, my_looks};
@@ -991,7 +1094,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
 #pragma unroll
         for (int k = 0; k < 6; k++) sums[k] += __shfl_down(sums[k], off, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         atomicAdd(&p.ctr->chunk_steps, (unsigned long long)my_steps);
         atomicAdd(&p.ctr->giant_steps, (unsigned long long)sums[0]);
         atomicAdd(&p.ctr->giant_comps, (unsigned long long)sums[1]);
@@ -999,6 +1102,10 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
         atomicAdd(&p.ctr->giant_reduce, (unsigned long long)sums[3]);
         atomicAdd(&p.ctr->giant_gcd_branch, (unsigned long long)sums[4]);
         atomicAdd(&p.ctr->giant_lookups, (unsigned long long)sums[5]);
+        for (int k = 0; k < 2; k++) {
+            atomicAdd(&p.ctr->giant_phases[k], (unsigned long long)phases[k]);
+            atomicAdd(&p.ctr->giant_lanes[k], (unsigned long long)lanes_on[k]);
+        }
     }
 }
 

@@ -70,7 +70,8 @@ struct PassCounters {
     // work of the giant walk's compositions (see GiantWork)
     unsigned long long giant_comps, giant_euclid, giant_reduce, giant_lookups, giant_gcd_branch;
     unsigned long long window_entries;  // list appends of the window walk
-    u64 pad3[2];
+    // phases of the giant walk (compose, walk) and the lanes they kept busy
+    unsigned long long giant_phases[2], giant_lanes[2];
 };
 
 // The fields of a segment that the walk kernels need, kept in LDS.

@@ -95,6 +95,14 @@ def test_kernel_times_and_step_counts():
             # about one reduction step in 16
             ent = st["window_entries"]
             assert 0.04 < ent / ks[k.index("walk_window")] < 0.09
+            # the giant walk runs its d's in phases of at most 64 busy lanes:
+            # every lookup belongs to a compose phase, every walk step to a
+            # walk phase
+            for ph in ("compose", "walk"):
+                nph, nln = st[f"giant_{ph}_phases"], st[f"giant_{ph}_lanes"]
+                assert 0 < nph and nph <= nln <= 64 * nph
+            assert st["giant_compose_lanes"] >= looks
+            assert st["giant_walk_lanes"] * 16 >= ks[k.index("walk_giant")]
         assert all(x >= 0 for x in kms)
         assert 0 < sum(kms) <= st["last_total_ms"] * 1.05 + 0.5
     # without the flag nothing is timed
