@@ -7,7 +7,18 @@ line (see the keys below).  The workload is the last 10^8-window below 10^11
 (about 10.1 million members of D), whose Eisenstein count the paper prints
 in Table 1 (3,345,503); the bench checks it.
 
+The same line carries, under "configs", the other measurement
+configurations, each with its time, discriminants/s, the walk kernels'
+roofline fractions (VALU issue slots of their counted work over their
+event-timed duration) and the oracle's rate on a bounded sample of the same
+workload: d1 the plain walk on [5, 10^6]; d2 [10^9, 10^9 + 10^7) with both
+methods (identical bitmaps required); d3 the 64 seeded uneven ranges, one
+batched call against 64 single calls; d5 the seeded Poisson request stream
+served at 10 to 10^4 requests/s, past saturation (p50/p99 latency,
+throughput).  The headline roofline comes from the headline steps alone.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--method auto|baby|infra]
+                  [--no-configs] [--no-serving] [--no-cpu-baseline] [--no-tune]
 """
 from __future__ import annotations
 
@@ -144,6 +155,266 @@ def cpu_model() -> str:
         pass
     return "unknown CPU"
 
+def stats_delta(st1, st0):
+    """Counters of eis_get_stats accumulated between two snapshots."""
+    out = {}
+    for k, v in st1.items():
+        if isinstance(v, list):
+            out[k] = [x - y for x, y in zip(v, st0[k])]
+        elif isinstance(v, (int, float)) and k in st0:
+            out[k] = v - st0[k]
+    return out
+
+
+def slot_model(eis, name, d):
+    """(VALU issue slots, units of work, unit name, model details) of the
+    work a walk kernel did, from the counters `d` (a stats_delta)."""
+    k = eis.KERNELS.index(name)
+    ks, kl = d["kernel_steps"], max(1, d["kernel_launches"][k])
+    if name == "walk_window":
+        work = {"rho_steps": ks[k], "entries": d["window_entries"]}
+        slots = sum(WINDOW_SLOTS[key] * v for key, v in work.items())
+        return (slots, ks[k], "rho step",
+                {"slots": WINDOW_SLOTS,
+                 "work_per_launch": {key: int(v / kl) for key, v in work.items()}})
+    if name != "walk_giant":
+        return VALU_SLOTS_PER_STEP[name] * ks[k], ks[k], "rho step", None
+    work = {key: d["giant_" + key]
+            for key in ("compositions", "gcd_branches", "euclid_steps", "reduce_steps",
+                        "lookups")}
+    work["walk_steps"] = ks[k]
+    slots = sum(GIANT_SLOTS[key] * v for key, v in work.items())
+    fill = {}
+    for ph in ("compose", "walk"):
+        nph, nln = d[f"giant_{ph}_phases"], d[f"giant_{ph}_lanes"]
+        fill[ph] = {"phases_per_launch": int(nph / kl),
+                    "busy_lanes_per_phase": round(nln / max(1, nph), 2)}
+    return (slots, work["compositions"],
+            "giant step (composition, reduction, walk to a distinguished ideal, lookup)",
+            {"slots": GIANT_SLOTS,
+             "work_per_launch": {key: int(v / kl) for key, v in work.items()},
+             "phase_fill": fill})
+
+
+WALKS = ["walk_plain", "walk_handoff", "walk_window", "walk_giant"]
+KERNEL_NAME = {"walk_plain": "k_walk_baby", "walk_handoff": "k_walk_baby",
+               "walk_window": "k_walk_window", "walk_giant": "k_walk_giant"}
+
+
+def walk_rooflines(eis, d):
+    """Per walk kernel with timed launches in `d`: achieved VALU lane-slots/s
+    (model slots of its counted work / its summed event time) and the
+    fraction of the peak; the dominant kernel (longest) first."""
+    out = {}
+    for name in WALKS:
+        k = eis.KERNELS.index(name)
+        ms, nl = d["kernel_ms"][k], d["kernel_launches"][k]
+        if not nl or ms <= 0 or not d["kernel_steps"][k]:
+            continue
+        slots, units, uw, md = slot_model(eis, name, d)
+        ach = slots / (ms / 1e3)
+        ent = {"kernel": KERNEL_NAME[name], "bound": "alu", "achieved": round(ach / 1e12, 3),
+               "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T VALU lane-slots/s",
+               "frac": round(ach / PEAK_LANE_OPS, 4), "ms": round(ms, 3), "launches": nl,
+               "ops_per_unit": round(slots / max(1, units), 1), "unit_of_work": uw,
+               "units": int(units)}
+        if md:
+            ent["model"] = md
+        out[name] = ent
+    return dict(sorted(out.items(), key=lambda kv: -kv[1]["ms"]))
+
+
+def oracle_rate(members, target_s: float):
+    """The oracle on a prefix of `members` (a shuffled array of members of D)
+    sized for about target_s seconds on all host cores: (discriminants/s,
+    sample size, seconds, rho steps)."""
+    import oracle
+    cores = os.cpu_count() or 1
+    k0 = min(4 * cores, members.size)
+    t = time.perf_counter()
+    oracle.classify_list(members[:k0], nthreads=cores)
+    dt0 = max(time.perf_counter() - t, 1e-3)
+    k = int(min(members.size - k0, max(cores, k0 * target_s / dt0)))
+    if k <= 0:
+        return k0 / dt0, k0, dt0, 0
+    sample = members[k0:k0 + k]
+    t = time.perf_counter()
+    _, steps = oracle.classify_list(sample, nthreads=cores)
+    dt = time.perf_counter() - t
+    return sample.size / dt, int(sample.size), dt, int(steps)
+
+
+def members_of(ranges, total: int, seed: int):
+    """A shuffled array of about `total` members of D drawn from the given
+    ranges, each range contributing in proportion to its number of
+    candidates (uniformly within it); the oracle's sieve finds them."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(seed)
+    ncand = [oracle.num_candidates(a, b) for a, b in ranges]
+    tot = max(1, sum(ncand))
+    out = []
+    for (a, b), n in zip(ranges, ncand):
+        want = int(round(total * n / tot))
+        if n == 0 or want == 0:
+            continue
+        # a window of candidates around 1.3 times the wanted count (about
+        # 0.81 of the candidates are in D), placed at random in the range
+        m = min(n, int(want * 1.3) + 64)
+        start = int(rng.integers(0, n - m + 1))
+        d0 = oracle.first_candidate(a) + 8 * start
+        bits, _ = oracle.sqfree_range(d0, d0 + 8 * m)
+        idx = np.flatnonzero(np.unpackbits(bits, bitorder="little")[:m])
+        if idx.size > want:
+            idx = rng.choice(idx, want, replace=False)
+        out.append(d0 + 8 * idx.astype(np.uint64))
+    arr = np.concatenate(out) if out else np.zeros(0, dtype=np.uint64)
+    rng.shuffle(arr)
+    return arr
+
+
+def cpu_sample(members, target_s: float, what: str):
+    rate, k, dt, steps = oracle_rate(members, target_s)
+    cores = os.cpu_count() or 1
+    return {"value": round(rate, 2), "unit": "discriminants/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} random members of D from {what}, full-period walk ({steps} rho "
+                      f"steps, {dt:.1f} s on {cores} threads of {cpu_model()})"}
+
+
+def measure_configs(eis, tune_path, cpu: bool, log, serving: bool = True):
+    """The other measurement configurations: time, discriminants/s and the
+    walk kernels' roofline fractions of each, and the oracle's rate on a
+    bounded sample of the same workload."""
+    import numpy as np
+    from paper_2507_06579_amd import serve, workloads
+    out = {}
+    kt = eis.EIS_FLAG_KERNEL_TIMES
+
+    def timed_count(ctx, a, b, reps):
+        ctx.eis_count(a, b)
+        s0 = ctx.eis_get_stats()
+        best = float("inf")
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = ctx.eis_count(a, b)
+            best = min(best, time.perf_counter() - t)
+        d = stats_delta(ctx.eis_get_stats(), s0)
+        for key, v in d.items():  # per call
+            d[key] = [x / reps for x in v] if isinstance(v, list) else v / reps
+        return r, best, d
+
+    # d1: the plain walk on [5, 10^6]
+    a, b = workloads.SMALL
+    log(f"config d1: [{a}, {b}) plain walk")
+    with eis.Context(method=eis.Method.BABY, flags=kt) as c:
+        (n_sq, n_e), dt, d = timed_count(c, a, b, 5)
+    out["d1"] = {"workload": f"plain walk, all d = 5 mod 8 in [{a}, {b})", "pi_D": n_sq,
+                 "pi_E": n_e, "ms": round(dt * 1e3, 3),
+                 "discriminants_per_s": round(n_sq / dt, 1),
+                 "roofline": walk_rooflines(eis, d)}
+    if cpu:
+        import oracle
+        t = time.perf_counter()
+        r = oracle.classify_range(a, b, want_bits=False)
+        dtc = time.perf_counter() - t
+        assert (r["n_sqfree"], r["n_eis"]) == (n_sq, n_e)
+        out["d1"]["cpu_baseline"] = {
+            "value": round(n_sq / dtc, 2), "unit": "discriminants/s",
+            "cores": os.cpu_count() or 1, "kind": "oracle",
+            "sample": f"the whole range ({r['steps']} rho steps, {dtc:.2f} s on "
+                      f"{os.cpu_count() or 1} threads of {cpu_model()}); same counts"}
+
+    # d2: plain walk against giant steps at 10^9
+    a, b = workloads.MID
+    out["d2"] = {"workload": f"all d = 5 mod 8 in [{a}, {b}), both methods"}
+    bits = {}
+    for label, method in (("baby", eis.Method.BABY), ("infra", eis.Method.INFRA)):
+        log(f"config d2: [{a}, {b}) {label}")
+        with eis.Context(method=method, flags=kt) as c:
+            r = c.eis_classify(a, b)
+            (n_sq, n_e), dt, d = timed_count(c, a, b, 5)
+        bits[label] = (bytes(r[0]), bytes(r[1]), r[2], r[3])
+        out["d2"][label] = {"ms": round(dt * 1e3, 3), "discriminants_per_s": round(n_sq / dt, 1),
+                            "executed_rho_steps_per_s": round(d["baby_steps"] / dt, 1),
+                            "roofline": walk_rooflines(eis, d)}
+    if bits["baby"] != bits["infra"]:
+        raise SystemExit("d2: the two methods' bitmaps differ")
+    out["d2"]["pi_D"], out["d2"]["pi_E"] = bits["baby"][2], bits["baby"][3]
+    out["d2"]["identical_bitmaps"] = True
+    if cpu:
+        out["d2"]["cpu_baseline"] = cpu_sample(members_of([(a, b)], 2000000, 11), 5.0,
+                                               f"[{a}, {b})")
+
+    # d3: 64 uneven ranges, one batched call against 64 single calls
+    ranges = workloads.batch_ranges()
+    ra, rb = [x for x, _ in ranges], [y for _, y in ranges]
+    log("config d3: 64 uneven ranges, batched and one by one")
+    with eis.Context(tune_cache_path=tune_path) as c:
+        c.eis_count_batch(ra, rb)
+        s0 = c.eis_get_stats()
+        tb = float("inf")
+        for _ in range(3):
+            t = time.perf_counter()
+            sb, eb = c.eis_count_batch(ra, rb)
+            tb = min(tb, time.perf_counter() - t)
+        t = time.perf_counter()
+        singles = [c.eis_count(x, y) for x, y in ranges]
+        ts = time.perf_counter() - t
+    batched = [(int(x), int(y)) for x, y in zip(sb, eb)]
+    if batched != singles:
+        raise SystemExit("d3: batched and single counts differ")
+    with eis.Context(tune_cache_path=tune_path, flags=kt | eis.EIS_FLAG_NO_GRAPHS) as c:
+        c.eis_count_batch(ra, rb)
+        s0 = c.eis_get_stats()
+        c.eis_count_batch(ra, rb)
+        dk = stats_delta(c.eis_get_stats(), s0)
+    n_d = sum(x for x, _ in batched)
+    out["d3"] = {"workload": f"64 ranges, start log-uniform in [1e6, 1e11], width log-uniform "
+                             f"in [1e4, 1e7], seed {workloads.BATCH_SEED}",
+                 "members_of_D": n_d, "pi_E": sum(y for _, y in batched),
+                 "batched_ms": round(tb * 1e3, 3), "singles_ms": round(ts * 1e3, 3),
+                 "batched_discriminants_per_s": round(n_d / tb, 1),
+                 "singles_discriminants_per_s": round(n_d / ts, 1),
+                 "identical_counts": True,
+                 "roofline": walk_rooflines(eis, dk)}
+    if cpu:
+        out["d3"]["cpu_baseline"] = cpu_sample(members_of(ranges, 1500000, 13), 5.0,
+                                               "the 64 ranges (in proportion to their widths)")
+
+    if not serving:
+        return out
+    # d5: serving, open-loop Poisson arrivals swept past saturation
+    sweep = []
+    srv_members = None
+    with eis.Context(serve_slots=256, tune_cache_path=tune_path) as c:
+        for rate in (10.0, 100.0, 1000.0, 3000.0, 10000.0):
+            n = int(min(2000, max(20, rate * 3.0)))
+            reqs = workloads.serve_requests(n, rate)
+            log(f"config d5: {n} requests at {rate:g} req/s")
+            s0 = c.eis_get_stats()
+            res = serve.run_open_loop(c, reqs)
+            d = stats_delta(c.eis_get_stats(), s0)
+            row = {"rate_req_s": rate}
+            row.update(serve.summarize(res, reqs))
+            # the walk work done over the run's wall time, against the peak
+            slots = sum(slot_model(eis, name, d)[0] for name in WALKS)
+            row["walk_frac_of_peak_over_wall_time"] = round(slots / res["wall_s"] / PEAK_LANE_OPS, 4)
+            row["saturated"] = row["throughput_req_s"] < 0.9 * rate
+            sweep.append(row)
+            if srv_members is None or len(reqs) > len(srv_members):
+                srv_members = [(x, y) for _, x, y in reqs]
+    sat = [r["rate_req_s"] for r in sweep if r["saturated"]]
+    out["d5"] = {"workload": "range counts [a, a+w), a log-uniform in [1e6, 1e11], w log-uniform "
+                             f"in [1e3, 1e7], seed {workloads.SERVE_SEED}",
+                 "sweep": sweep,
+                 "max_throughput_req_s": max(r["throughput_req_s"] for r in sweep),
+                 "first_saturated_rate_req_s": sat[0] if sat else None}
+    if cpu:
+        out["d5"]["cpu_baseline"] = cpu_sample(members_of(srv_members, 1500000, 17), 5.0,
+                                               "the requested ranges (in proportion to their "
+                                               "widths)")
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -159,9 +430,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="auto method without running the autotuner first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=100.0)
-    ap.add_argument("--serve-n", type=int, default=300)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving sweep (config d5)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="measure the headline workload only (no d1-d3, d5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the per-d walks "
@@ -182,8 +454,11 @@ def main():
     sq = torch.zeros(nb, dtype=torch.uint8, device=dev)
     eb = torch.zeros(nb, dtype=torch.uint8, device=dev)
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    import tempfile
+    tune_dir = tempfile.mkdtemp(prefix="eis_tune_")
+    tune_path = os.path.join(tune_dir, "tune.json")
     ctx = eis.Context(device=0, method=method, flags=eis.EIS_FLAG_KERNEL_TIMES,
-                      window_scale=args.window_scale)
+                      window_scale=args.window_scale, tune_cache_path=tune_path)
     if method == eis.Method.AUTO and not args.no_tune:
         t = time.perf_counter()
         ctx.eis_tune()
@@ -331,22 +606,20 @@ def main():
         "roofline": roofline,
         "roofline_other_walks": others,
     }
-    if not args.no_serving:
-        from paper_2507_06579_amd import serve
-        log(f"serving: {args.serve_n} requests, Poisson at {args.serve_rate} req/s")
-        reqs = workloads.serve_requests(args.serve_n, args.serve_rate)
-        with eis.Context(device=0, serve_slots=256) as sctx:
-            res = serve.run_open_loop(sctx, reqs)
-        srv = serve.summarize(res, reqs)
-        srv["rate_req_s"] = args.serve_rate
-        srv["workload"] = ("range counts [a, a+w), a log-uniform in [1e6, 1e11], "
-                           "w log-uniform in [1e3, 1e7]")
-        out["p99_query_latency_ms"] = srv["p99_ms"]
-        out["serving"] = srv
+    ctx.close()
+    if not args.no_configs:
+        if not os.path.exists(tune_path):
+            tune_path = None  # untuned: the contexts of the configs take the defaults
+        cfgs = measure_configs(eis, tune_path, not args.no_cpu_baseline, log,
+                               serving=not args.no_serving)
+        out["configs"] = cfgs
+        if "d5" in cfgs:
+            row = next(r for r in cfgs["d5"]["sweep"] if r["rate_req_s"] == 100.0)
+            out["p99_query_latency_ms"] = row["p99_ms"]
+            out["serving"] = dict(row, workload=cfgs["d5"]["workload"])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(a, b)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
