@@ -155,6 +155,12 @@ typedef struct {
     uint64_t giant_compose_lanes;
     uint64_t giant_walk_phases;
     uint64_t giant_walk_lanes;
+    /* serving admission by device memory: the bytes the admitted requests
+     * hold for their giant-step scratch, and the budget they share (the
+     * context's mem_budget_bytes less its fixed buffers; 0 before the first
+     * eis_submit) */
+    uint64_t serve_bytes_reserved;
+    uint64_t serve_bytes_budget;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */
@@ -254,11 +260,19 @@ int eis_count_batch_set(eis_ctx *ctx, int set, const uint64_t *a, const uint64_t
 /* ----- Serving (continuous batching of range-count queries) ----------- */
 
 /* Queue the count of [a, b).  *ticket receives a handle for eis_wait.
- * A server thread (started by the first call) runs passes back to back; each
- * pass takes the next chunk (at most 2^20 candidates) of every admitted
- * request, so requests that arrive while others run join the next pass and
- * a large request does not hold up small ones (continuous batching).
- * EIS_EBUSY when serve_slots requests are already queued or running. */
+ * A server thread (started by the first call) runs passes back to back, two
+ * in flight at a time; each pass takes the next chunk (at most 2^20
+ * candidates) of every admitted request, so requests that arrive while
+ * others run join the next pass and a large request does not hold up small
+ * ones (continuous batching).  Admission is by slots and by device memory:
+ * a request reserves the giant-step scratch (dictionary lists, tables,
+ * window records, tasks) of its first chunk -- nothing at heights the plain
+ * walk takes -- against the serving budget (mem_budget_bytes less the
+ * context's fixed buffers; see eis_stats.serve_bytes_*), until it finishes
+ * or is cancelled.  EIS_EBUSY when serve_slots requests are already queued
+ * or running, or when the admitted requests hold so much of the budget that
+ * this one does not fit now (retry later); EIS_ENOMEM when it could not fit
+ * even alone.  Nothing is queued on error. */
 int eis_submit(eis_ctx *ctx, uint64_t a, uint64_t b, uint64_t *ticket);
 
 /* Wait up to timeout_us microseconds (< 0 = forever) for a ticket.  On

@@ -89,6 +89,8 @@ class EisStats(ctypes.Structure):
         ("giant_compose_lanes", ctypes.c_uint64),
         ("giant_walk_phases", ctypes.c_uint64),
         ("giant_walk_lanes", ctypes.c_uint64),
+        ("serve_bytes_reserved", ctypes.c_uint64),
+        ("serve_bytes_budget", ctypes.c_uint64),
     ]
 
     def as_dict(self):

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -113,6 +114,7 @@ struct Request {
     u64 dispatched = 0;  // candidates handed to passes
     u64 completed = 0;   // candidates whose pass has finished
     u64 n_sq = 0, n_eis = 0;
+    u64 reserved = 0;    // device bytes admitted for it (see chunk_footprint)
     int status = EIS_OK;
     bool cancelled = false;
     bool finished = false;
@@ -146,6 +148,22 @@ struct PassBufs {
     u32 infra_emax_cap = 0;
     u32 infra_tsize_cap = 0;
     bool ready = false;
+};
+
+// A pass of the server in flight: its own counters, counts and pinned host
+// staging (the host fills the next pass's segment table and reads the last
+// pass's counts while this one runs); the rest of the pass buffers is the
+// context's, which the passes use in stream order.
+struct Flight {
+    PassCounters *ctrs = nullptr;
+    unsigned long long *counts = nullptr;    // 2 per segment
+    SegInfo *h_segs = nullptr;               // pinned
+    unsigned long long *h_counts = nullptr;  // pinned
+    hipEvent_t done = nullptr;
+    std::vector<std::pair<u64, u64>> parts;  // (ticket, candidates) per segment
+    bool retry = false;
+    bool busy = false;
+    u64 seq = 0;
 };
 
 // Autotuner height bins: bin b holds 10^(b/2) <= d < 10^((b+1)/2), b < 25.
@@ -209,6 +227,12 @@ struct eis_ctx {
     u64 next_ticket = 1;
     bool stop = false;
     std::thread server;
+    Flight flights[2];
+    std::atomic<bool> flights_ready{false};
+    u64 flight_seq = 0;
+    u64 serve_budget = 0;    // device bytes for the requests' giant-step scratch
+    u64 serve_reserved = 0;  // of which the admitted requests hold
+    hipEvent_t ev_order = nullptr;  // orders other streams after the context's
 };
 
 // ---------------------------------------------------------------------------
@@ -222,10 +246,27 @@ static int hip_status(hipError_t e)
     return EIS_EDEVICE;
 }
 
-#define HIP_TRY(expr)                                \
-    do {                                             \
-        hipError_t _e = (expr);                      \
-        if (_e != hipSuccess) return hip_status(_e); \
+// With EIS_TRACE_ERRORS set in the environment, every failed HIP call is
+// reported on stderr with its source line (the status alone does not say
+// which call failed).
+static int hip_fail(hipError_t e, const char *what, int line)
+{
+    static const bool trace = std::getenv("EIS_TRACE_ERRORS") != nullptr;
+    if (trace) std::fprintf(stderr, "eis: line %d: %s: %s\n", line, what, hipGetErrorString(e));
+    return hip_status(e);
+}
+
+// a call whose failure is not acted on (teardown), reported when tracing
+#define HIP_IGNORE(expr)                                            \
+    do {                                                            \
+        hipError_t _e = (expr);                                     \
+        if (_e != hipSuccess) (void)hip_fail(_e, #expr, __LINE__);  \
+    } while (0)
+
+#define HIP_TRY(expr)                                               \
+    do {                                                            \
+        hipError_t _e = (expr);                                     \
+        if (_e != hipSuccess) return hip_fail(_e, #expr, __LINE__); \
     } while (0)
 
 extern "C" uint64_t eis_first_candidate(uint64_t a)
@@ -307,11 +348,11 @@ static void load_tune_cache(eis_ctx *c)
 
 static void free_infra(eis_ctx *c)
 {
-    (void)hipFree(c->pb.state);
-    (void)hipFree(c->pb.tasks);
-    (void)hipFree(c->pb.lists);
-    (void)hipFree(c->pb.lres);
-    (void)hipFree(c->pb.tables);
+    HIP_IGNORE(hipFree(c->pb.state));
+    HIP_IGNORE(hipFree(c->pb.tasks));
+    HIP_IGNORE(hipFree(c->pb.lists));
+    HIP_IGNORE(hipFree(c->pb.lres));
+    HIP_IGNORE(hipFree(c->pb.tables));
     c->pb.state = nullptr;
     c->pb.tasks = nullptr;
     c->pb.lists = nullptr;
@@ -325,7 +366,7 @@ static void free_infra(eis_ctx *c)
 
 static void drop_graphs(eis_ctx *c)
 {
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->graphs) HIP_IGNORE(hipGraphExecDestroy(kv.second));
     c->graphs.clear();
 }
 
@@ -344,29 +385,41 @@ extern "C" void eis_destroy(eis_ctx *c)
 {
     if (!c) return;
     stop_server(c);
-    (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    HIP_IGNORE(hipSetDevice(c->device));
+    if (c->stream) HIP_IGNORE(hipStreamSynchronize(c->stream));
+    for (Flight &f : c->flights) {
+        HIP_IGNORE(hipFree(f.ctrs));
+        HIP_IGNORE(hipFree(f.counts));
+        if (f.h_segs) HIP_IGNORE(hipHostFree(f.h_segs));
+        if (f.h_counts) HIP_IGNORE(hipHostFree(f.h_counts));
+        if (f.done) HIP_IGNORE(hipEventDestroy(f.done));
+    }
+    if (c->ev_order) HIP_IGNORE(hipEventDestroy(c->ev_order));
+    c->ev_order = nullptr;
+
     drop_graphs(c);
     free_infra(c);
-    (void)hipFree(c->d_primes);
-    (void)hipFree(c->pb.segs);
-    (void)hipFree(c->pb.roff);
-    (void)hipFree(c->pb.sq_words);
-    (void)hipFree(c->pb.eis_words);
-    (void)hipFree(c->pb.list_plain);
-    (void)hipFree(c->pb.list_giant);
-    (void)hipFree(c->pb.fb_list);
-    (void)hipFree(c->pb.ctrs);
-    (void)hipFree(c->pb.counts);
-    (void)hipFree(c->pb.q);
-    if (c->pb.h_segs) (void)hipHostFree(c->pb.h_segs);
-    if (c->h_counts) (void)hipHostFree(c->h_counts);
-    if (c->ev_walk0) (void)hipEventDestroy(c->ev_walk0);
-    if (c->ev_walk1) (void)hipEventDestroy(c->ev_walk1);
-    for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
-    if (c->ev_all0) (void)hipEventDestroy(c->ev_all0);
-    if (c->ev_all1) (void)hipEventDestroy(c->ev_all1);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+    HIP_IGNORE(hipFree(c->d_primes));
+    HIP_IGNORE(hipFree(c->pb.segs));
+    HIP_IGNORE(hipFree(c->pb.roff));
+    HIP_IGNORE(hipFree(c->pb.sq_words));
+    HIP_IGNORE(hipFree(c->pb.eis_words));
+    HIP_IGNORE(hipFree(c->pb.list_plain));
+    HIP_IGNORE(hipFree(c->pb.list_giant));
+    HIP_IGNORE(hipFree(c->pb.fb_list));
+    HIP_IGNORE(hipFree(c->pb.ctrs));
+    HIP_IGNORE(hipFree(c->pb.counts));
+    HIP_IGNORE(hipFree(c->pb.q));
+    if (c->pb.h_segs) HIP_IGNORE(hipHostFree(c->pb.h_segs));
+    if (c->h_counts) HIP_IGNORE(hipHostFree(c->h_counts));
+    if (c->ev_walk0) HIP_IGNORE(hipEventDestroy(c->ev_walk0));
+    if (c->ev_walk1) HIP_IGNORE(hipEventDestroy(c->ev_walk1));
+    for (hipEvent_t e : c->kev) HIP_IGNORE(hipEventDestroy(e));
+    if (c->ev_all0) HIP_IGNORE(hipEventDestroy(c->ev_all0));
+    if (c->ev_all1) HIP_IGNORE(hipEventDestroy(c->ev_all1));
+    if (c->stream) HIP_IGNORE(hipStreamDestroy(c->stream));
+    // teardown leaves no error pending in this thread for later calls
+    (void)hipGetLastError();
     delete c;
 }
 
@@ -487,9 +540,20 @@ static int ensure_pass_buffers(eis_ctx *c)
     return EIS_OK;
 }
 
+// Before a shared pass buffer is freed or replaced: let every pass already
+// enqueued on the context's stream (the server keeps up to two in flight)
+// finish with it.
+static int quiesce(eis_ctx *c)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return EIS_OK;
+}
+
 static int ensure_roff(eis_ctx *c, u64 n)
 {
     if (c->pb.roff_cap >= n) return EIS_OK;
+    int qrc = quiesce(c);
+    if (qrc != EIS_OK) return qrc;
     (void)hipFree(c->pb.roff);
     c->pb.roff = nullptr;
     c->pb.roff_cap = 0;
@@ -502,6 +566,8 @@ static int ensure_roff(eis_ctx *c, u64 n)
 static int ensure_counts(eis_ctx *c, u64 pairs)
 {
     if (c->pb.counts_cap < pairs) {
+        int qrc = quiesce(c);
+        if (qrc != EIS_OK) return qrc;
         (void)hipFree(c->pb.counts);
         c->pb.counts = nullptr;
         c->pb.counts_cap = 0;
@@ -540,6 +606,8 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
     if (c->pb.lists && c->pb.infra_batch_cap >= cap && c->pb.infra_emax_cap >= emax &&
         c->pb.infra_tsize_cap >= tsize)
         return EIS_OK;
+    int qrc = quiesce(c);
+    if (qrc != EIS_OK) return qrc;
     free_infra(c);
     drop_graphs(c);
     const u64 bytes = cap * infra_bytes_per_d(emax, tsize);
@@ -684,6 +752,7 @@ static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u6
 }
 
 static int collect_pass(eis_ctx *c);
+static int add_counters(eis_ctx *c, const PassCounters *h, bool retry);
 
 // Wait for the pass an asynchronous call left running (it may be on another
 // stream) before anything of a new call touches the shared buffers; its
@@ -858,6 +927,8 @@ static int launch_pass(eis_ctx *c, const PassPlan &pl, const PassBufs &B, hipStr
         key.push_back((u64)reinterpret_cast<uintptr_t>(B.ctrs));
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
+            // capture on an idle stream (a server pass may still be in flight)
+            HIP_TRY(hipStreamSynchronize(st));
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             int brc = enqueue_pass_body(c, pl, B, st, false);
@@ -923,11 +994,17 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
 }
 
 // Read the pass counters after the stream has finished the pass.
-static int collect_pass(eis_ctx *c)
+// Add the counters of a finished pass (at `ctrs`; `retry`: it had the retry
+// round) to the statistics; EIS_EINTERNAL if a walk of it overran its step
+// budget.  With `timed`, the pass's event pairs are read too.
+static int collect_counters(eis_ctx *c, PassCounters *ctrs, bool retry, bool timed)
 {
-    c->uncollected = false;
     PassCounters h[kPassCounterSets];
-    if (hipMemcpy(h, c->pending_ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
+    if (hipMemcpy(h, ctrs, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EIS_EDEVICE;
+    if (!timed) {
+        std::lock_guard<std::mutex> lk(c->stats_mu);
+        return add_counters(c, h, retry);
+    }
     float wms = 0.f;
     bool have_ms = hipEventElapsedTime(&wms, c->ev_walk0, c->ev_walk1) == hipSuccess;
     if (!have_ms) (void)hipGetLastError();
@@ -945,9 +1022,22 @@ static int collect_pass(eis_ctx *c)
         }
     }
     c->kev_used = 0;
+    return add_counters(c, h, retry);
+}
+
+// Read the pass counters after the stream has finished the pass.
+static int collect_pass(eis_ctx *c)
+{
+    c->uncollected = false;
+    return collect_counters(c, c->pending_ctrs, c->pending_retry, true);
+}
+
+// The counter sets of one pass into the statistics (stats_mu held).
+static int add_counters(eis_ctx *c, const PassCounters *h, bool retry)
+{
     c->stats.discriminants += (u64)h[0].list_len + h[1].list_len;
     // the hand-off walk ran on the retry round's list when there was one
-    const PassCounters &hf = c->pending_retry ? h[3] : h[2];
+    const PassCounters &hf = retry ? h[3] : h[2];
     c->stats.baby_steps += h[0].baby_steps + h[1].baby_steps + h[1].chunk_steps + hf.baby_steps;
     c->stats.kernel_steps[EIS_K_WALK_PLAIN] += h[0].baby_steps;
     c->stats.kernel_steps[EIS_K_WALK_WINDOW] += h[1].baby_steps;
@@ -966,7 +1056,7 @@ static int collect_pass(eis_ctx *c)
     c->stats.giant_walk_lanes += h[1].giant_lanes[1];
     c->stats.refills += h[0].refills + h[1].refills + hf.refills;
     c->stats.fallbacks += hf.list_len;
-    if (c->pending_retry) c->stats.giant_retries += h[2].list_len;
+    if (retry) c->stats.giant_retries += h[2].list_len;
     return (h[0].err_count | h[1].err_count | hf.err_count) ? EIS_EINTERNAL : EIS_OK;
 }
 
@@ -988,6 +1078,13 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
     int rc = settle_pending(c);
     if (rc == EIS_OK) rc = ensure_counts(c, 1);
     if (rc != EIS_OK) return rc;
+    if (st != c->stream) {
+        // the shared pass buffers may still be in use by passes on the
+        // context's own stream (the server's): order this stream after them
+        if (!c->ev_order) HIP_TRY(hipEventCreate(&c->ev_order));
+        HIP_TRY(hipEventRecord(c->ev_order, c->stream));
+        HIP_TRY(hipStreamWaitEvent(st, c->ev_order, 0));
+    }
     const u64 n = eis_num_candidates(a, b);
     const u64 d0 = eis_first_candidate(a);
     HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4, st));
@@ -1350,27 +1447,180 @@ extern "C" int eis_count_batch(eis_ctx *c, const uint64_t *a, const uint64_t *b,
 // order, the next chunk (at most kServeChunk candidates) of every admitted
 // request, up to the pass's capacity; a request finishes when its last chunk
 // has been through a pass.  Requests that arrive while a pass runs join the
-// next one, next to the remaining chunks of the earlier ones.
+// next one, next to the remaining chunks of the earlier ones.  Two passes
+// are in flight at a time (each with its own counters and host staging):
+// the server enqueues pass k+1 before it waits for pass k, so the device
+// does not idle while the host plans.
+//
+// Admission is by slots and by device memory.  The plain walk keeps no
+// per-d state beyond the fixed pass buffers; a chunk at a height that takes
+// giant steps needs the lists, tables, window records and tasks of its
+// candidates (chunk_footprint).  A request reserves its first chunk's
+// footprint against the serving budget (the context's budget less the fixed
+// buffers) while it is in the arrival order: eis_submit refuses it with
+// EIS_EBUSY while the admitted requests hold too much of the budget, and
+// with EIS_ENOMEM if it could not fit even alone.
+
+// Device bytes of giant-step scratch that n candidates from d0 hold while
+// their pass runs (0 at heights the plain walk takes).
+static u64 chunk_footprint(const eis_ctx *c, u64 d0, u64 n)
+{
+    if (n == 0 || !method_for(c, d0)) return 0;
+    const u64 dlast = d0 + 8 * (n - 1);
+    u32 emax = 0, tsize = 0;
+    infra_geometry((double)(float)scale_for(c, d0) * std::pow((double)dlast, 0.25), emax, tsize);
+    return n * infra_bytes_per_d(emax, tsize);
+}
+
+// The fixed buffers of serving and the two flights (gpu_mu held).
+static int ensure_flights(eis_ctx *c)
+{
+    if (c->flights_ready) return EIS_OK;
+    int rc = ensure_pass_buffers(c);
+    if (rc == EIS_OK) rc = ensure_roff(c, std::max<u64>(c->primes_host.size(), 1));
+    if (rc != EIS_OK) return rc;
+    const u64 per = kPassCounterSets * sizeof(PassCounters) + 2ull * kMaxSegments * 8;
+    if (c->bytes_held + 2 * per > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
+    for (Flight &f : c->flights) {
+        if (hipMalloc(&f.ctrs, kPassCounterSets * sizeof(PassCounters)) != hipSuccess ||
+            hipMalloc(&f.counts, 2ull * kMaxSegments * 8) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&f.h_segs), kMaxSegments * sizeof(SegInfo),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&f.h_counts), 2ull * kMaxSegments * 8,
+                          hipHostMallocDefault) != hipSuccess)
+            return EIS_ENOMEM;
+        if (hipEventCreate(&f.done) != hipSuccess) return EIS_EDEVICE;
+    }
+    c->bytes_held += 2 * per;
+    const u64 fixed = c->bytes_held - c->pb.infra_bytes;
+    c->serve_budget = c->cfg.mem_budget_bytes > fixed ? c->cfg.mem_budget_bytes - fixed : 0;
+    c->flights_ready = true;
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    c->stats.serve_bytes_budget = c->serve_budget;
+    return EIS_OK;
+}
+
+// Enqueue one pass of the server on flight f (gpu_mu held).
+static int enqueue_flight(eis_ctx *c, Flight &f, const std::vector<HostSeg> &segs)
+{
+    (void)hipGetLastError();  // launch checks below must not see an older error
+    int rc = settle_pending(c);
+    if (rc != EIS_OK) return rc;
+    hipStream_t st = c->stream;
+    const u64 held = c->bytes_held - c->pb.infra_bytes;
+    const u64 avail = c->cfg.mem_budget_bytes > held ? c->cfg.mem_budget_bytes - held : 0;
+    PassPlan pl;
+    plan_pass(c, segs.data(), (u32)segs.size(), f.h_segs, avail, kInfraBatchMin, pl);
+    rc = ensure_roff(c, std::max<u64>(pl.roff_total, 1));
+    if (rc == EIS_OK && pl.giant_cand) rc = ensure_infra(c, pl.batch, pl.emax, pl.tsize);
+    if (rc != EIS_OK) return rc;
+    PassBufs B = c->pb;
+    B.ctrs = f.ctrs;
+    B.counts = f.counts;
+    B.counts_cap = kMaxSegments;
+    HIP_TRY(hipMemcpyAsync(B.segs, f.h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(f.counts), 4ull * pl.nseg, st));
+    rc = launch_pass(c, pl, B, st, true, false);
+    if (rc != EIS_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(f.h_counts, f.counts, 2ull * pl.nseg * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(f.done, st));
+    f.retry = pl.giant_cand && pl.nbatches == 1;
+    f.busy = true;
+    f.seq = ++c->flight_seq;
+    const u64 launches = 7 + (pl.giant_cand ? 1 + 5ull * pl.nbatches + (pl.nbatches == 1 ? 5 : 0) : 0);
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    c->stats.launches += launches;
+    return EIS_OK;
+}
+
+// Hand the counts of a finished pass (or its error) to its requests and
+// retire what is finished or cancelled (smu taken here).
+static void finish_parts(eis_ctx *c, const std::vector<std::pair<u64, u64>> &parts,
+                         const unsigned long long *h_counts, int rc)
+{
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        for (size_t s = 0; s < parts.size(); s++) {
+            auto it = c->reqs.find(parts[s].first);
+            if (it == c->reqs.end()) continue;
+            Request &r = it->second;
+            if (rc != EIS_OK) {
+                r.status = rc;
+                r.finished = true;
+                continue;
+            }
+            r.n_sq += h_counts[2 * s];
+            r.n_eis += h_counts[2 * s + 1];
+            r.completed += parts[s].second;
+            if (r.completed >= r.ncand) r.finished = true;
+        }
+        // retire finished and cancelled requests from the arrival order, and
+        // release their device-memory reservations
+        std::deque<u64> keep;
+        for (u64 t : c->order) {
+            Request &r = c->reqs[t];
+            if (r.finished || (r.cancelled && r.completed >= r.dispatched)) {
+                if (!r.finished) r.finished = true;
+                c->serve_reserved -= r.reserved;
+                r.reserved = 0;
+                std::lock_guard<std::mutex> sl(c->stats_mu);
+                if (r.status == EIS_OK && !r.cancelled) c->stats.requests_done++;
+                c->stats.serve_bytes_reserved = c->serve_reserved;
+            } else {
+                keep.push_back(t);
+            }
+        }
+        c->order.swap(keep);
+    }
+    c->dcv.notify_all();
+}
+
+// Wait for flight f's pass and hand out its results.
+static void collect_flight(eis_ctx *c, Flight &f)
+{
+    int rc = (hipEventSynchronize(f.done) == hipSuccess) ? EIS_OK : EIS_EDEVICE;
+    if (rc == EIS_OK) rc = collect_counters(c, f.ctrs, f.retry, false);
+    f.busy = false;
+    finish_parts(c, f.parts, f.h_counts, rc);
+    f.parts.clear();
+}
 
 static void server_loop(eis_ctx *c)
 {
     (void)hipSetDevice(c->device);
+    int cur = 0;  // the flight the next pass goes to
     for (;;) {
         std::vector<HostSeg> segs;
         std::vector<std::pair<u64, u64>> parts;  // (ticket, candidates) per segment
+        bool stop = false;
         {
             std::unique_lock<std::mutex> lk(c->smu);
-            c->scv.wait(lk, [&] {
-                if (c->stop) return true;
+            auto has_work = [&] {
                 for (u64 t : c->order) {
                     const Request &r = c->reqs[t];
                     if (!r.cancelled && r.dispatched < r.ncand) return true;
                 }
                 return false;
-            });
-            if (c->stop) return;
+            };
+            const bool in_flight = c->flights[0].busy || c->flights[1].busy;
+            if (!in_flight) c->scv.wait(lk, [&] { return c->stop || has_work(); });
+            stop = c->stop;
+            // With a pass in flight, the next one is planned at once only
+            // when at least half a pass of work is waiting: a small pass
+            // queued behind a running one would hold up the requests that
+            // arrive meanwhile (they would wait for both), and under light
+            // load the device has no backlog to keep it busy anyway.
+            bool plan = !stop;
+            if (plan && in_flight) {
+                u64 waiting = 0;
+                for (u64 t : c->order) {
+                    const Request &r = c->reqs[t];
+                    if (!r.cancelled) waiting += r.ncand - r.dispatched;
+                }
+                plan = waiting >= kPassCandidates / 2;
+            }
             u64 cand = 0;
-            for (u64 t : c->order) {
+            for (u64 t : plan ? c->order : std::deque<u64>()) {
                 Request &r = c->reqs[t];
                 if (r.cancelled || r.dispatched >= r.ncand) continue;
                 if (segs.size() == kMaxSegments) break;
@@ -1383,7 +1633,7 @@ static void server_loop(eis_ctx *c)
                 h.n = (u32)take;
                 h.slot = (u32)segs.size();
                 h.method = method_for(c, h.d0);
-            h.wscale = (float)scale_for(c, h.d0);
+                h.wscale = (float)scale_for(c, h.d0);
                 h.dst_bit = 0;
                 segs.push_back(h);
                 parts.emplace_back(t, take);
@@ -1391,58 +1641,43 @@ static void server_loop(eis_ctx *c)
                 cand += (take + 31) / 32 * 32;
             }
         }
-        int rc = EIS_OK;
-        {
-            std::lock_guard<std::mutex> g(c->gpu_mu);
-            rc = settle_pending(c);
-            if (rc == EIS_OK) rc = ensure_counts(c, segs.size());
-            if (rc == EIS_OK) {
-                hipStream_t st = c->stream;
-                if (launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4 * segs.size(), st) != hipSuccess)
-                    rc = EIS_EDEVICE;
-                PassPlan pl;
-                if (rc == EIS_OK) rc = run_pass(c, segs, st, true, pl);
-                if (rc == EIS_OK &&
-                    hipMemcpyAsync(c->h_counts, c->pb.counts, 2 * segs.size() * sizeof(unsigned long long),
-                                   hipMemcpyDeviceToHost, st) != hipSuccess)
-                    rc = EIS_EDEVICE;
-                if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
-                if (rc == EIS_OK) rc = collect_pass(c);
+        if (stop) {
+            for (Flight &f : c->flights)
+                if (f.busy) {
+                    (void)hipEventSynchronize(f.done);
+                    f.busy = false;
+                }
+            return;
+        }
+        bool enqueued = false;
+        if (!segs.empty()) {
+            Flight &f = c->flights[cur];
+            if (f.busy) collect_flight(c, f);
+            int rc;
+            {
+                std::lock_guard<std::mutex> g(c->gpu_mu);
+                rc = enqueue_flight(c, f, segs);
+            }
+            f.parts = parts;
+            if (rc != EIS_OK) {
+                f.busy = false;
+                finish_parts(c, f.parts, nullptr, rc);
+                f.parts.clear();
+            } else {
+                enqueued = true;
+                cur ^= 1;
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(c->smu);
-            for (size_t s = 0; s < parts.size(); s++) {
-                auto it = c->reqs.find(parts[s].first);
-                if (it == c->reqs.end()) continue;
-                Request &r = it->second;
-                if (rc != EIS_OK) {
-                    r.status = rc;
-                    r.finished = true;
-                    continue;
-                }
-                r.n_sq += c->h_counts[2 * s];
-                r.n_eis += c->h_counts[2 * s + 1];
-                r.completed += parts[s].second;
-                if (r.completed >= r.ncand) r.finished = true;
-            }
-            // retire finished and cancelled requests from the arrival order
-            std::deque<u64> keep;
-            for (u64 t : c->order) {
-                Request &r = c->reqs[t];
-                if (r.finished || (r.cancelled && r.completed >= r.dispatched)) {
-                    if (!r.finished) r.finished = true;
-                    if (r.status == EIS_OK && !r.cancelled) {
-                        std::lock_guard<std::mutex> sl(c->stats_mu);
-                        c->stats.requests_done++;
-                    }
-                } else {
-                    keep.push_back(t);
-                }
-            }
-            c->order.swap(keep);
-        }
-        c->dcv.notify_all();
+        // Wait for the older pass in flight; the newer one keeps the device
+        // busy meanwhile.  A pass just enqueued alone is not waited for:
+        // the next round plans the pass behind it first.
+        Flight &f0 = c->flights[0], &f1 = c->flights[1];
+        Flight *older = nullptr;
+        if (f0.busy && f1.busy)
+            older = (f0.seq < f1.seq) ? &f0 : &f1;
+        else if (!enqueued)
+            older = f0.busy ? &f0 : (f1.busy ? &f1 : nullptr);
+        if (older) collect_flight(c, *older);
     }
 }
 
@@ -1455,12 +1690,34 @@ extern "C" int eis_submit(eis_ctx *c, uint64_t a, uint64_t b, uint64_t *ticket)
         std::lock_guard<std::mutex> lk(c->smu);
         if (c->stop) return EIS_EINVAL;
         if (c->order.size() >= c->cfg.serve_slots) return EIS_EBUSY;
-        if (!c->server.joinable()) c->server = std::thread(server_loop, c);
+    }
+    if (!c->flights_ready) {
+        std::lock_guard<std::mutex> g(c->gpu_mu);
+        if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
+        rc = ensure_flights(c);
+        if (rc != EIS_OK) return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        if (c->stop) return EIS_EINVAL;
+        if (c->order.size() >= c->cfg.serve_slots) return EIS_EBUSY;
         Request r;
-        r.ticket = c->next_ticket++;
         r.d0 = eis_first_candidate(a);
         r.ncand = eis_num_candidates(a, b);
-        if (r.ncand == 0) r.finished = true;
+        r.reserved = chunk_footprint(c, r.d0, std::min<u64>(r.ncand, kServeChunk));
+        if (r.reserved > c->serve_budget) return EIS_ENOMEM;
+        if (c->serve_reserved + r.reserved > c->serve_budget) return EIS_EBUSY;
+        if (!c->server.joinable()) c->server = std::thread(server_loop, c);
+        r.ticket = c->next_ticket++;
+        if (r.ncand == 0) {
+            r.finished = true;
+            r.reserved = 0;
+        }
+        c->serve_reserved += r.reserved;
+        {
+            std::lock_guard<std::mutex> sl(c->stats_mu);
+            c->stats.serve_bytes_reserved = c->serve_reserved;
+        }
         c->reqs[r.ticket] = r;
         if (!r.finished) c->order.push_back(r.ticket);
         *ticket = r.ticket;
@@ -1511,6 +1768,12 @@ extern "C" int eis_cancel(eis_ctx *c, uint64_t ticket)
             if (r.completed >= r.dispatched) {
                 // nothing of it is on the device: retire it now
                 r.finished = true;
+                c->serve_reserved -= r.reserved;
+                r.reserved = 0;
+                {
+                    std::lock_guard<std::mutex> sl(c->stats_mu);
+                    c->stats.serve_bytes_reserved = c->serve_reserved;
+                }
                 std::deque<u64> keep;
                 for (u64 t : c->order)
                     if (t != ticket) keep.push_back(t);

@@ -352,6 +352,7 @@ __global__ __launch_bounds__(256) void k_retry_window(InfraParams p) { walk_wind
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_window : k_walk_window, dim3(grid), dim3(256),
                        p.nseg * sizeof(SegLds), stream, p);
     return hipGetLastError();
@@ -541,6 +542,7 @@ hipError_t launch_build_tables(const InfraParams &p, u32 grid, bool retry, hipSt
 {
     if (p.batch == 0 || grid == 0) return hipSuccess;
     if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_tables : k_build_tables, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
@@ -720,6 +722,7 @@ hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t str
 {
     if (p.batch == 0) return hipSuccess;
     const u32 per_block = 256u * kSquarePerThread;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_square : k_giant_square, dim3((p.batch + per_block - 1) / per_block),
                        dim3(256), 0, stream, p);
     return hipGetLastError();
@@ -1115,6 +1118,7 @@ __global__ __launch_bounds__(256) void k_retry_giant(InfraParams p) { walk_giant
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_giant : k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }

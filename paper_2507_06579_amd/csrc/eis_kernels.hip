@@ -38,6 +38,7 @@ hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream)
     if (nwords == 0) return hipSuccess;
     u64 blocks = (nwords + 255) / 256;
     if (blocks > 4096) blocks = 4096;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_zero_u32, dim3((u32)blocks), dim3(256), 0, stream, p, nwords);
     return hipGetLastError();
 }
@@ -78,6 +79,7 @@ hipError_t launch_prime_offsets(const PrimeEntry *primes, const SegInfo *segs, u
                                 u32 np_max, u64 *roff, hipStream_t stream)
 {
     if (np_max == 0 || nseg == 0) return hipSuccess;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_prime_offsets, dim3((np_max + 255) / 256, nseg), dim3(256), 0, stream,
                        primes, segs, roff);
     return hipGetLastError();
@@ -229,6 +231,7 @@ hipError_t launch_sieve(const PrimeEntry *primes, const u64 *roff, const SegInfo
                         PassCounters *ctr_giant, hipStream_t stream)
 {
     if (nblocks == 0 || nseg == 0) return hipSuccess;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_sieve, dim3(nblocks), dim3(256), 0, stream, primes, roff, segs, nseg,
                        nblocks, nsmall, nsmall_p, sq_words, list_plain, ctr_plain, list_giant,
                        ctr_giant);
@@ -391,6 +394,7 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
 hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_walk_baby, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
 }
@@ -445,6 +449,7 @@ hipError_t launch_popcount_segs(const u32 *sq_words, const u32 *eis_words, const
     if (nseg == 0 || words_max == 0) return hipSuccess;
     u32 bx = (words_max + 255) / 256;
     if (bx > 256) bx = 256;
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_popcount_segs, dim3(bx, nseg), dim3(256), 0, stream, sq_words,
                        eis_words, segs, counts);
     return hipGetLastError();

@@ -60,6 +60,7 @@ __global__ void k_store_seg(SegInfo s, SegInfo *dst)
 
 hipError_t launch_store_seg(const SegInfo &s, SegInfo *dst, hipStream_t stream)
 {
+    (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(k_store_seg, dim3(1), dim3(64), 0, stream, s, dst);
     return hipGetLastError();
 }

@@ -148,3 +148,46 @@ def test_serving_concurrent_waiters():
         if rc == eis.Status.ETIMEDOUT:
             s, e = c.eis_wait(t, 30_000_000)
         assert (s, e) == c.eis_count(10**10, 10**10 + 10**6)
+
+
+def test_serving_admission_by_device_memory():
+    """A small memory budget: a request whose giant-step scratch cannot fit
+    even alone is refused with ENOMEM, requests that fit are admitted while
+    the reservations of the admitted ones leave room (EBUSY otherwise), the
+    plain walk's heights need no reservation, and every admitted result
+    equals the oracle's."""
+    budget = 200 * 2**20 + 300 * 2**20  # about the fixed buffers + 300 MiB
+    with eis.Context(mem_budget_bytes=budget, serve_slots=256) as c:
+        t_plain = c.eis_submit(10**6, 10**6 + 80000)  # plain walk: no reservation
+        st = c.eis_get_stats()
+        sb = st["serve_bytes_budget"]
+        _say(f"serving budget {sb} bytes")
+        assert 0 < sb < budget
+        # 2^20 candidates near 10^11 need about 2 GB of dictionaries
+        with pytest.raises(eis.EisError) as ei:
+            c.eis_submit(10**11 - 8 * 2**20, 10**11)
+        assert ei.value.status == eis.Status.ENOMEM
+        # 40,000 candidates near 10^11 need about 76 MB each: a few at a time
+        ranges = [(10**11 - 8 * 40000 * (k + 1), 10**11 - 8 * 40000 * k) for k in range(24)]
+        admitted, busy = [], 0
+        for a, b in ranges:
+            try:
+                admitted.append((c.eis_submit(a, b), a, b))
+            except eis.EisError as e:
+                assert e.status == eis.Status.EBUSY
+                busy += 1
+            assert c.eis_get_stats()["serve_bytes_reserved"] <= sb
+        _say(f"admitted {len(admitted)}, refused {busy} (memory)")
+        assert busy > 0 and len(admitted) >= 2
+        got = [(c.eis_wait(t, 60_000_000), a, b) for t, a, b in admitted]
+        assert c.eis_wait(t_plain, 60_000_000) == (
+            oracle.mobius_count(10**6, 10**6 + 80000),
+            oracle.classify_range(10**6, 10**6 + 80000, want_bits=False)["n_eis"])
+        assert c.eis_get_stats()["serve_bytes_reserved"] == 0
+        for (res, a, b) in got[:3]:
+            ref = oracle.classify_range(a, b, want_bits=False)
+            assert res == (ref["n_sqfree"], ref["n_eis"]), (a, b)
+        # memory freed: a refused range is admitted now
+        a, b = ranges[-1]
+        t = c.eis_submit(a, b)
+        assert c.eis_wait(t, 60_000_000) == c.eis_count(a, b)
