@@ -144,6 +144,36 @@ def cpu_baseline(a: int, b: int, target_s: float = 15.0):
                       f"one thread: {rate1:.1f} discriminants/s on {k1} of them"}
 
 
+def cpu_baseline_method(a: int, b: int, target_s: float = 8.0):
+    """The method itself on the CPU (ref/: Algorithm Infrastructure with
+    NUCOMP / NUDUPL, exact integers, all host threads) on a bounded random
+    sample of the members of D in [a, b): the second CPU baseline, beside the
+    oracle's plain definition."""
+    import numpy as np
+    import oracle
+    import ref
+    from paper_2507_06579_amd import workloads
+    bits, _ = oracle.sqfree_range(a, b)
+    n = oracle.num_candidates(a, b)
+    d0 = oracle.first_candidate(a)
+    idx = np.flatnonzero(np.unpackbits(bits, bitorder="little")[:n])
+    members = (d0 + 8 * idx[workloads.sample_indices(idx.size, idx.size, seed=9)]).astype(np.int64)
+    cores = os.cpu_count() or 1
+    k0 = min(64 * cores, members.size)
+    t = time.perf_counter()
+    ref.classify_list(members[:k0], nthreads=cores)
+    dt0 = max(time.perf_counter() - t, 1e-3)
+    k = int(min(members.size - k0, max(cores, k0 * target_s / dt0)))
+    sample = members[k0:k0 + k]
+    t = time.perf_counter()
+    flags, bad = ref.classify_list(sample, nthreads=cores)
+    dt = time.perf_counter() - t
+    return {"value": round(sample.size / dt, 2), "unit": "discriminants/s", "cores": cores,
+            "kind": "method (CPU, Algorithm Infrastructure with NUCOMP/NUDUPL, int64/int128)",
+            "sample": f"{sample.size} random members of D in [{a}, {b}) ({dt:.1f} s on {cores} "
+                      f"threads of {cpu_model()}; {bad} failed a check; {int(flags.sum())} in E)"}
+
+
 def cpu_model() -> str:
     """The host CPU's model name (from /proc/cpuinfo), or 'unknown CPU'."""
     try:
@@ -620,6 +650,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(a, b)
+        log("cpu baseline of the method (ref/ on a bounded sample)")
+        out["cpu_baseline_method"] = cpu_baseline_method(a, b)
     print(json.dumps(out), flush=True)
 
 
