@@ -85,6 +85,15 @@ typedef enum {
 #define EIS_FLAG_NO_GRAPHS 1u    /* run batched passes as plain launches, not hipGraph replays */
 #define EIS_FLAG_KERNEL_TIMES 2u /* time every kernel launch of plain (non-graph) passes with
                                     events on the launch stream; totals in eis_stats */
+/* Method variants of the giant-step method (Appendix A); every setting gives
+ * the same bits, only the work differs. */
+#define EIS_FLAG_NO_CONJUGATE_LOOKUPS 4u /* the paper's stride: giant step mu_1 with direct
+                                            lookups only (default: step mu_1^2, each giant
+                                            ideal looked up with its conjugate too, by the
+                                            symmetry of the cycle under conjugation) */
+#define EIS_FLAG_NO_SMALL_NORM_PRODUCT 8u /* NUCOMP/NUDUPL with partial reduction for every
+                                             norm (default: the plain ideal product when a
+                                             norm u <= 50, as NUCOMPchoose prescribes) */
 
 /* Kernels of a pass, for the per-kernel entries of eis_stats. */
 typedef enum {

@@ -9,6 +9,8 @@ from ._lib import (  # noqa: F401
     EIS_MAX_D,
     EIS_FLAG_NO_GRAPHS,
     EIS_FLAG_KERNEL_TIMES,
+    EIS_FLAG_NO_CONJUGATE_LOOKUPS,
+    EIS_FLAG_NO_SMALL_NORM_PRODUCT,
     EIS_SET_SQUAREFREE,
     EIS_SET_PRIME,
     KERNELS,

@@ -18,6 +18,8 @@ EIS_SET_SQUAREFREE = 0
 EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
 EIS_FLAG_KERNEL_TIMES = 2
+EIS_FLAG_NO_CONJUGATE_LOOKUPS = 4
+EIS_FLAG_NO_SMALL_NORM_PRODUCT = 8
 # eis_kernel: index of the per-kernel entries of the stats
 KERNELS = ["prime_offsets", "sieve", "walk_plain", "walk_window", "build_tables", "walk_giant",
            "walk_handoff", "popcount", "giant_square", "giant_retry"]

@@ -429,7 +429,9 @@ extern "C" int eis_create(const eis_config *cfg, eis_ctx **out)
     eis_config def;
     eis_config_default(&def);
     if (!cfg) cfg = &def;
-    if ((cfg->flags & ~(uint32_t)(EIS_FLAG_NO_GRAPHS | EIS_FLAG_KERNEL_TIMES)) != 0) return EIS_EINVAL;
+    if ((cfg->flags & ~(uint32_t)(EIS_FLAG_NO_GRAPHS | EIS_FLAG_KERNEL_TIMES |
+                                  EIS_FLAG_NO_CONJUGATE_LOOKUPS | EIS_FLAG_NO_SMALL_NORM_PRODUCT)) != 0)
+        return EIS_EINVAL;
     if (cfg->method < EIS_METHOD_BABY || cfg->method > EIS_METHOD_AUTO) return EIS_EINVAL;
     if (cfg->window_scale < 0) return EIS_EINVAL;
 
@@ -637,17 +639,28 @@ static u32 primes_needed(const eis_ctx *c, u64 dmax)
                  c->primes_host.begin());
 }
 
-// Dictionary geometry for heights up to dmax.
-static void infra_geometry(double scaled_root, u32 &emax, u32 &tsize)
+// Dictionary geometry for heights up to dmax: mu_1 is entry scaled_root/16
+// (at least the 16th), and the window runs a few entries past it, or (the
+// variant with the paper's stride) to 1.5 times its step count.
+static void infra_geometry(double scaled_root, u32 variant, u32 &emax, u32 &tsize)
 {
     double n = scaled_root / 16.0;
     u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
     emain = std::max<u32>(emain, 16);
-    emax = (emain + 16 + 7) / 8 * 8;  // whole 8-entry chunks (64-byte write-outs)
+    const u32 want = (variant & kVariantNoConjugate) ? emain + (3 * emain) / 4 + 16 : emain + 16;
+    emax = (want + 7) / 8 * 8;  // whole 8-entry chunks (64-byte write-outs)
     if (emax > 496) emax = 496;
-    // load factor at most 0.5 for the usual count (mu_1 plus a few)
+    // load factor at most 0.5 for the usual count
+    const u32 count = (variant & kVariantNoConjugate) ? emain + emain / 2 + 4 : emain + 4;
     tsize = 32;
-    while (tsize < 2 * (std::min(emain, emax - 8) + 4)) tsize <<= 1;
+    while (tsize < 2 * std::min(count, emax)) tsize <<= 1;
+}
+
+// the method variant bits of a context's flags
+static u32 variant_of(const eis_ctx *c)
+{
+    return ((c->cfg.flags & EIS_FLAG_NO_CONJUGATE_LOOKUPS) ? kVariantNoConjugate : 0u) |
+           ((c->cfg.flags & EIS_FLAG_NO_SMALL_NORM_PRODUCT) ? kVariantNoSmallNorm : 0u);
 }
 
 // lower end of tuner bin b: 10^(b/2), rounded up for odd b
@@ -737,7 +750,7 @@ static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u6
     pl.grid_plain = (u32)std::min<u64>((pl.plain_cand + 255) / 256, max_plain);
     pl.grid_fb = (u32)c->num_cu;
     if (pl.giant_cand) {
-        infra_geometry(nmax_giant, pl.emax, pl.tsize);
+        infra_geometry(nmax_giant, variant_of(c), pl.emax, pl.tsize);
         const u64 per_d = infra_bytes_per_d(pl.emax, pl.tsize);
         const u64 fit = std::max<u64>(infra_avail / per_d / batch_min * batch_min, batch_min);
         pl.batch = std::min<u64>(pl.giant_cand, fit);
@@ -854,6 +867,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, const PassBufs &B, 
         ip.max_steps = (u32)c->cfg.max_steps_per_d;
         ip.max_giants = 1u << 20;
         ip.emain_shift = 0;
+        ip.variant = variant_of(c);
         ip.eis_words = B.eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
@@ -1468,7 +1482,8 @@ static u64 chunk_footprint(const eis_ctx *c, u64 d0, u64 n)
     if (n == 0 || !method_for(c, d0)) return 0;
     const u64 dlast = d0 + 8 * (n - 1);
     u32 emax = 0, tsize = 0;
-    infra_geometry((double)(float)scale_for(c, d0) * std::pow((double)dlast, 0.25), emax, tsize);
+    infra_geometry((double)(float)scale_for(c, d0) * std::pow((double)dlast, 0.25), variant_of(c), emax,
+                   tsize);
     return n * infra_bytes_per_d(emax, tsize);
 }
 

@@ -402,7 +402,8 @@ __device__ __forceinline__ Form ideal_form(double u, double v, double d, Chk &ba
 // caller whose lanes mix squares and products may send both through NUCOMP
 // and keep every lane on one path.
 //
-// The small-norm case (a norm u_k <= 50) takes the plain ideal product,
+// The small-norm case (a norm u_k <= 50; unless small_norm_product is off,
+// a switchable variant) takes the plain ideal product,
 // I_1 I_2 = S [u/2, (v + sqrt d)/2] with gamma = S: that is NUCOMP / NUDUPL
 // with the partial reduction switched off (no partial Euclid step, so
 // x = 1, y = 0 and gamma = G, the gcd of the norms and s), here obtained by
@@ -412,18 +413,21 @@ __device__ __forceinline__ Form ideal_form(double u, double v, double d, Chk &ba
 constexpr double kSmallNorm = 50.0;
 
 __device__ __forceinline__ void square_ideal(double u, double v, double d, double L, Form &f3,
-                                             Gamma &g, Chk &bad, GiantWork &wk)
+                                             Gamma &g, Chk &bad, GiantWork &wk,
+                                             bool small_norm_product = true)
 {
-    const double Lk = (fabs(u) <= kSmallNorm) ? __builtin_inf() : L;
+    const double Lk = (small_norm_product && fabs(u) <= kSmallNorm) ? __builtin_inf() : L;
     nudupl(ideal_form(u, v, d, bad), Lk, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }
 
 __device__ __forceinline__ void compose_ideals(double u1, double v1, double u2, double v2,
                                                double d, double L, Form &f3, Gamma &g, Chk &bad,
-                                               GiantWork &wk)
+                                               GiantWork &wk, bool small_norm_product = true)
 {
-    const double Lk = (fabs(u1) <= kSmallNorm || fabs(u2) <= kSmallNorm) ? __builtin_inf() : L;
+    const double Lk = (small_norm_product && (fabs(u1) <= kSmallNorm || fabs(u2) <= kSmallNorm))
+                          ? __builtin_inf()
+                          : L;
     nucomp(ideal_form(u1, v1, d, bad), ideal_form(u2, v2, d, bad), Lk, f3, g, bad, wk);
     bad.fail |= (f3.u == 0.0);
 }

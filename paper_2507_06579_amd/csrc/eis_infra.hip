@@ -76,7 +76,6 @@ __device__ __forceinline__ bool is_dp(float Q4) { return __builtin_amdgcn_fractf
 
 constexpr u32 kTableMax = 1024;     // largest table (slots) per d
 constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
-constexpr u32 kWalkChunk = 32;      // of which one iteration of the giant walk takes at most this many
 constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
 constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
 
@@ -139,7 +138,8 @@ __device__ __forceinline__ bool window_hit(float Q, float hit)
 // entry ends the window (jc + kExtraSteps).
 __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned long long *lb,
                                               u32 *rb, float Q, float P, u32 S2k, float acc,
-                                              u32 jc, u32 emain, u32 &cnt, u32 &j1e, u32 &jlast)
+                                              u32 jc, u32 emain, bool long_ext, u32 &cnt, u32 &j1,
+                                              u32 &j1e, u32 &jlast)
 {
     const u32 slot = cnt % kRing;
     rg.key[slot][lane] = entry_of(Q, P);
@@ -147,7 +147,12 @@ __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned
     cnt++;
     if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
     jlast = jc;
-    j1e = (cnt == emain) ? jlast + kExtraSteps : j1e;
+    if (cnt == emain) {
+        // mu_1: the window runs kExtraSteps past it, or (the variant with
+        // the paper's stride) to half its step count past it
+        j1 = jc;
+        j1e = jc + (long_ext ? max(kExtraSteps, jc / 2) : kExtraSteps);
+    }
 }
 
 __device__ __forceinline__ void walk_window_body(InfraParams p)
@@ -176,6 +181,8 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
     u32 *rb = p.lres;
     float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f, hit = -1.f;
     u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
+    u32 j1 = 0;  // step count of mu_1
+    const bool long_ext = (p.variant & kVariantNoConjugate) != 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool live = false;
     u64 my_steps = 0, my_refills = 0, my_entries = 0;
@@ -229,7 +236,8 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
                     emain = min((u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8)) + p.emain_shift,
                                 p.emax - 8);
                     if (window_hit(Q, hit))
-                        window_append(rg, lane, lb, rb, Q, P, S2, 0.f, 1, emain, cnt, j1e, jlast);
+                        window_append(rg, lane, lb, rb, Q, P, S2, 0.f, 1, emain, long_ext, cnt, j1,
+                                      j1e, jlast);
                     live = true;
                 }
             }
@@ -263,10 +271,11 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
             const bool dA = window_hit(Q1, hit), dB = window_hit(Q2, hit);
             if (dA || dB)
                 window_append(rg, lane, lb, rb, dA ? Q1 : Q2, dA ? P1 : P2, S2 + 2 * it + (dA ? 1u : 2u),
-                              dA ? accA : acc, j + 2 * it + (dA ? 1u : 2u), emain, cnt, j1e, jlast);
-            if (dA && dB)
-                window_append(rg, lane, lb, rb, Q2, P2, S2 + 2 * it + 2, acc, j + 2 * it + 2, emain, cnt,
+                              dA ? accA : acc, j + 2 * it + (dA ? 1u : 2u), emain, long_ext, cnt, j1,
                               j1e, jlast);
+            if (dA && dB)
+                window_append(rg, lane, lb, rb, Q2, P2, S2 + 2 * it + 2, acc, j + 2 * it + 2, emain,
+                              long_ext, cnt, j1, j1e, jlast);
             const u64 ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) | __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
             const u64 ev = (mA | mB | ms) & lm;
             if (ev) {
@@ -287,10 +296,14 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
                         my_steps += j + kx - 1;
                     } else {
                         // end of the window; its extension past mu_1 must be
-                        // short next to mu_1's own distance (see above)
-                        const u32 j1 = j1e - kExtraSteps;
+                        // short next to mu_1's own distance (see above): at
+                        // most mu_1's step count, or three quarters of it with
+                        // the paper's stride (whose second giant ideal lies
+                        // only twice as far as mu_1)
                         const u32 S2e = S2 + 2 * it + 2 + (u32)acc;
-                        const bool ok = j1e != ~0u && jlast - j1 <= j1 && cnt < p.emax && S2e < (1u << 24);
+                        const u32 ext_max = long_ext ? (3 * j1) / 4 : j1;
+                        const bool ok = j1e != ~0u && jlast - j1 <= ext_max && cnt < p.emax &&
+                                        S2e < (1u << 24);
                         if (ok) {
                             if (cnt % kRing) ring_flush(rg, lane, lb, rb, cnt / kRing * kRing);
                             st.emain = emain;
@@ -685,14 +698,25 @@ __device__ __forceinline__ void giant_square_body(InfraParams p)
         Chk ck;
         GiantWork wk;
         // g = reduce(mu_1^2), then g2 = reduce(g^2): log g = 2 log mu_1 - log
-        // gamma + the residues of the reduction steps, and likewise for g2
+        // gamma + the residues of the reduction steps, and likewise for g2.
+        // With the paper's stride the step is mu_1 itself (its predecessor
+        // Q' = (d - P^2)/Q exact in fp64) and g2 = reduce(mu_1^2).
         double uQ = 4.0 * (double)__uint_as_float((u32)(m1 >> 32)), uP = 4.0 * (double)__uint_as_float((u32)m1);
         u32 uS = m1S;
+        const bool stride1 = (p.variant & kVariantNoConjugate) != 0;
+        const bool snp = (p.variant & kVariantNoSmallNorm) == 0;
+        if (stride1) {
+            const double Qp = ex_div(fma(-uP, uP, dd), uQ, ck);
+            out.g.Q4 = (float)uQ * 0.25f;
+            out.g.P4 = (float)uP * 0.25f;
+            out.g.Qp4 = (float)Qp * 0.25f;
+            out.g.S = uS;
+        }
 #pragma unroll 1
-        for (int k = 0; k < 2; k++) {
+        for (int k = stride1 ? 1 : 0; k < 2; k++) {
             Form f3;
             Gamma gm;
-            square_ideal(uQ, uP, dd, L, f3, gm, ck, wk);
+            square_ideal(uQ, uP, dd, L, f3, gm, ck, wk, snp);
             const u32 lg = gamma_log(gm, ck);
             double Qk, Pk, Qpk;
             const u32 Sr = reduce_form(f3, dd, s, Qk, Pk, Qpk, ck, wk);
@@ -981,7 +1005,8 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                 const double dd = (double)item_d(segs, item);
                 const float sq = pl.sq[s];
                 compose_ideals(4.0 * (double)pl.m1Q[s], 4.0 * (double)pl.m1P[s], 4.0 * (double)pl.cQ[s],
-                               4.0 * (double)pl.cP[s], dd, (double)pl.L[s], f3, gm, ck, wk);
+                               4.0 * (double)pl.cP[s], dd, (double)pl.L[s], f3, gm, ck, wk,
+                               (p.variant & kVariantNoSmallNorm) == 0);
                 const u32 lg = gamma_log(gm, ck);
                 double Qk, Pk, Qpk;
                 const u32 Sr = reduce_form(f3, dd, 4.0 * (double)sq, Qk, Pk, Qpk, ck, wk);
@@ -1005,7 +1030,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                     const u32 St = (lrs[ed] >> 1) % 3u;
                     flag = ((Sw + 3u - St) % 3u) == 0u;
                     done = true;
-                } else if (ec != kNoEntry) {
+                } else if (ec != kNoEntry && !(p.variant & kVariantNoConjugate)) {
                     const u32 St = (lrs[ec] >> 1) % 3u;
                     flag = ((Sw + St) % 3u) == 0u;
                     done = true;

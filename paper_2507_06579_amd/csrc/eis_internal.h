@@ -161,7 +161,17 @@ struct InfraParams {
     u32 max_giants;             // per-d budget of giant steps
     u32 emain_shift;            // mu_1 this many entries later (the retry round)
     u32 *eis_words;             // output bitmaps of the pass
+    u32 variant;                // kVariant* bits (0: the default method)
 };
+
+// Method variants (all give the same bits).  kVariantNoConjugate: the giant
+// step is mu_1 itself (the paper's stride) and only direct lookups are made;
+// the window then runs to 1.5 times mu_1's step count, so that a step cannot
+// jump over the stored stretch past a period.  kVariantNoSmallNorm: NUCOMP /
+// NUDUPL with their partial reduction for every norm, instead of the plain
+// ideal product when a norm u is <= 50.
+constexpr u32 kVariantNoConjugate = 1;
+constexpr u32 kVariantNoSmallNorm = 2;
 
 // Launchers (all enqueue on `stream`, never synchronise).
 hipError_t launch_zero_u32(u32 *p, u64 nwords, hipStream_t stream);

@@ -170,3 +170,37 @@ def test_serving_stream_equals_oracle():
     with eis.Context() as c:
         s, e = c.eis_count_batch(a, b)
         assert [(int(x), int(y)) for x, y in zip(s, e)] == want
+
+
+VARIANTS = [
+    ("no-conjugate", eis.EIS_FLAG_NO_CONJUGATE_LOOKUPS),
+    ("no-small-norm", eis.EIS_FLAG_NO_SMALL_NORM_PRODUCT),
+    ("both", eis.EIS_FLAG_NO_CONJUGATE_LOOKUPS | eis.EIS_FLAG_NO_SMALL_NORM_PRODUCT),
+]
+
+
+@pytest.mark.parametrize("label,flags", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_method_variants_give_the_same_bits(label, flags):
+    """The switchable variants of the giant-step method (the paper's stride
+    with direct lookups only; NUCOMP with partial reduction for small norms
+    too) against the oracle: the plain-walk slice [5, 10^6] bit for bit with
+    the live oracle, and the 10^9 and Table 1 windows against the goldens."""
+    a, b = workloads.SMALL
+    ref = oracle.classify_range(a, b)
+    with eis.Context(method=eis.Method.INFRA, flags=flags) as c:
+        sq, eb, ns, ne = c.eis_classify(a, b)
+        n = eis.eis_num_candidates(a, b)
+        nb = (n + 7) // 8
+        assert (ns, ne) == (ref["n_sqfree"], ref["n_eis"])
+        assert np.array_equal(eb[:nb], ref["eis_bits"][:nb])
+        for name in ("mid_1e9", "table1_1e11"):
+            if name not in G["windows"]:
+                continue
+            w = G["windows"][name]
+            s0 = c.eis_get_stats()
+            sq, eb, ns, ne = c.eis_classify(w["a"], w["b"])
+            s1 = c.eis_get_stats()
+            _say(f"{label} {name}: giant steps {s1['giant_steps'] - s0['giant_steps']}, "
+                 f"retried {s1['giant_retries'] - s0['giant_retries']}, "
+                 f"to the plain walk {s1['fallbacks'] - s0['fallbacks']}")
+            _check_window(name, sq, eb, ns, ne)
