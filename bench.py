@@ -494,7 +494,14 @@ def main():
         ctx.eis_tune()
         log(f"autotuner: {time.perf_counter() - t:.1f} s")
     chosen, wscale = ctx.eis_tuned_choice(a)
-    log(f"method at d={a}: {chosen.name}, window scale {wscale}")
+    wchunk, pass_cand = ctx.eis_tuned_shape(a)
+    log(f"method at d={a}: {chosen.name}, window scale {wscale}, walk chunk {wchunk}, "
+        f"pass {pass_cand} candidates")
+    if os.path.exists(tune_path):
+        with open(tune_path) as f:
+            tune_doc = json.load(f)
+        for bn in tune_doc["bins"]:
+            log(f"tuner bin {bn}")
 
     def step():
         ctx.eis_classify_async(a, b, sq.data_ptr(), eb.data_ptr(), counts.data_ptr(), 0)
@@ -628,7 +635,8 @@ def main():
         "config": {"workload": f"large height: all d = 5 mod 8 in [{a}, {b})",
                    "candidates": n, "members_of_D": n_sq, "pi_E": n_e,
                    "method": args.method, "chosen_method": chosen.name.lower(),
-                   "window_scale": wscale},
+                   "window_scale": wscale, "walk_chunk": wchunk,
+                   "pass_candidates": pass_cand},
         "baby_steps_per_s": round(baby / elapsed, 1),
         "fallbacks_per_step": (st["fallbacks"] - base["fallbacks"]) // args.steps,
         "giant_steps_per_s": round(giant / elapsed, 1),

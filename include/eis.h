@@ -298,22 +298,31 @@ int eis_cancel(eis_ctx *ctx, uint64_t ticket);
 
 /* ----- Autotuner ----------------------------------------------------- */
 
-/* Time the plain walk and the giant-step method (window scales 1 to 7) on
- * sample ranges of 2^23 candidates, one per half-decade height bin
- * 10^(b/2) <= d < 10^((b+1)/2) from 10^6 to 10^12, starting at the bin's
- * geometric middle, and keep per bin the faster method and its best window
- * scale (below 10^6: the plain walk).  The AUTO method then follows these
- * choices (an explicit method or window scale in the config still wins).
- * With cfg.tune_cache_path set at eis_create, the choices are loaded from
- * that file when it exists and holds every bin, and eis_tune writes them
- * there (EIS_EINVAL if the file cannot be written; the choices are in force
- * anyway).  Every choice gives the same bits; only the time differs.  Takes
- * a few seconds.  Thread-safe against the other calls. */
+/* Autotuner.  Per half-decade height bin 10^(b/2) <= d < 10^((b+1)/2) from
+ * 10^6 to 10^12, starting at the bin's geometric middle: time the plain walk
+ * and the giant-step method at window scales 1 to 5 on 2^23 candidates and
+ * keep the faster method and its best scale (below 10^6: the plain walk);
+ * for the giant-step method, time the giant walk's walk chunk (8, 16, 32
+ * reduction steps per phase) at that scale; then time a full pass's worth
+ * of candidates cut into passes of 2^22, 2^23 and 2^24 candidates.  The AUTO
+ * method then follows these choices (an explicit method or window scale in
+ * the config still wins).  With cfg.tune_cache_path set at eis_create, the
+ * choices are loaded from that file when it exists and holds every bin, and
+ * eis_tune writes them there with every timing (EIS_EINVAL if the file
+ * cannot be written; the choices are in force anyway).  Every choice gives
+ * the same bits; only the time differs.  Takes a few seconds.  Thread-safe
+ * against the other calls. */
 int eis_tune(eis_ctx *ctx);
 
 /* The choice in force for height d: *method (an eis_method, BABY or INFRA)
  * and *window_scale. */
 int eis_tuned_choice(eis_ctx *ctx, uint64_t d, int *method, double *window_scale);
+
+/* The tuned shape parameters in force for height d: *walk_chunk, the giant
+ * walk's reduction steps per walk phase (default 16), and *pass_candidates,
+ * the candidates per pass a range starting at d is cut into (default 2^24).
+ * Either pointer may be NULL. */
+int eis_tuned_shape(eis_ctx *ctx, uint64_t d, uint32_t *walk_chunk, uint64_t *pass_candidates);
 
 /* Counters since eis_create. */
 int eis_get_stats(eis_ctx *ctx, eis_stats *out);

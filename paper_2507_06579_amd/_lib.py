@@ -29,7 +29,7 @@ EXPORTED_SYMBOLS = [
     "eis_first_candidate", "eis_count", "eis_classify", "eis_classify_async",
     "eis_last_error", "eis_count_batch", "eis_submit", "eis_wait", "eis_cancel",
     "eis_get_stats", "eis_strerror", "eis_abi_version", "eis_tune", "eis_tuned_choice",
-    "eis_count_set", "eis_count_batch_set", "eis_classify_async_noalloc",
+    "eis_count_set", "eis_count_batch_set", "eis_classify_async_noalloc", "eis_tuned_shape",
 ]
 # eis_classify_async_noalloc's limit (EIS_NOALLOC_MAX_CANDIDATES)
 NOALLOC_MAX_CANDIDATES = 1 << 20
@@ -165,6 +165,8 @@ def lib():
     L.eis_count_batch_set.restype = c_int
     L.eis_tuned_choice.argtypes = [vp, u64, P(c_int), P(ctypes.c_double)]
     L.eis_tuned_choice.restype = c_int
+    L.eis_tuned_shape.argtypes = [vp, u64, P(ctypes.c_uint32), P(u64)]
+    L.eis_tuned_shape.restype = c_int
     if L.eis_abi_version() != ABI_VERSION:
         raise OSError(f"{_LIB_PATH} has ABI version {L.eis_abi_version()}, this binding "
                       f"expects {ABI_VERSION}: rebuild it")
@@ -330,6 +332,13 @@ class Context:
         _check(lib().eis_tuned_choice(self._h, d, ctypes.byref(m), ctypes.byref(w)),
                "eis_tuned_choice")
         return Method(m.value), float(w.value)
+
+    def eis_tuned_shape(self, d: int):
+        """(walk chunk, candidates per pass) in force for height d."""
+        ch, ps = ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check(lib().eis_tuned_shape(self._h, d, ctypes.byref(ch), ctypes.byref(ps)),
+               "eis_tuned_shape")
+        return int(ch.value), int(ps.value)
 
     def eis_get_stats(self):
         st = EisStats()

@@ -106,6 +106,7 @@ struct HostSeg {
     float wscale;  // giant steps: window scale of the segment
     u64 dst_bit;   // candidate offset of the segment in the caller's bitmap
     u32 set = kSetSquarefree;  // the candidate set counted and walked
+    u32 walk_chunk = kDefaultWalkChunk;  // giant walk: reduction steps per walk phase
 };
 
 struct Request {
@@ -186,6 +187,8 @@ struct eis_ctx {
     bool tuned = false;
     int tuned_method[kTuneBins] = {};
     double tuned_ws[kTuneBins] = {};
+    u32 tuned_chunk[kTuneBins] = {};     // giant walk: reduction steps per walk phase
+    u32 tuned_pass_log2[kTuneBins] = {}; // a range's pass size, log2 of candidates
     std::string tune_path;
 
     // prime table
@@ -309,8 +312,10 @@ extern "C" void eis_config_default(eis_config *cfg)
 }
 
 // Autotuner cache: a small JSON object written by eis_tune,
-//   {"arch": "gfx950", "bins": [{"b": 12, "method": 0, "window_scale": 2.0, ...}, ...]}
-// read back by scanning for the three keys of every bin.
+//   {"arch": "gfx950", "bins": [{"b": 12, "method": 0, "window_scale": 2.0,
+//     "walk_chunk": 16, "pass_log2": 24, ...}, ...]}
+// read back by scanning for the keys of every bin (the two shape keys are
+// optional: a bin without them keeps the defaults).
 static void load_tune_cache(eis_ctx *c)
 {
     FILE *f = std::fopen(c->tune_path.c_str(), "r");
@@ -323,6 +328,7 @@ static void load_tune_cache(eis_ctx *c)
     if (txt.find("\"gfx950\"") == std::string::npos) return;
     int method[kTuneBins];
     double ws[kTuneBins];
+    u32 chunk[kTuneBins], plog[kTuneBins];
     u32 seen = 0;
     size_t at = 0;
     while ((at = txt.find("\"b\":", at)) != std::string::npos) {
@@ -334,6 +340,16 @@ static void load_tune_cache(eis_ctx *c)
             method[b] = m;
             ws[b] = w;
             seen |= 1u << b;
+            // optional shape keys within this bin's object
+            const size_t end = txt.find('}', at);
+            const std::string obj = txt.substr(at, end == std::string::npos ? std::string::npos : end - at);
+            int ch = (int)kDefaultWalkChunk, pl2 = 24;
+            const size_t kc = obj.find("\"walk_chunk\":");
+            if (kc != std::string::npos) std::sscanf(obj.c_str() + kc, "\"walk_chunk\": %d", &ch);
+            const size_t kp = obj.find("\"pass_log2\":");
+            if (kp != std::string::npos) std::sscanf(obj.c_str() + kp, "\"pass_log2\": %d", &pl2);
+            chunk[b] = (u32)std::min(std::max(ch, 1), 64);
+            plog[b] = (u32)std::min(std::max(pl2, 22), 24);
         }
         at += 4;
     }
@@ -342,6 +358,8 @@ static void load_tune_cache(eis_ctx *c)
     for (int b = 0; b < kTuneBins; b++) {
         c->tuned_method[b] = method[b];
         c->tuned_ws[b] = ws[b];
+        c->tuned_chunk[b] = chunk[b];
+        c->tuned_pass_log2[b] = plog[b];
     }
     c->tuned = true;
 }
@@ -695,6 +713,19 @@ static double scale_for(const eis_ctx *c, u64 d0)
     return c->window_scale;
 }
 
+static u32 chunk_for(const eis_ctx *c, u64 d0)
+{
+    if (c->tuned) return c->tuned_chunk[bin_of(d0)];
+    return kDefaultWalkChunk;
+}
+
+// candidates per pass when a range starting at d0 is cut into passes
+static u64 pass_for(const eis_ctx *c, u64 d0)
+{
+    if (c->tuned) return u64(1) << c->tuned_pass_log2[bin_of(d0)];
+    return kPassCandidates;
+}
+
 // ---------------------------------------------------------------------------
 // one pass
 // ---------------------------------------------------------------------------
@@ -707,6 +738,7 @@ struct PassPlan {
     u32 nbatches = 0;
     u32 grid_plain = 0, grid_win = 0, grid_giant = 0, grid_fb = 0, grid_tables = 0;
     u64 roff_total = 0;
+    u32 walk_chunk = kDefaultWalkChunk;  // that of the highest giant-step segment
 };
 
 // Fill the pinned segment table and the plan of a pass.
@@ -718,6 +750,7 @@ static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u6
     u32 word = 0, block = 0;
     u64 roff = 0;
     double nmax_giant = 0.0;  // largest wscale * d^(1/4) of the giant-step segments
+    u64 dmax_giant = 0;       // start of the highest giant-step segment
     for (u32 s = 0; s < pl.nseg; s++) {
         const HostSeg &h = segs[s];
         SegInfo &g = hs[s];
@@ -737,6 +770,10 @@ static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u6
         roff += g.np;
         pl.np_max = std::max(pl.np_max, g.np);
         if (h.method) {
+            if (pl.giant_cand == 0 || h.d0 > dmax_giant) {
+                dmax_giant = h.d0;
+                pl.walk_chunk = h.walk_chunk;
+            }
             pl.giant_cand += h.n;
             nmax_giant = std::max(nmax_giant, (double)g.wscale * std::pow((double)dlast, 0.25));
         } else {
@@ -868,6 +905,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, const PassBufs &B, 
         ip.max_giants = 1u << 20;
         ip.emain_shift = 0;
         ip.variant = variant_of(c);
+        ip.walk_chunk = pl.walk_chunk;
         ip.eis_words = B.eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
@@ -926,7 +964,7 @@ static std::vector<u64> plan_key(const eis_ctx *c, const PassPlan &pl)
 {
     return {pl.nseg, pl.nblocks, pl.np_max, pl.words, pl.plain_cand ? 1ull : 0ull,
             pl.giant_cand ? 1ull : 0ull, pl.emax, pl.tsize, pl.batch, pl.nbatches, pl.grid_plain,
-            pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d};
+            pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d, pl.walk_chunk};
 }
 
 // Enqueue a planned pass on buffer set B, whose segment table is in place:
@@ -982,13 +1020,13 @@ static void mark_pending(eis_ctx *c, const PassPlan &pl, PassCounters *ctrs, hip
 // Run one pass of segments on the context's buffers (counts are accumulated
 // into c->pb.counts, which the caller zeroes).  Asynchronous: the counters
 // are read by collect_pass once the stream has finished.
-static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st, bool graph,
-                    PassPlan &pl)
+// Plan a pass on the context's buffers and allocate what it needs (done by
+// run_pass; the tuner calls it ahead, so that no allocation falls inside a
+// timed region).
+static int prepare_pass(eis_ctx *c, const std::vector<HostSeg> &segs, PassPlan &pl)
 {
-    (void)hipGetLastError();  // launch checks below must not see an older error
     int rc = settle_pending(c);
     if (rc != EIS_OK) return rc;
-    c->kev_used = 0;
     rc = ensure_pass_buffers(c);
     if (rc != EIS_OK) return rc;
     const u64 held = c->bytes_held - c->pb.infra_bytes;  // other buffers of the context
@@ -1000,6 +1038,16 @@ static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st
         rc = ensure_infra(c, pl.batch, pl.emax, pl.tsize);
         if (rc != EIS_OK) return rc;
     }
+    return EIS_OK;
+}
+
+static int run_pass(eis_ctx *c, const std::vector<HostSeg> &segs, hipStream_t st, bool graph,
+                    PassPlan &pl)
+{
+    (void)hipGetLastError();  // launch checks below must not see an older error
+    c->kev_used = 0;
+    int rc = prepare_pass(c, segs, pl);
+    if (rc != EIS_OK) return rc;
     HIP_TRY(hipMemcpyAsync(c->pb.segs, c->pb.h_segs, pl.nseg * sizeof(SegInfo), hipMemcpyHostToDevice, st));
     rc = launch_pass(c, pl, c->pb, st, graph, true);
     if (rc != EIS_OK) return rc;
@@ -1104,14 +1152,18 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
     HIP_TRY(launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4, st));
     HIP_TRY(hipEventRecord(c->ev_all0, st));
     int status = EIS_OK;
-    for (u64 off = 0; off < n; off += kPassCandidates) {
-        const u32 pn = (u32)std::min<u64>(kPassCandidates, n - off);
+    // passes of the tuned size for the range's height (a multiple of 2^22
+    // candidates, so that every pass starts on a bitmap byte)
+    const u64 ps = std::min<u64>(std::max<u64>(pass_for(c, d0), u64(1) << 22), kPassCandidates);
+    for (u64 off = 0; off < n; off += ps) {
+        const u32 pn = (u32)std::min<u64>(ps, n - off);
         std::vector<HostSeg> segs(1);
         segs[0].d0 = d0 + 8 * off;
         segs[0].n = pn;
         segs[0].slot = 0;
         segs[0].method = method_for(c, segs[0].d0);
         segs[0].wscale = (float)scale_for(c, segs[0].d0);
+        segs[0].walk_chunk = chunk_for(c, segs[0].d0);
         segs[0].dst_bit = off;
         segs[0].set = set;
         PassPlan pl;
@@ -1123,7 +1175,7 @@ static int run_range(eis_ctx *c, uint64_t a, uint64_t b, uint8_t *h_sq, uint8_t 
         if (h_eis) HIP_TRY(hipMemcpyAsync(h_eis + boff, c->pb.eis_words, bytes, hipMemcpyDeviceToHost, st));
         if (d_sq) HIP_TRY(hipMemcpyAsync(d_sq + boff, c->pb.sq_words, bytes, hipMemcpyDeviceToDevice, st));
         if (d_eis) HIP_TRY(hipMemcpyAsync(d_eis + boff, c->pb.eis_words, bytes, hipMemcpyDeviceToDevice, st));
-        if (sync || off + kPassCandidates < n) {
+        if (sync || off + ps < n) {
             // the pass buffers are reused: wait before the next pass
             HIP_TRY(hipStreamSynchronize(st));
             int prc = collect_pass(c);
@@ -1308,6 +1360,7 @@ extern "C" int eis_classify_async_noalloc(eis_ctx *c, uint64_t a, uint64_t b,
     h.slot = 0;
     h.method = method_for(c, h.d0);
     h.wscale = (float)scale_for(c, h.d0);
+    h.walk_chunk = chunk_for(c, h.d0);
     h.dst_bit = 0;
     SegInfo hs;
     PassPlan pl;
@@ -1371,6 +1424,7 @@ static void pack_passes(eis_ctx *c, const std::vector<std::tuple<u64, u64, u32>>
             h.slot = slot;
             h.method = method_for(c, h.d0);
             h.wscale = (float)scale_for(c, h.d0);
+            h.walk_chunk = chunk_for(c, h.d0);
             h.dst_bit = off;
             h.set = set;
             pieces.push_back(h);
@@ -1649,6 +1703,7 @@ static void server_loop(eis_ctx *c)
                 h.slot = (u32)segs.size();
                 h.method = method_for(c, h.d0);
                 h.wscale = (float)scale_for(c, h.d0);
+                h.walk_chunk = chunk_for(c, h.d0);
                 h.dst_bit = 0;
                 segs.push_back(h);
                 parts.emplace_back(t, take);
@@ -1805,82 +1860,144 @@ extern "C" int eis_cancel(eis_ctx *c, uint64_t ticket)
 // autotuner
 // ---------------------------------------------------------------------------
 
-// Device time of one pass over [d0, d0 + 8 n) with a given method and scale.
-static int time_pass(eis_ctx *c, u64 d0, u32 n, u32 method, double ws, float &ms)
+// Device time of the candidates [d0, d0 + 8 n) cut into passes of ps
+// candidates, with a given method, window scale and walk chunk.
+static int time_range(eis_ctx *c, u64 d0, u64 n, u64 ps, u32 method, double ws, u32 chunk,
+                      float &ms)
 {
-    std::vector<HostSeg> segs(1);
-    segs[0].d0 = d0;
-    segs[0].n = n;
-    segs[0].slot = 0;
-    segs[0].method = method;
-    segs[0].wscale = (float)ws;
-    segs[0].dst_bit = 0;
     hipStream_t st = c->stream;
     int rc = settle_pending(c);
     if (rc == EIS_OK) rc = ensure_counts(c, 1);
+    if (rc == EIS_OK && n) {
+        // allocate for the first (largest) pass before the timed region
+        std::vector<HostSeg> segs(1);
+        segs[0].d0 = d0;
+        segs[0].n = (u32)std::min<u64>(ps, n);
+        segs[0].slot = 0;
+        segs[0].method = method;
+        segs[0].wscale = (float)ws;
+        segs[0].walk_chunk = chunk;
+        segs[0].dst_bit = 0;
+        PassPlan pl;
+        rc = prepare_pass(c, segs, pl);
+    }
     if (rc == EIS_OK && launch_zero_u32(reinterpret_cast<u32 *>(c->pb.counts), 4, st) != hipSuccess)
         rc = EIS_EDEVICE;
-    PassPlan pl;
     if (rc == EIS_OK && hipEventRecord(c->ev_all0, st) != hipSuccess) rc = EIS_EDEVICE;
-    if (rc == EIS_OK) rc = run_pass(c, segs, st, false, pl);
+    for (u64 off = 0; rc == EIS_OK && off < n; off += ps) {
+        std::vector<HostSeg> segs(1);
+        segs[0].d0 = d0 + 8 * off;
+        segs[0].n = (u32)std::min<u64>(ps, n - off);
+        segs[0].slot = 0;
+        segs[0].method = method;
+        segs[0].wscale = (float)ws;
+        segs[0].walk_chunk = chunk;
+        segs[0].dst_bit = 0;
+        PassPlan pl;
+        rc = run_pass(c, segs, st, false, pl);
+        if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
+        if (rc == EIS_OK) rc = collect_pass(c);
+    }
     if (rc == EIS_OK && hipEventRecord(c->ev_all1, st) != hipSuccess) rc = EIS_EDEVICE;
     if (rc == EIS_OK && hipStreamSynchronize(st) != hipSuccess) rc = EIS_EDEVICE;
-    if (rc == EIS_OK) {
-        int prc = collect_pass(c);
-        if (prc != EIS_OK) rc = prc;
-    }
     if (rc == EIS_OK && hipEventElapsedTime(&ms, c->ev_all0, c->ev_all1) != hipSuccess) rc = EIS_EDEVICE;
     return rc;
 }
 
+// Autotuner.  Per half-decade bin from 10^6, at the bin's geometric middle:
+// the plain walk against the giant-step method at six window scales on half
+// a pass (2^23 candidates); then, for the giant-step method, the walk chunk
+// (8, 16, 32 reduction steps per walk phase) at the chosen scale; then the
+// pass size (2^24, 2^23, 2^22 candidates; a smaller pass must be 2 % faster
+// to be kept) on a full pass of candidates.  The cache records every timing
+// beside the choices.
 extern "C" int eis_tune(eis_ctx *c)
 {
     if (!c) return EIS_EINVAL;
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
     const double scales[] = {1.0, 1.5, 2.0, 2.5, 3.5, 5.0};
+    const u32 chunks[] = {8, 16, 32};
+    const u32 plogs[] = {24, 23, 22};  // the largest first: a smaller one must win by 2 %
     const u32 n = 1u << 23;  // candidates per sample: half a full pass
     int method[kTuneBins];
     double wsc[kTuneBins], plain_ms[kTuneBins], giant_ms[kTuneBins];
+    u32 chunk[kTuneBins], plog[kTuneBins];
+    double chunk_ms[kTuneBins][3], pass_ms[kTuneBins][3];
     for (int b = 0; b < kTuneBins; b++) {
         method[b] = 0;
         wsc[b] = kDefaultWindowScale;
         plain_ms[b] = giant_ms[b] = 0.0;
+        chunk[b] = kDefaultWalkChunk;
+        plog[b] = 24;
+        for (int k = 0; k < 3; k++) chunk_ms[b][k] = pass_ms[b][k] = 0.0;
     }
     float ms = 0.f;
     // one untimed pass of each method allocates every buffer
-    int rc = time_pass(c, 1000000005ull, n, 0, kDefaultWindowScale, ms);
-    if (rc == EIS_OK) rc = time_pass(c, 1000000005ull, n, 1, 5.0, ms);
+    int rc = time_range(c, 1000000005ull, n, n, 0, kDefaultWindowScale, kDefaultWalkChunk, ms);
+    if (rc == EIS_OK) rc = time_range(c, 1000000005ull, n, n, 1, 5.0, kDefaultWalkChunk, ms);
     if (rc != EIS_OK) return rc;
     // bins from 10^6 up, each sampled from its geometric middle: the last
     // sample, at 10^11.75, ends below 10^12
     for (int b = kTuneFirstBin; b < kTuneBins - 1; b++) {
         const u64 d0 = eis_first_candidate((u64)std::llround(std::pow(10.0, (b + 0.5) / 2.0)));
-        rc = time_pass(c, d0, n, 0, kDefaultWindowScale, ms);
+        rc = time_range(c, d0, n, n, 0, kDefaultWindowScale, kDefaultWalkChunk, ms);
         if (rc != EIS_OK) return rc;
         plain_ms[b] = ms;
         double best = 1e30, best_ws = kDefaultWindowScale;
         for (double ws : scales) {
-            rc = time_pass(c, d0, n, 1, ws, ms);
+            rc = time_range(c, d0, n, n, 1, ws, kDefaultWalkChunk, ms);
             if (rc != EIS_OK) return rc;
             if (ms < best) {
                 best = ms;
                 best_ws = ws;
             }
         }
-        giant_ms[b] = best;
         method[b] = best < plain_ms[b] ? 1 : 0;
         wsc[b] = best_ws;
+        if (method[b]) {
+            double cbest = 1e30;
+            for (int k = 0; k < 3; k++) {
+                if (chunks[k] == kDefaultWalkChunk) {
+                    ms = (float)best;
+                } else {
+                    rc = time_range(c, d0, n, n, 1, best_ws, chunks[k], ms);
+                    if (rc != EIS_OK) return rc;
+                }
+                chunk_ms[b][k] = ms;
+                if (ms < cbest) {
+                    cbest = ms;
+                    chunk[b] = chunks[k];
+                }
+            }
+            best = cbest;
+        }
+        giant_ms[b] = best;
+        double pbest = 1e30;
+        for (int k = 0; k < 3; k++) {
+            rc = time_range(c, d0, kPassCandidates, u64(1) << plogs[k], (u32)method[b], wsc[b],
+                            chunk[b], ms);
+            if (rc != EIS_OK) return rc;
+            pass_ms[b][k] = ms;
+            if (ms < pbest * (k ? 0.98 : 1.0)) {
+                pbest = ms;
+                plog[b] = plogs[k];
+            }
+        }
     }
     // below 10^6 the plain walk; the last bin holds d = 10^12 only
     for (int b = 0; b < kTuneFirstBin; b++) wsc[b] = wsc[kTuneFirstBin];
     method[kTuneBins - 1] = method[kTuneBins - 2];
     wsc[kTuneBins - 1] = wsc[kTuneBins - 2];
+    chunk[kTuneBins - 1] = chunk[kTuneBins - 2];
+    plog[kTuneBins - 1] = plog[kTuneBins - 2];
     {
         std::lock_guard<std::mutex> lk(c->smu);
         for (int b = 0; b < kTuneBins; b++) {
             c->tuned_method[b] = method[b];
             c->tuned_ws[b] = wsc[b];
+            c->tuned_chunk[b] = chunk[b];
+            c->tuned_pass_log2[b] = plog[b];
         }
         c->tuned = true;
     }
@@ -1890,13 +2007,26 @@ extern "C" int eis_tune(eis_ctx *c)
         std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"bins\": [\n", n);
         for (int b = 0; b < kTuneBins; b++)
             std::fprintf(f,
-                         "  {\"b\": %d, \"method\": %d, \"window_scale\": %.3f, \"from\": %llu, "
-                         "\"plain_ms\": %.3f, \"giant_ms\": %.3f}%s\n",
-                         b, method[b], wsc[b], (unsigned long long)bin_start(b), plain_ms[b],
-                         giant_ms[b], b < kTuneBins - 1 ? "," : "");
+                         "  {\"b\": %d, \"method\": %d, \"window_scale\": %.3f, \"walk_chunk\": %u, "
+                         "\"pass_log2\": %u, \"from\": %llu, \"plain_ms\": %.3f, \"giant_ms\": %.3f, "
+                         "\"chunk_ms_8_16_32\": [%.3f, %.3f, %.3f], \"pass_ms_24_23_22\": [%.3f, %.3f, %.3f]}%s\n",
+                         b, method[b], wsc[b], chunk[b], plog[b], (unsigned long long)bin_start(b),
+                         plain_ms[b], giant_ms[b], chunk_ms[b][0], chunk_ms[b][1], chunk_ms[b][2],
+                         pass_ms[b][0], pass_ms[b][1], pass_ms[b][2], b < kTuneBins - 1 ? "," : "");
         std::fprintf(f, "]}\n");
         if (std::fclose(f) != 0) return EIS_EINVAL;
     }
+    return EIS_OK;
+}
+
+extern "C" int eis_tuned_shape(eis_ctx *c, uint64_t d, uint32_t *walk_chunk,
+                               uint64_t *pass_candidates)
+{
+    if (!c) return EIS_EINVAL;
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (walk_chunk) *walk_chunk = chunk_for(c, d);
+    if (pass_candidates)
+        *pass_candidates = std::min<u64>(std::max<u64>(pass_for(c, d), u64(1) << 22), kPassCandidates);
     return EIS_OK;
 }
 

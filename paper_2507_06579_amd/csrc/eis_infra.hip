@@ -825,7 +825,7 @@ __device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long
 //                  conjugate), and on a miss composes the d's next giant
 //                  ideal c_{k+1} = reduce(g c_k) by NUCOMP (or, after the
 //                  first lookup, takes the precomputed second giant ideal);
-//   walk phase     up to 64 walking d's: each lane takes at most kPoolChunk
+//   walk phase     up to 64 walking d's: each lane takes at most walk_chunk
 //                  reduction steps towards the next distinguished ideal.
 // A phase runs once 64 d's are ready for it (else the fuller queue runs), so
 // that NUCOMP, the costliest part, runs with every lane busy, and a long
@@ -836,7 +836,6 @@ __device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long
 // estimated walks) first.
 constexpr u32 kPoolSlots = 128;  // d's per wave (a power of two)
 constexpr u32 kPoolMask = kPoolSlots - 1;
-constexpr u32 kPoolChunk = 16;   // reduction steps per walk phase
 
 // Structure of arrays, indexed by slot: a walk phase touches only the walk
 // fields.  pk packs the residues (bits 0-1 of g, 2-3 of c_k, 4-5 of the walk,
@@ -887,6 +886,8 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
     };
     GiantPool &pl = pools[threadIdx.x >> 6];
     const u32 lane = __lane_id();
+    // reduction steps per walk phase (a tuned shape parameter)
+    const u32 chunk = __builtin_amdgcn_readfirstlane(min(max(p.walk_chunk, 1u), 64u));
     const u32 mask = p.tsize - 1;
     // ring heads and tails (wave-uniform); every slot starts free
     u32 head[3] = {0u, 0u, 0u}, tail[3] = {kPoolSlots, 0u, 0u};
@@ -1088,7 +1089,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                 const u32 pk = pl.pk[s];
                 u32 u = 0;
                 float acc = 0.f;
-                for (; u < kPoolChunk && !is_dp(Qw); u++) {
+                for (; u < chunk && !is_dp(Qw); u++) {
                     float Pn, Qn;
                     rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc);
                     Qpw = Qw;

@@ -162,7 +162,11 @@ struct InfraParams {
     u32 emain_shift;            // mu_1 this many entries later (the retry round)
     u32 *eis_words;             // output bitmaps of the pass
     u32 variant;                // kVariant* bits (0: the default method)
+    u32 walk_chunk;             // giant walk: reduction steps per walk phase
 };
+
+// Default reduction steps per walk phase of the giant walk.
+constexpr u32 kDefaultWalkChunk = 16;
 
 // Method variants (all give the same bits).  kVariantNoConjugate: the giant
 // step is mu_1 itself (the paper's stride) and only direct lookups are made;

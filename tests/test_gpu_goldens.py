@@ -99,9 +99,16 @@ def test_async_device_pointers_on_table1_window():
                   int(cnt[0].item()), int(cnt[1].item()))
 
 
-def _tune_file(tmp_path, method_of_bin, ws_of_bin):
+def _tune_file(tmp_path, method_of_bin, ws_of_bin, chunk_of_bin=None, plog_of_bin=None):
+    def shape(b):
+        out = ""
+        if chunk_of_bin:
+            out += f', "walk_chunk": {chunk_of_bin(b)}'
+        if plog_of_bin:
+            out += f', "pass_log2": {plog_of_bin(b)}'
+        return out
     bins = ",\n".join(
-        f'  {{"b": {b}, "method": {method_of_bin(b)}, "window_scale": {ws_of_bin(b):.3f}}}'
+        f'  {{"b": {b}, "method": {method_of_bin(b)}, "window_scale": {ws_of_bin(b):.3f}{shape(b)}}}'
         for b in range(25))
     path = tmp_path / "tune.json"
     path.write_text('{"arch": "gfx950", "bins": [\n' + bins + "\n]}\n")
@@ -204,3 +211,27 @@ def test_method_variants_give_the_same_bits(label, flags):
                  f"retried {s1['giant_retries'] - s0['giant_retries']}, "
                  f"to the plain walk {s1['fallbacks'] - s0['fallbacks']}")
             _check_window(name, sq, eb, ns, ne)
+
+
+def test_tuned_shape_knobs_give_the_same_bits(tmp_path):
+    """Every tuned shape parameter -- the giant walk's walk chunk (8, 16, 32
+    reduction steps per phase) and the pass size a range is cut into (2^22,
+    2^23, 2^24 candidates) -- with the giant-step method at several scales:
+    the full windows and the 64-range batch equal the oracle's goldens."""
+    chunks, plogs, scales = [8, 16, 32], [22, 23, 24], [1.5, 2.0, 3.5]
+    path = _tune_file(tmp_path, lambda b: 1 if b >= 12 else 0, lambda b: scales[b % 3],
+                      lambda b: chunks[b % 3], lambda b: plogs[(b // 3) % 3])
+    with eis.Context(tune_cache_path=path) as c:
+        seen = {c.eis_tuned_shape(d) for d in (10**9, 4 * 10**9, 10**11 - 1, 10**12 - 1)}
+        assert all(ch in chunks and ps in (2**22, 2**23, 2**24) for ch, ps in seen)
+        assert len(seen) > 1
+        for name in ("mid_1e9", "table1_1e11", "top_1e12"):
+            if name not in G["windows"]:
+                continue
+            w = G["windows"][name]
+            _say(f"tuned shapes {c.eis_tuned_shape(w['a'])} on {name}")
+            sq, eb, ns, ne = c.eis_classify(w["a"], w["b"])
+            _check_window(name, sq, eb, ns, ne)
+        a, b, want = _batch("batch")
+        s, e = c.eis_count_batch(a, b)
+        assert [(int(x), int(y)) for x, y in zip(s, e)] == want

@@ -37,14 +37,26 @@ def test_tune_choices_cache_and_bits(tmp_path):
     with open(path) as f:
         doc = json.load(f)
     assert doc["arch"] == "gfx950" and len(doc["bins"]) == 25
+    for bn in doc["bins"]:
+        assert bn["walk_chunk"] in (8, 16, 32) and bn["pass_log2"] in (22, 23, 24)
+        if bn["b"] >= 12 and bn["b"] < 24:
+            # every timing behind the choice is recorded
+            assert min(bn["pass_ms_24_23_22"]) > 0
+            if bn["method"] == 1:
+                assert min(bn["chunk_ms_8_16_32"]) > 0
     with eis.Context(method=eis.Method.BABY) as c:
         plain = [c.eis_classify(a, b) for a, b in ranges]
     for (sq1, e1, n1, m1), (sq2, e2, n2, m2) in zip(tuned, plain):
         assert (n1, m1) == (n2, m2)
         assert bytes(sq1) == bytes(sq2) and bytes(e1) == bytes(e2)
-    # a new context loads the cache
+    # a new context loads the cache, shapes included
     with eis.Context(tune_cache_path=path) as c:
         assert [c.eis_tuned_choice(d) for d in heights] == choices
+        shapes = [c.eis_tuned_shape(d) for d in heights]
+    byb = {x["b"]: x for x in doc["bins"]}
+    for d, (ch, ps) in zip(heights, shapes):
+        b = max(k for k, x in byb.items() if x["from"] <= d)
+        assert (ch, ps) == (byb[b]["walk_chunk"], 2 ** byb[b]["pass_log2"]), d
     # an explicit method and scale win over the tuned choice
     with eis.Context(tune_cache_path=path, method=eis.Method.INFRA, window_scale=2.75) as c:
         assert c.eis_tuned_choice(10**11) == (eis.Method.INFRA, 2.75)
