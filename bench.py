@@ -48,15 +48,18 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma) and
 # two exit tests -> 11 + 2 (rcp) - 2 (floor, fract) = 11 slots.
 VALU_SLOTS_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0}
-# Window walk, per lane path like the giant walk's model: per rho step the
-# same step (11), the distinguished-ideal test (mul, fract, cmp: 2) and the
-# window-end tests (2 per pair: 1); per distinguished ideal
-# appended (counted by the kernel, eis_stats.window_entries) the append: the
-# selection of the pair's first distinguished ideal, LDS staging, count,
-# residue sum and mu_1 bookkeeping (18 VALU) and an eighth of a chunk
-# write-out (3 VALU).  The wave runs the append whenever any of its lanes
-# appends; the lanes that do not append are not counted.
-WINDOW_SLOTS = {"rho_steps": 14.0, "entries": 18.375}
+# Window walk, per lane path like the giant walk's model, counted in the
+# gfx950 code of the built kernel: per rho step the step with its two
+# half-period compares (12), the distinguished-ideal test (mul, fract, cmp: 3)
+# and half of the two per-pair window tests (mu_1 staged, window end: 1); per
+# distinguished ideal appended (counted by the kernel, eis_stats.window_entries)
+# the append: the selection of the pair's first distinguished ideal, its
+# residue sum and step, LDS staging and count (15 VALU) and an eighth of a
+# chunk write-out (3 VALU).  The wave runs the append whenever any of its lanes
+# appends; the lanes that do not append are not counted.  mu_1's bookkeeping
+# (once per window) and a window's end (written at the wave's next pause) are
+# not counted.
+WINDOW_SLOTS = {"rho_steps": 16.0, "entries": 15.375}
 # Giant-step walk: VALU issue slots per unit of its work, counted the same
 # way in the gfx950 code of the built kernel (per-lane path; a branch that a
 # lane does not take is not counted for it), the units being counted by the

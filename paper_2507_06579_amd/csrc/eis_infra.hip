@@ -131,29 +131,23 @@ __device__ __forceinline__ bool window_hit(float Q, float hit)
     return __builtin_amdgcn_fractf(Q * kDpScale) == hit;
 }
 
-// Window bookkeeping of a distinguished ideal (Q, P) (quarter units) reached
-// at step jc: stage it as entry cnt of the lane's list (its key and twice its
-// residue sum, S2k + acc), write out a full chunk, and note the step jc of
-// the last entry and, for mu_1 (the emain-th entry), the step from which an
-// entry ends the window (jc + kExtraSteps).
+// Stage a distinguished ideal (Q, P) (quarter units) with twice its residue
+// sum res2 as entry cnt of the lane's list, and write out a full chunk.
 __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned long long *lb,
-                                              u32 *rb, float Q, float P, u32 S2k, float acc,
-                                              u32 jc, u32 emain, bool long_ext, u32 &cnt, u32 &j1,
-                                              u32 &j1e, u32 &jlast)
+                                              u32 *rb, float Q, float P, u32 res2, u32 &cnt)
 {
     const u32 slot = cnt % kRing;
     rg.key[slot][lane] = entry_of(Q, P);
-    rg.res[slot][lane] = S2k + (u32)acc;
+    rg.res[slot][lane] = res2;
     cnt++;
     if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
-    jlast = jc;
-    if (cnt == emain) {
-        // mu_1: the window runs kExtraSteps past it, or (the variant with
-        // the paper's stride) to half its step count past it
-        j1 = jc;
-        j1e = jc + (long_ext ? max(kExtraSteps, jc / 2) : kExtraSteps);
-    }
 }
+
+// How a lane's window ended, kept until the wave's next pause (the lane
+// appends nothing meanwhile, so its list, count and steps stay as they were):
+// half period (the flag in bit 0), window end (residue sums within range or
+// not).
+constexpr u32 kFinNone = 0, kFinWindow = 1, kFinRange = 2, kFinHalf = 4;
 
 __device__ __forceinline__ void walk_window_body(InfraParams p)
 {
@@ -176,12 +170,15 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
     // lane state: the d at batch position pos, its list (entry e at lb[e],
     // rb[e]), the walk in quarter units (see rho_step_q), S2 = twice the
     // residue sum at the start of the current chunk of steps, and the window
-    // bookkeeping (an entry at step >= j1e ends the window)
+    // bookkeeping: jlast = the step of the last entry; e1 = emain until mu_1
+    // (entry emain - 1) is staged, then ~0; an entry at step >= j1e ends the
+    // window, which is kept if that entry's step is at most jok.
     unsigned long long *lb = p.lists;
     u32 *rb = p.lres;
     float sq = 0.f, sqc = 0.f, P = 0.25f, Q = 0.5f, Qp = 0.5f, hit = -1.f;
-    u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, j1e = ~0u, jlast = 0;
-    u32 j1 = 0;  // step count of mu_1
+    u32 S2 = 0, j = 0, idx = 0, pos = 0, item = 0, cnt = 0, emain = kMinMain, e1 = ~0u;
+    u32 j1e = ~0u, jok = 0, jlast = 0;
+    u32 fin = kFinNone, jend = 0;  // how and after how many steps the window ended
     const bool long_ext = (p.variant & kVariantNoConjugate) != 0;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the queue
     bool live = false;
@@ -230,14 +227,15 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
                     rg.key[0][lane] = entry_of(0.5f, P);
                     rg.res[0][lane] = 0u;
                     cnt = 1;
-                    j1e = ~0u;
                     jlast = 0;
                     const float n = segs[item >> kItemShift].wscale * sqrtf(sqrtf((float)d)) * (1.f / 16.f);
                     emain = min((u32)fminf(fmaxf(rintf(n), (float)kMinMain), (float)(p.emax - 8)) + p.emain_shift,
                                 p.emax - 8);
-                    if (window_hit(Q, hit))
-                        window_append(rg, lane, lb, rb, Q, P, S2, 0.f, 1, emain, long_ext, cnt, j1,
-                                      j1e, jlast);
+                    e1 = emain;
+                    if (window_hit(Q, hit)) {
+                        window_append(rg, lane, lb, rb, Q, P, S2, cnt);
+                        jlast = 1;
+                    }
                     live = true;
                 }
             }
@@ -247,11 +245,15 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
 
         // Two steps per iteration.  A lane that reaches the half period or
         // the end of its window is finished at once and idles (its steps go
-        // on, but it appends nothing); the loop is left for a refill when
-        // `batch` lanes idle (when all idle once the queue is drained).  The
-        // window ends once an entry at least kExtraSteps past mu_1 is staged,
-        // or when the list is full; the test runs after every pair, so no
-        // lane starts a pair with fewer than two free entries.
+        // on, but it appends nothing); its outcome is written at the next
+        // pause of the loop, which comes when `batch` lanes idle (when all
+        // idle once the queue is drained).  The window ends once an entry at
+        // least kExtraSteps past mu_1 is staged, or when the list is full;
+        // the test runs after every pair, so no lane starts a pair with fewer
+        // than two free entries.  With the short extension the list cannot
+        // fill: at most seven entries follow mu_1 (entries at the five steps
+        // after it, the one that ends the window and its pair's second), and
+        // mu_1 is at most entry emax - 9.
         const u32 keep = __any(npos != kNoItem) ? 64u - batch : 0u;
         const u32 iters = (K + 1) / 2;
         u32 it = 0;
@@ -269,20 +271,39 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
             // second for a lane whose two ideals are both distinguished (one
             // lane-pair in 256), instead of an append per step.
             const bool dA = window_hit(Q1, hit), dB = window_hit(Q2, hit);
-            if (dA || dB)
-                window_append(rg, lane, lb, rb, dA ? Q1 : Q2, dA ? P1 : P2, S2 + 2 * it + (dA ? 1u : 2u),
-                              dA ? accA : acc, j + 2 * it + (dA ? 1u : 2u), emain, long_ext, cnt, j1,
-                              j1e, jlast);
-            if (dA && dB)
-                window_append(rg, lane, lb, rb, Q2, P2, S2 + 2 * it + 2, acc, j + 2 * it + 2, emain,
-                              long_ext, cnt, j1, j1e, jlast);
-            const u64 ms = __builtin_amdgcn_ballot_w64(jlast >= j1e) | __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
+            if (dA || dB) {
+                const u32 k = 2 * it + (dA ? 1u : 2u);
+                window_append(rg, lane, lb, rb, dA ? Q1 : Q2, dA ? P1 : P2,
+                              S2 + k + (u32)(dA ? accA : acc), cnt);
+                jlast = j + k;
+            }
+            if (dA && dB) {
+                window_append(rg, lane, lb, rb, Q2, P2, S2 + 2 * it + 2 + (u32)acc, cnt);
+                jlast = j + 2 * it + 2;
+            }
+            // mu_1 staged (once per window): it is the last entry, or the
+            // pair's first when the pair staged two and went past it
+            if (__builtin_amdgcn_ballot_w64(cnt >= e1)) {
+                if (cnt >= e1) {
+                    const u32 j1 = (cnt == emain) ? jlast : jlast - 1;
+                    // the window runs kExtraSteps past mu_1, or (the variant
+                    // with the paper's stride) half mu_1's step count; its
+                    // extension must stay short next to mu_1's own distance:
+                    // at most mu_1's step count, or three quarters of it with
+                    // the paper's stride (whose second giant ideal lies only
+                    // twice as far as mu_1)
+                    j1e = j1 + (long_ext ? max(kExtraSteps, j1 / 2) : kExtraSteps);
+                    jok = j1 + (long_ext ? (3 * j1) / 4 : j1);
+                    e1 = ~0u;
+                }
+            }
+            u64 ms = __builtin_amdgcn_ballot_w64(jlast >= j1e);
+            if (long_ext) ms |= __builtin_amdgcn_ballot_w64(cnt >= cnt_end);
             const u64 ev = (mA | mB | ms) & lm;
             if (ev) {
                 if ((ev >> lane) & 1ull) {
                     const bool exA = (mA >> lane) & 1ull;
                     const bool exB = !exA && ((mB >> lane) & 1ull);
-                    WindowState st = {0u, 0u, item, 0u};
                     if (exA || exB) {
                         // half-period symmetry: the unit is found without giant steps
                         const u32 kx = 2 * it + (exA ? 1u : 2u);
@@ -292,33 +313,14 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
                         const u32 S = (S2 + kx + (u32)accx) >> 1;
                         const u32 rj = __builtin_amdgcn_fractf(Pj) > 0.5f ? 2u : 1u;
                         const u32 v = qrule ? (2u * S - rj) : (2u * (S - rj));
-                        emit_flag(p.eis_words, idx, v % 3u == 0u);
-                        my_steps += j + kx - 1;
+                        fin = kFinHalf | (v % 3u == 0u ? 1u : 0u);
+                        jend = j + kx - 1;
                     } else {
-                        // end of the window; its extension past mu_1 must be
-                        // short next to mu_1's own distance (see above): at
-                        // most mu_1's step count, or three quarters of it with
-                        // the paper's stride (whose second giant ideal lies
-                        // only twice as far as mu_1)
                         const u32 S2e = S2 + 2 * it + 2 + (u32)acc;
-                        const u32 ext_max = long_ext ? (3 * j1) / 4 : j1;
-                        const bool ok = j1e != ~0u && jlast - j1 <= ext_max && cnt < p.emax &&
-                                        S2e < (1u << 24);
-                        if (ok) {
-                            if (cnt % kRing) ring_flush(rg, lane, lb, rb, cnt / kRing * kRing);
-                            st.emain = emain;
-                            st.count = cnt;
-                        } else {
-                            const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
-                            p.fb_list[f] = item;
-                        }
-                        my_steps += j + 2 * it + 1;
+                        fin = S2e < (1u << 24) ? kFinWindow : kFinRange;
+                        jend = j + 2 * it + 1;
                     }
-                    p.state[pos] = st;
-                    my_entries += cnt - 1;  // appends after the entry of (1)
                     hit = -1.f;
-                    j1e = ~0u;
-                    cnt = 0;
                 }
                 lm &= ~ev;
                 stop = (u32)__builtin_popcountll(lm) <= keep;
@@ -327,6 +329,30 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
             Q = Q2;
             P = P2;
             if (++it >= iters || stop) break;
+        }
+        // ---- outcomes of the windows that ended -------------------------
+        if (fin != kFinNone) {
+            WindowState st = {0u, 0u, item, 0u};
+            if (fin & kFinHalf) {
+                emit_flag(p.eis_words, idx, (fin & 1u) != 0u);
+            } else {
+                const bool ok = fin == kFinWindow && e1 == ~0u && jlast <= jok && cnt < p.emax;
+                if (ok) {
+                    if (cnt % kRing) ring_flush(rg, lane, lb, rb, cnt / kRing * kRing);
+                    st.emain = emain;
+                    st.count = cnt;
+                } else {
+                    const u32 f = atomicAdd(&p.fb_ctr->list_len, 1u);
+                    p.fb_list[f] = item;
+                }
+            }
+            p.state[pos] = st;
+            my_steps += jend;
+            my_entries += cnt - 1;  // appends after the entry of (1)
+            j1e = ~0u;
+            e1 = ~0u;
+            cnt = 0;
+            fin = kFinNone;
         }
         live = (lm >> lane) & 1ull;
         if (live) {
@@ -342,6 +368,7 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
                 my_entries += cnt - 1;
                 hit = -1.f;
                 j1e = ~0u;
+                e1 = ~0u;
                 cnt = 0;
                 live = false;
             }
