@@ -412,12 +412,37 @@ int walk_window_blocks_per_cu()
 // same XCD and share its L2: hardware block b goes to XCD b % 8.
 //
 // A slot holds (fingerprint << 9) | (e + 1) for list entry e (emax <= 496,
-// so e + 1 < 2^9), the fingerprint being the top 7 bits of the key's hash;
-// 0 is empty.
+// so e + 1 < 2^9), the fingerprint being the top 7 bits of the key's hash
+// (1 in place of 0, so that no fingerprint matches an empty slot); 0 is
+// empty.  An entry goes to its key's home group (kGroup aligned slots, one
+// 16-byte load), or, when that group is full, to the first group after it
+// that is not, so that a lookup reads the home group whole: the key is in
+// it, or the group is full and the key may lie further on.
 // ---------------------------------------------------------------------------
 constexpr u32 kSlotIndexBits = 9;
 constexpr u32 kSlotIndexMask = (1u << kSlotIndexBits) - 1;
-__device__ __forceinline__ u32 slot_fp(u32 h) { return h >> (32 - (16 - kSlotIndexBits)); }
+constexpr u32 kGroup = 8;
+__device__ __forceinline__ u32 slot_fp(u32 h) { return max(h >> (32 - (16 - kSlotIndexBits)), 1u); }
+__device__ __forceinline__ u32 home_slot(u32 h, u32 mask) { return h & mask & ~(kGroup - 1); }
+
+// Insert val (hash h) into a wave's LDS table of mask + 1 slots: at the
+// next position of its home group, or, when that group is full, of the
+// first group after it that is not (so a key lies in its home group, or
+// that group is full and the key lies further on).  fill counts the
+// insertions per group; a group's entries fill its first slots.
+__device__ __forceinline__ void table_insert(u32 *tab, u32 *fill, u32 h, u32 mask, u32 val)
+{
+    const u32 gmask = mask / kGroup;
+    u32 g = (h & mask) / kGroup;
+    for (u32 probe = 0; probe <= gmask; probe++) {
+        const u32 k = atomicAdd(&fill[g], 1u);
+        if (k < kGroup) {
+            tab[g * kGroup + k] = val;
+            return;
+        }
+        g = (g + 1) & gmask;
+    }
+}
 
 // The lane's list entries (entry lane + 64 k, k < kLoads) of the d at batch
 // position pos, which has cnt of them.
@@ -454,7 +479,8 @@ __device__ __forceinline__ void wave_lds_sync()
 // alike, 7 slower).  A position takes giant steps iff its window left
 // entries (count > 0).
 template <u32 kLoads, u32 kAhead>
-__device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&tab)[4][kTableMax])
+__device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&tab)[4][kTableMax],
+                                                  u32 (&fill)[4][kTableMax / kGroup])
 {
     const u32 nblk = gridDim.x, b = blockIdx.x;
     const u32 xcd = b % 8, q = nblk / 8, r = nblk % 8;
@@ -476,6 +502,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
     for (u32 g = lb; 4 * g < n; g += nblk) {
         const u32 pos = 4 * g + wv;
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
+        for (u32 t = lane; t < p.tsize / kGroup; t += 64) fill[wv][t] = 0u;
         wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoads; k++) {
@@ -484,12 +511,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
                 const u32 qb = (u32)(ent[0][k] >> 32), pb = (u32)ent[0][k];
                 const u32 h = dict_hash(qb, pb);
                 const u32 val = (e + 1) | (slot_fp(h) << kSlotIndexBits);
-                u32 slot = h & mask;
-                for (u32 probe = 0; probe < p.tsize; probe++) {
-                    const u32 prev = atomicCAS(&tab[wv][slot], 0u, val);
-                    if (prev == 0u) break;
-                    slot = (slot + 1) & mask;
-                }
+                table_insert(tab[wv], fill[wv], h, mask, val);
             }
         }
         wave_lds_sync();
@@ -515,7 +537,8 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
 // Long lists (64 kLoadsLong >= emax): entries one group ahead, counts two.
 constexpr u32 kLoadsLong = 8;
 
-__device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&tab)[4][kTableMax])
+__device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&tab)[4][kTableMax],
+                                                  u32 (&fill)[4][kTableMax / kGroup])
 {
     const u32 nblk = gridDim.x, b = blockIdx.x;
     const u32 xcd = b % 8, q = nblk / 8, r = nblk % 8;
@@ -536,6 +559,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
         const u32 cnt2 = count_of(g + 2 * nblk);
         load_entries<kLoadsLong>(p, pos + 4 * nblk, cnt1, ent1);
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
+        for (u32 t = lane; t < p.tsize / kGroup; t += 64) fill[wv][t] = 0u;
         wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoadsLong; k++) {
@@ -544,12 +568,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
                 const u32 qb = (u32)(ent0[k] >> 32), pb = (u32)ent0[k];
                 const u32 h = dict_hash(qb, pb);
                 const u32 val = (e + 1) | (slot_fp(h) << kSlotIndexBits);
-                u32 slot = h & mask;
-                for (u32 probe = 0; probe < p.tsize; probe++) {
-                    const u32 prev = atomicCAS(&tab[wv][slot], 0u, val);
-                    if (prev == 0u) break;
-                    slot = (slot + 1) & mask;
-                }
+                table_insert(tab[wv], fill[wv], h, mask, val);
             }
         }
         wave_lds_sync();
@@ -569,10 +588,11 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
 __device__ __forceinline__ void build_tables_entry(InfraParams p)
 {
     __shared__ u32 tab[4][kTableMax];
+    __shared__ u32 fill[4][kTableMax / kGroup];
     if (p.emax <= 128)
-        build_tables_body<2, 3>(p, tab);
+        build_tables_body<2, 3>(p, tab, fill);
     else
-        build_tables_long(p, tab);
+        build_tables_long(p, tab, fill);
 }
 
 __global__ __launch_bounds__(256) void k_build_tables(InfraParams p) { build_tables_entry(p); }
@@ -581,7 +601,7 @@ __global__ __launch_bounds__(256) void k_retry_tables(InfraParams p) { build_tab
 hipError_t launch_build_tables(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (p.batch == 0 || grid == 0) return hipSuccess;
-    if (p.tsize > kTableMax || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
+    if (p.tsize > kTableMax || p.tsize < kGroup || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
     (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_tables : k_build_tables, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
@@ -785,16 +805,18 @@ hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t str
 constexpr u32 kNoEntry = ~0u;
 
 // Lookup of the window entries with keys (qb, pa) and (qb, pc) in a d's
-// table (open addressing, linear probing): their indices, or kNoEntry.  The
-// two probe chains advance together, so that their loads overlap; a slot's
-// fingerprint match is confirmed against the full key in the list.  Split in
-// two so that the first probe's loads can be issued well before their
-// values are needed (their latency then hides behind other work).
+// table: their indices and residue sums, or kNoEntry.  Split in two so that
+// the loads of the two home groups are issued well before their values are
+// needed (their latency then hides behind the composition).  A group's
+// first slot with the key's fingerprint is confirmed against the full key
+// in the list, whose residue sum is loaded with it; the rest (a false first
+// candidate with another after it, or a full group without the key, about
+// one chain in a thousand at the usual load) scans slot by slot.
 struct DictProbe {
     unsigned long long ka, kc;  // the two keys
-    u32 fa, fc;                 // their fingerprints
-    u32 sa, sc;                 // their first slots
-    u32 va, vc;                 // the first slots' contents (loads in flight)
+    u32 fa, fc;                 // their fingerprints, shifted to the slot's field
+    u32 ga, gc;                 // the first slots of their home groups
+    uint4 va, vc;               // the home groups (loads in flight)
 };
 
 __device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 mask, u32 qb, u32 pa, u32 pc)
@@ -803,43 +825,91 @@ __device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 mask, u32 q
     d.ka = ((unsigned long long)qb << 32) | pa;
     d.kc = ((unsigned long long)qb << 32) | pc;
     const u32 ha = dict_hash(qb, pa), hc = dict_hash(qb, pc);
-    d.fa = slot_fp(ha);
-    d.fc = slot_fp(hc);
-    d.sa = ha & mask;
-    d.sc = hc & mask;
-    d.va = tbl[d.sa];
-    d.vc = tbl[d.sc];
+    d.fa = slot_fp(ha) << kSlotIndexBits;
+    d.fc = slot_fp(hc) << kSlotIndexBits;
+    d.ga = home_slot(ha, mask);
+    d.gc = home_slot(hc, mask);
+    d.va = *reinterpret_cast<const uint4 *>(tbl + d.ga);
+    d.vc = *reinterpret_cast<const uint4 *>(tbl + d.gc);
     return d;
 }
 
-__device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long long *lst, u32 mask,
-                                             u32 tsize, DictProbe d, u32 &ea, u32 &ec)
+// In group g: the position of the first slot whose fingerprint field is f
+// (kGroup if none), whether another such slot follows, and whether the
+// group has an empty slot.
+__device__ __forceinline__ u32 group_match(uint4 g, u32 f, bool &more, bool &open)
 {
-    bool da = false, dc = false;
-    ea = ec = kNoEntry;
-    u32 va = d.va, vc = d.vc, sa = d.sa, sc = d.sc;
-    for (u32 probe = 0; probe < tsize && !(da && dc); probe++) {
-        if (probe > 0) {
-            va = da ? 0u : tbl[sa];
-            vc = dc ? 0u : tbl[sc];
+    const u32 pat = f | (f << 16);
+    const u32 w[4] = {g.x, g.y, g.z, g.w};
+    u32 mb = 0;
+    bool em = false;
+#pragma unroll
+    for (u32 k = 0; k < 4; k++) {
+        const u32 x = w[k] ^ pat;
+        mb |= ((x & 0xfe00u) == 0u ? 1u : 0u) << (2 * k);
+        mb |= (x < 0x02000000u ? 1u : 0u) << (2 * k + 1);
+        em = em || (w[k] & 0xffffu) == 0u || w[k] < 0x10000u;
+    }
+    more = (mb & (mb - 1u)) != 0u;
+    open = em;
+    return mb ? (u32)__builtin_ctz(mb) : kGroup;
+}
+
+// list entry of slot i (< kGroup) of group g
+__device__ __forceinline__ u32 group_entry(uint4 g, u32 i)
+{
+    const u32 lo = (i & 2u) ? g.y : g.x, hi = (i & 2u) ? g.w : g.z;
+    const u32 w = (i & 4u) ? hi : lo;
+    return ((w >> (16u * (i & 1u))) & kSlotIndexMask) - 1u;
+}
+
+// Slot-by-slot scan from slot s (a home group's first) to the first empty
+// slot: the entry with key k and fingerprint field f, or kNoEntry.
+__device__ __forceinline__ u32 dict_scan(const u16 *tbl, const unsigned long long *lst, u32 mask,
+                                         u32 tsize, u32 s, u32 f, unsigned long long k)
+{
+    for (u32 probe = 0; probe < tsize; probe++) {
+        const u32 v = tbl[s];
+        if (v == 0u) break;
+        if ((v & ~kSlotIndexMask) == f && lst[(v & kSlotIndexMask) - 1] == k)
+            return (v & kSlotIndexMask) - 1;
+        s = (s + 1) & mask;
+    }
+    return kNoEntry;
+}
+
+__device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long long *lst,
+                                             const u32 *lres, u32 mask, u32 tsize, const DictProbe &d,
+                                             u32 &ea, u32 &ec, u32 &ra, u32 &rc)
+{
+    bool morea, moreC, opena, openc;
+    const u32 ia = group_match(d.va, d.fa, morea, opena);
+    const u32 ic = group_match(d.vc, d.fc, moreC, openc);
+    // the first candidates, their list keys and residue sums loaded together
+    const u32 ca = ia < kGroup ? group_entry(d.va, ia) : 0u;
+    const u32 cc = ic < kGroup ? group_entry(d.vc, ic) : 0u;
+    unsigned long long la = 0, lc = 0;
+    ra = rc = 0u;
+    if (ia < kGroup) {
+        la = lst[ca];
+        ra = lres[ca];
+    }
+    if (ic < kGroup) {
+        lc = lst[cc];
+        rc = lres[cc];
+    }
+    ea = (ia < kGroup && la == d.ka) ? ca : kNoEntry;
+    ec = (ic < kGroup && lc == d.kc) ? cc : kNoEntry;
+    const bool slowa = ea == kNoEntry && ((ia < kGroup && morea) || !opena);
+    const bool slowc = ec == kNoEntry && ((ic < kGroup && moreC) || !openc);
+    if (__builtin_amdgcn_ballot_w64(slowa || slowc)) {
+        if (slowa) {
+            ea = dict_scan(tbl, lst, mask, tsize, d.ga, d.fa, d.ka);
+            if (ea != kNoEntry) ra = lres[ea];
         }
-        if (!da) {
-            if (va == 0u) {
-                da = true;
-            } else if ((va >> kSlotIndexBits) == d.fa && lst[(va & kSlotIndexMask) - 1] == d.ka) {
-                ea = (va & kSlotIndexMask) - 1;
-                da = true;
-            }
-            sa = (sa + 1) & mask;
-        }
-        if (!dc) {
-            if (vc == 0u) {
-                dc = true;
-            } else if ((vc >> kSlotIndexBits) == d.fc && lst[(vc & kSlotIndexMask) - 1] == d.kc) {
-                ec = (vc & kSlotIndexMask) - 1;
-                dc = true;
-            }
-            sc = (sc + 1) & mask;
+        if (slowc) {
+            ec = dict_scan(tbl, lst, mask, tsize, d.gc, d.fc, d.kc);
+            if (ec != kNoEntry) rc = lres[ec];
         }
     }
 }
@@ -1047,19 +1117,18 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
             }
             bool gone = false, next_walk = false;
             if (on) {
-                u32 ed, ec;
-                dict_finish2(p.tables + (u64)pos * p.tsize, p.lists + (u64)pos * p.emax, mask, p.tsize,
-                             dp, ed, ec);
+                u32 ed, ec, rd, rc;
+                dict_finish2(p.tables + (u64)pos * p.tsize, p.lists + (u64)pos * p.emax,
+                             p.lres + (u64)pos * p.emax, mask, p.tsize, dp, ed, ec, rd, rc);
                 my_looks++;
                 const u32 Sw = (pk >> 4) & 3u;
-                const u32 *lrs = p.lres + (u64)pos * p.emax;
                 bool done = false, flag = false;
                 if (ed != kNoEntry && ng > 1) {
-                    const u32 St = (lrs[ed] >> 1) % 3u;
+                    const u32 St = (rd >> 1) % 3u;
                     flag = ((Sw + 3u - St) % 3u) == 0u;
                     done = true;
                 } else if (ec != kNoEntry && !(p.variant & kVariantNoConjugate)) {
-                    const u32 St = (lrs[ec] >> 1) % 3u;
+                    const u32 St = (rc >> 1) % 3u;
                     flag = ((Sw + St) % 3u) == 0u;
                     done = true;
                 }
@@ -1171,6 +1240,9 @@ __global__ __launch_bounds__(256) void k_retry_giant(InfraParams p) { walk_giant
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
+    // lookups read whole 16-byte groups of the tables
+    if (p.tsize > kTableMax || p.tsize < kGroup || (p.tsize & (p.tsize - 1)) != 0)
+        return hipErrorInvalidValue;
     (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_giant : k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();

@@ -141,6 +141,23 @@ def test_serving_concurrent_waiters():
             a = 10**6 + 100 * k
             ref = oracle.classify_range(a, a + 5000, want_bits=False)
             assert results[t] == (ref["n_sqfree"], ref["n_eis"])
+        # two waiters on one ticket: one retires it with the result, the
+        # other returns EINVAL (unknown ticket) instead of waiting on
+        t = c.eis_submit(10**9, 10**9 + 10**6)
+        rcs = []
+
+        def waiter2():
+            rcs.append(c.eis_wait_status(t, 30_000_000))
+
+        ths = [threading.Thread(target=waiter2) for _ in range(2)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        codes = sorted(int(r[0]) for r in rcs)
+        assert codes == sorted([int(eis.Status.OK), int(eis.Status.EINVAL)]), rcs
+        ok = [r for r in rcs if r[0] == eis.Status.OK][0]
+        assert (ok[1], ok[2]) == c.eis_count(10**9, 10**9 + 10**6)
         # a timed-out wait leaves the ticket pending
         t = c.eis_submit(10**10, 10**10 + 10**6)
         rc, s, e = c.eis_wait_status(t, 0)
