@@ -72,23 +72,26 @@ __device__ __forceinline__ double ex_div(double a, double b, Chk &c)
     return q;
 }
 
-// q = floor(a / b) and r = a - q b for integer-valued fp32 0 <= a < 2^21,
+// -q and r = a - q b, for q = floor(a / b) and integer-valued fp32 0 <= a < 2^21,
 // 0 < b < 2^21.  The estimate floor(fl(a c) rcp(b)) with c = 1 + 2^-21 is
 // never below the true quotient k: the relative errors of the roundings
 // (the product a c, the reciprocal's 1 ulp, the final product) add up to
 // less than 2^-21.  It is at most k + 1: for b <= 2 the reciprocal and the
 // last product are exact and a 2^-21 < 1, and for b >= 3 the excess is
-// below (a / b) 1.5 2^-21 < 0.5.  So r < 0 detects the one possible
-// overshoot, undone without a branch.
+// below (a / b) 1.5 2^-21 < 0.5.  An overshoot needs (k + 1) b - a <= 1.5 a
+// 2^-21, i.e. r = b - 1 and a >= 2^21 / 1.5: it cannot happen below
+// 1.4 10^6 and is rare above; r < 0 detects it, and it is undone by
+// arithmetic (a wave-uniform branch around the correction measured slower).
 constexpr float kDivBias = 1.f + 0x1p-21f;
 
-__device__ __forceinline__ float fl_div32(float a, float b, float &r)
+// (-q, so that callers fold it into an fma without a negation)
+__device__ __forceinline__ float neg_fl_div32(float a, float b, float &r)
 {
-    const float q = floorf((a * kDivBias) * __builtin_amdgcn_rcpf(b));
-    const float r0 = fmaf(-q, b, a);
+    float nq = ceilf(-(a * kDivBias) * __builtin_amdgcn_rcpf(b));
+    const float r0 = fmaf(nq, b, a);
     const float over = r0 < 0.f ? 1.f : 0.f;
     r = fmaf(over, b, r0);
-    return q - over;
+    return nq + over;
 }
 
 // Work counts of one composition (for the instruction model of the giant
@@ -98,36 +101,38 @@ struct GiantWork {
     u32 euclid = 0, reduce = 0, gcd_branch = 0;
 };
 
-// Extended Euclid: x*a + y*b = g = gcd(a, b) >= 0, for integers
-// |a|, |b| < 2^21 (then |x|, |y| < 2^21 too): exact in fp32.  Invariants:
-// x0 A + y0 B = a and x1 A + y1 B = b for the inputs A = |a|, B = |b|; the
-// loop ends when one of a, b is 0, and the other is the gcd.  Two division
-// steps per iteration, the second with the roles of (a, x0, y0) and
-// (b, x1, y1) exchanged and applied only if the first left a != 0 (a
-// select, not a branch), so that no step moves registers around.
-__device__ __forceinline__ void xgcd(double ad, double bd, double &x, double &y, double &g,
-                                     GiantWork &wk)
+// Extended Euclid, the first cofactor only: g = gcd(a, b) >= 0 and x with
+// x a + y b = g for some integer y (so x a = g mod b), for integers |a|,
+// |b| < 2^21 (then |x| < 2^21 too): exact in fp32.  Invariants: x0 A = a and
+// x1 A = b modulo B, for the inputs A = |a|, B = |b|; the loop ends when one
+// of a, b is 0, and the other is the gcd.  A caller that needs y computes
+// (g - x a) / b, an exact division.  Two division steps per iteration, the
+// second with the roles of (a, x0) and (b, x1) exchanged and applied only if
+// the first left a != 0 (a select, not a branch), so that no step moves
+// registers around.
+__device__ __forceinline__ void xgcd1(double ad, double bd, double &x, double &g, GiantWork &wk)
 {
-    const float sa = ad < 0.0 ? -1.f : 1.f, sb = bd < 0.0 ? -1.f : 1.f;
+    const float sa = ad < 0.0 ? -1.f : 1.f;
     float a = (float)fabs(ad), b = (float)fabs(bd);
-    float x0 = 1.f, x1 = 0.f, y0 = 0.f, y1 = 1.f;
+    float x0 = 1.f, x1 = 0.f;
+    u32 iters = 0;
     while (a != 0.f && b != 0.f) {
         float r;
-        float q = fl_div32(a, b, r);
+        float nq = neg_fl_div32(a, b, r);
         a = r;
-        x0 = fmaf(-q, x1, x0);
-        y0 = fmaf(-q, y1, y0);
+        x0 = fmaf(nq, x1, x0);
         const bool go = a != 0.f;
-        q = fl_div32(b, go ? a : 1.f, r);
+        nq = neg_fl_div32(b, go ? a : 1.f, r);
         b = go ? r : b;
-        x1 = go ? fmaf(-q, x0, x1) : x1;
-        y1 = go ? fmaf(-q, y0, y1) : y1;
-        wk.euclid += go ? 2u : 1u;
+        x1 = go ? fmaf(nq, x0, x1) : x1;
+        iters++;
     }
     const bool az = a == 0.f;
+    // every iteration takes two steps but the last, whose second step is
+    // skipped when it leaves a = 0
+    wk.euclid += iters ? 2u * iters - (az ? 1u : 0u) : 0u;
     g = (double)(az ? b : a);
     x = (double)((az ? x1 : x0) * sa);
-    y = (double)((az ? y1 : y0) * sb);
 }
 
 struct Form {
@@ -152,23 +157,24 @@ __device__ __forceinline__ void partial_euclid(double &bxd, double &byd, double 
 {
     float u = (float)bxd, v = (float)byd, X = 1.f, Y = 0.f;  // (b_x, b_y, x, y)
     const float Lf = (float)L;
-    bool odd = false;  // after an odd step count the roles stay exchanged
-    int n = 0;
+    bool odd = false;  // the last iteration took one step: the roles stay exchanged
+    int iters = 0;
     bool run = v > Lf && u != 0.f;
     while (run) {
         float r;
-        float q = fl_div32(v, u, r);
+        float nq = neg_fl_div32(v, u, r);
         v = r;
-        Y = fmaf(-q, X, Y);
+        Y = fmaf(nq, X, Y);
         // now (b_x, b_y, x, y) = (v, u, Y, X)
         const bool go = u > Lf && v != 0.f;
-        q = fl_div32(u, go ? v : 1.f, r);
+        nq = neg_fl_div32(u, go ? v : 1.f, r);
         u = go ? r : u;
-        X = go ? fmaf(-q, Y, X) : X;
-        n += go ? 2 : 1;
+        X = go ? fmaf(nq, Y, X) : X;
+        iters++;
         odd = !go;
         run = go && v > Lf && u != 0.f;
     }
+    const int n = 2 * iters - (odd ? 1 : 0);
     z = n;
     float bx = odd ? v : u, by = odd ? u : v, xf = odd ? Y : X, yf = odd ? X : Y;
     if (n & 1) {
@@ -192,8 +198,8 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
     }
     const double s = ex_div(f1.v + f2.v, 2.0, bad);
     const double m = f2.v - s;
-    double b, c, F;
-    xgcd(f2.u, f1.u, b, c, F, wk);  // b u2 + c u1 = F
+    double b, F;
+    xgcd1(f2.u, f1.u, b, F, wk);  // b u2 = F (mod u1)
     double G, Bx, By, Cy, Dy;
     if (nn_mod(s, F) == 0.0) {
         G = F;
@@ -203,9 +209,12 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
         Cy = ex_div(f2.u, G, bad);
         Dy = ex_div(s, G, bad);
     } else {
-        double x2, y2;
+        double y2;
         wk.gcd_branch = 1;
-        xgcd(F, s, x2, y2, G, wk);  // x2 F + y2 s = G
+        // c with b u2 + c u1 = F (an exact division)
+        chk(b * f2.u, bad);
+        const double c = ex_div(fma(-b, f2.u, F), f1.u, bad);
+        xgcd1(s, F, y2, G, wk);  // y2 s = G (mod F); only y2 mod F/G matters
         const double H = ex_div(F, G, bad);
         By = ex_div(f1.u, G, bad);
         Cy = ex_div(f2.u, G, bad);
@@ -290,8 +299,8 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
 __device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk &bad,
                                        GiantWork &wk)
 {
-    double x0, y0, G;
-    xgcd(f.u, f.v, x0, y0, G, wk);  // x0 u + y0 v = G
+    double y0, G;
+    xgcd1(f.v, f.u, y0, G, wk);  // y0 v = G (mod u); only y0 mod u/G matters
     const double By = ex_div(f.u, G, bad);
     const double Dy = ex_div(f.v, G, bad);
     // B_x = y0 w mod B_y, reduced factor by factor

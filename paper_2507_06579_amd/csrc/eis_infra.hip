@@ -983,8 +983,8 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
     };
     GiantPool &pl = pools[threadIdx.x >> 6];
     const u32 lane = __lane_id();
-    // reduction steps per walk phase (a tuned shape parameter)
-    const u32 chunk = __builtin_amdgcn_readfirstlane(min(max(p.walk_chunk, 1u), 64u));
+    // reduction steps per walk phase (a tuned shape parameter), even
+    const u32 chunk = __builtin_amdgcn_readfirstlane((min(max(p.walk_chunk, 2u), 64u) + 1u) & ~1u);
     const u32 mask = p.tsize - 1;
     // ring heads and tails (wave-uniform); every slot starts free
     u32 head[3] = {0u, 0u, 0u}, tail[3] = {kPoolSlots, 0u, 0u};
@@ -1181,21 +1181,35 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
             bool at_dp = false, gone = false, more = false;
             if (on) {
                 const float sq = pl.sq[s], sqc = sq * kQuotBias;
-                float Qw = pl.Qw[s], Pw = pl.Pw[s], Qpw = pl.Qpw[s];
+                // Two steps per iteration on fixed registers: the next Q
+                // overwrites the previous one (Q_{j+1} = Q_{j-1} + q (P_j -
+                // P_{j+1})), so Qa and Qb swap roles every step, and so do Pa
+                // and Pb; nothing is copied.  After an odd number of steps the
+                // current ideal is (Pb, Qb).
+                float Pa = pl.Pw[s], Pb = 0.f, Qa = pl.Qw[s], Qb = pl.Qpw[s];
                 const u32 pk = pl.pk[s];
                 u32 u = 0;
                 float acc = 0.f;
-                for (; u < chunk && !is_dp(Qw); u++) {
-                    float Pn, Qn;
-                    rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc);
-                    Qpw = Qw;
-                    Qw = Qn;
-                    Pw = Pn;
+                bool run = !is_dp(Qa);
+                for (u32 k = 0; k < chunk; k += 2) {
+                    if (run) {
+                        rho_step_q(sq, sqc, Pa, Qa, Qb, Pb, Qb, acc);
+                        u++;
+                        run = !is_dp(Qb);
+                    }
+                    if (run) {
+                        rho_step_q(sq, sqc, Pb, Qb, Qa, Pa, Qa, acc);
+                        u++;
+                        run = !is_dp(Qa);
+                    }
+                    if (!__any(run)) break;
                 }
+                const bool odd = (u & 1u) != 0u;
+                const float Qw = odd ? Qb : Qa, Qpw = odd ? Qa : Qb, Pw = odd ? Pb : Pa;
                 const u32 Sw = (((pk >> 4) & 3u) + ((u + (u32)acc) >> 1)) % 3u;
                 const u32 w = (pk >> 8) + u;
                 my_steps += u;
-                at_dp = is_dp(Qw);
+                at_dp = !run;
                 if (!at_dp && w >= kWalkLimit) {
                     handoff(pl.item[s]);
                     my_giants += pl.ng[s];
