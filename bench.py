@@ -49,17 +49,17 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # two exit tests -> 11 + 2 (rcp) - 2 (floor, fract) = 11 slots.
 VALU_SLOTS_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0}
 # Window walk, per lane path like the giant walk's model, counted in the
-# gfx950 code of the built kernel: per rho step the step with its two
-# half-period compares (12), the distinguished-ideal test (mul, fract, cmp: 3)
-# and half of the two per-pair window tests (mu_1 staged, window end: 1); per
-# distinguished ideal appended (counted by the kernel, eis_stats.window_entries)
-# the append: the selection of the pair's first distinguished ideal, its
-# residue sum and step, LDS staging and count (15 VALU) and an eighth of a
-# chunk write-out (3 VALU).  The wave runs the append whenever any of its lanes
-# appends; the lanes that do not append are not counted.  mu_1's bookkeeping
-# (once per window) and a window's end (written at the wave's next pause) are
-# not counted.
-WINDOW_SLOTS = {"rho_steps": 16.0, "entries": 15.375}
+# gfx950 code of the built kernel with the same issue rules: per rho step the
+# step with its two half-period compares (11), the distinguished-ideal test
+# (mul, fract, cmp: 2) and half of the two per-pair window tests (mu_1
+# staged, window end: 1); per distinguished ideal appended (counted by the
+# kernel, eis_stats.window_entries) the append: the selection of the pair's
+# first distinguished ideal, its residue sum and step, LDS staging and count
+# (15) and an eighth of a chunk write-out (3).  The wave runs the append
+# whenever any of its lanes appends; the lanes that do not append are not
+# counted.  mu_1's bookkeeping (once per window) and a window's end (written
+# at the wave's next pause) are not counted.
+WINDOW_SLOTS = {"rho_steps": 14.0, "entries": 15.375}
 # Giant-step walk: VALU issue slots per unit of its work, counted the same
 # way in the gfx950 code of the built kernel (per-lane path; a branch that a
 # lane does not take is not counted for it), the units being counted by the
@@ -67,14 +67,18 @@ WINDOW_SLOTS = {"rho_steps": 16.0, "entries": 15.375}
 #   composition, fixed part: the two ideal forms, NUCOMP on its common path
 #     (gcd dividing s, partial Euclid with z != 0), the residue of gamma, the
 #     set-up and final checks of the reduction, the kernel's bookkeeping: 330;
-#   NUCOMP's gcd branch, when taken (H, l and their reductions mod H): 126;
-#   Euclid step (extended or partial Euclid, two per loop iteration): 15;
+#   NUCOMP's gcd branch, when taken (the second Bezout cofactor, H, l and
+#     their reductions mod H): 136;
+#   Euclid step (extended or partial Euclid, two per loop iteration of 27):
+#     13.5;
 #   reduction step after a composition (fp64, with its checks): 47;
 #   walk step towards the next distinguished ideal (the step, the test): 11;
-#   lookup of a distinguished ideal and its conjugate (hashes, first probe,
-#     the extra step for the conjugate's key): 67.
-GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 126.0, "euclid_steps": 15.0,
-               "reduce_steps": 47.0, "walk_steps": 11.0, "lookups": 67.0}
+#   lookup of a distinguished ideal and its conjugate (two hashes, the scan
+#     of two 8-slot groups for fingerprints and empty slots, the tests on a
+#     lane's path when no slot matches, the extra step for the conjugate's
+#     key): 140.
+GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "euclid_steps": 13.5,
+               "reduce_steps": 47.0, "walk_steps": 11.0, "lookups": 140.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the
@@ -106,6 +110,66 @@ def measured_traffic(kernel: str, workload: str):
     if not ent or ent.get("device_sources_sha256") != device_sources_sha256():
         return None
     return int(ent["hbm_bytes_per_launch"])
+
+
+TRAFFIC_KERNELS = ["k_walk_giant", "k_walk_window", "k_build_tables", "k_giant_square"]
+
+
+def record_traffic(fetch_dir: str, write_dir: str, probe_mib: int, commands):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of this bench
+    (one step, --copy-probe-mib probe_mib): FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) of each kernel's last dispatch, each scaled by what the same
+    counter reads for the copy probe (probe_mib MiB read and written).  Runs
+    on the host from the counter files alone."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        per = {}
+        for fn in files:
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+                    per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        return per
+
+    def last_of(per, name):
+        hits = [(did, v) for (k, did), v in per.items() if name in k]
+        return max(hits)[1] if hits else None
+
+    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    probe_kib = probe_mib * 1024.0
+    # the copy probe: the elementwise kernel that moved the most bytes
+    fcopy = max(v for (k, _), v in fetch.items() if "elementwise" in k)
+    wcopy = max(v for (k, _), v in write.items() if "elementwise" in k)
+    fs, ws = probe_kib / fcopy, probe_kib / wcopy
+    doc = {"_note": "HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs "
+                    "(KiB per dispatch, the last dispatch of each kernel), each scaled by the "
+                    "reading of the same counter for an elementwise copy of "
+                    f"{probe_mib} MiB read + {probe_mib} MiB written in the same run "
+                    "(bench.py --copy-probe-mib); valid while the device sources hash to "
+                    "device_sources_sha256",
+           "copy_probe": {"mib": probe_mib, "fetch_kib": fcopy, "write_kib": wcopy,
+                          "fetch_scale": fs, "write_scale": ws}}
+    sha = device_sources_sha256()
+    for k in TRAFFIC_KERNELS:
+        fk, wk = last_of(fetch, k), last_of(write, k)
+        if fk is None or wk is None:
+            continue
+        doc[k] = {"large:infra": {"device_sources_sha256": sha, "fetch_kib": fk, "write_kib": wk,
+                                  "fetch_scale": fs, "write_scale": ws,
+                                  "hbm_bytes_per_launch": int(round((fk * fs + wk * ws) * 1024)),
+                                  "commands": list(commands)}}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    return doc
 
 
 def log(msg):
@@ -467,7 +531,20 @@ def main():
                     help="skip the serving sweep (config d5)")
     ap.add_argument("--no-configs", action="store_true",
                     help="measure the headline workload only (no d1-d3, d5)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from the output folders of two "
+                         "rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this bench with "
+                         "--copy-probe-mib (given here too), then exit; no GPU is used")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="with --record-traffic: a command line to record beside the counts")
     args = ap.parse_args()
+    if args.record_traffic:
+        doc = record_traffic(args.record_traffic[0], args.record_traffic[1],
+                             args.copy_probe_mib or 1024, args.traffic_command)
+        for k in TRAFFIC_KERNELS:
+            if k in doc:
+                print(f"{k}: {doc[k]['large:infra']['hbm_bytes_per_launch'] / 1e9:.3f} GB per launch")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the per-d walks "
                                    "are independent, so a range would shard into blocks of "

@@ -319,7 +319,7 @@ int eis_tune(eis_ctx *ctx);
 int eis_tuned_choice(eis_ctx *ctx, uint64_t d, int *method, double *window_scale);
 
 /* The tuned shape parameters in force for height d: *walk_chunk, the giant
- * walk's reduction steps per walk phase (default 16), and *pass_candidates,
+ * walk's reduction steps per walk phase (default 8), and *pass_candidates,
  * the candidates per pass a range starting at d is cut into (default 2^24).
  * Either pointer may be NULL. */
 int eis_tuned_shape(eis_ctx *ctx, uint64_t d, uint32_t *walk_chunk, uint64_t *pass_candidates);

@@ -165,8 +165,9 @@ struct InfraParams {
     u32 walk_chunk;             // giant walk: reduction steps per walk phase
 };
 
-// Default reduction steps per walk phase of the giant walk.
-constexpr u32 kDefaultWalkChunk = 16;
+// Default reduction steps per walk phase of the giant walk (the tuner's
+// usual choice above 10^10).
+constexpr u32 kDefaultWalkChunk = 8;
 
 // Method variants (all give the same bits).  kVariantNoConjugate: the giant
 // step is mu_1 itself (the paper's stride) and only direct lookups are made;
