@@ -299,12 +299,14 @@ int eis_cancel(eis_ctx *ctx, uint64_t ticket);
 /* ----- Autotuner ----------------------------------------------------- */
 
 /* Autotuner.  Per half-decade height bin 10^(b/2) <= d < 10^((b+1)/2) from
- * 10^6 to 10^12, starting at the bin's geometric middle: time the plain walk
- * and the giant-step method at window scales 1 to 5 on 2^23 candidates and
- * keep the faster method and its best scale (below 10^6: the plain walk);
+ * 10^6 to 10^12: time the plain walk and the giant-step method at eight
+ * window scales from 1 to 5, each on 2^22 candidates at the bin's lower and
+ * upper quarter points, and keep the faster method and its best scale by the
+ * summed times (below 10^6: the plain walk); at the bin's geometric middle,
  * for the giant-step method, time the giant walk's walk chunk (8, 16, 32
- * reduction steps per phase) at that scale; then time a full pass's worth
- * of candidates cut into passes of 2^22, 2^23 and 2^24 candidates.  The AUTO
+ * reduction steps per phase) at that scale on 2^23 candidates; then time a
+ * full pass's worth of candidates cut into passes of 2^22, 2^23 and 2^24
+ * candidates.  The AUTO
  * method then follows these choices (an explicit method or window scale in
  * the config still wins).  With cfg.tune_cache_path set at eis_create, the
  * choices are loaded from that file when it exists and holds every bin, and
@@ -319,7 +321,7 @@ int eis_tune(eis_ctx *ctx);
 int eis_tuned_choice(eis_ctx *ctx, uint64_t d, int *method, double *window_scale);
 
 /* The tuned shape parameters in force for height d: *walk_chunk, the giant
- * walk's reduction steps per walk phase (default 8), and *pass_candidates,
+ * walk's reduction steps per walk phase (default 16), and *pass_candidates,
  * the candidates per pass a range starting at d is cut into (default 2^24).
  * Either pointer may be NULL. */
 int eis_tuned_shape(eis_ctx *ctx, uint64_t d, uint32_t *walk_chunk, uint64_t *pass_candidates);

@@ -668,10 +668,12 @@ static void infra_geometry(double scaled_root, u32 variant, u32 &emax, u32 &tsiz
     const u32 want = (variant & kVariantNoConjugate) ? emain + (3 * emain) / 4 + 16 : emain + 16;
     emax = (want + 7) / 8 * 8;  // whole 8-entry chunks (64-byte write-outs)
     if (emax > 496) emax = 496;
-    // load factor at most 0.5 for the usual count
+    // whole 8-slot groups (one 16-byte load each) at a load of at most 0.3
+    // for the usual count: a lookup then reads a second group for fewer than
+    // one key in 300; at most kTableSlotsMax slots
     const u32 count = (variant & kVariantNoConjugate) ? emain + emain / 2 + 4 : emain + 4;
-    tsize = 32;
-    while (tsize < 2 * std::min(count, emax)) tsize <<= 1;
+    const u32 groups = (10 * std::min(count, emax) + 23) / 24;
+    tsize = 8 * std::min(std::max(groups, 4u), kTableSlotsMax / 8);
 }
 
 // the method variant bits of a context's flags
@@ -1904,26 +1906,28 @@ static int time_range(eis_ctx *c, u64 d0, u64 n, u64 ps, u32 method, double ws, 
     return rc;
 }
 
-// Autotuner.  Per half-decade bin from 10^6, at the bin's geometric middle:
-// the plain walk against the giant-step method at six window scales on half
-// a pass (2^23 candidates); then, for the giant-step method, the walk chunk
-// (8, 16, 32 reduction steps per walk phase) at the chosen scale; then the
-// pass size (2^24, 2^23, 2^22 candidates; a smaller pass must be 2 % faster
-// to be kept) on a full pass of candidates.  The cache records every timing
-// beside the choices.
+// Autotuner.  Per half-decade bin from 10^6: the plain walk against the
+// giant-step method at eight window scales, each timed on 2^22 candidates at
+// the bin's lower and upper quarter points (plain_ms, giant_ms and scale_ms
+// are these sums); then, at the bin's geometric middle, for the giant-step
+// method the walk chunk (8, 16, 32 reduction steps per walk phase) at the
+// chosen scale on 2^23 candidates, and the pass size (2^24, 2^23, 2^22
+// candidates; a smaller pass must be 2 % faster to be kept) on a full pass
+// of candidates.  The cache records every timing beside the choices.
 extern "C" int eis_tune(eis_ctx *c)
 {
     if (!c) return EIS_EINVAL;
     std::lock_guard<std::mutex> g(c->gpu_mu);
     if (hipSetDevice(c->device) != hipSuccess) return EIS_EDEVICE;
-    const double scales[] = {1.0, 1.5, 2.0, 2.5, 3.5, 5.0};
+    constexpr int kScales = 8;
+    const double scales[kScales] = {1.0, 1.5, 1.75, 2.0, 2.25, 2.5, 3.5, 5.0};
     const u32 chunks[] = {8, 16, 32};
     const u32 plogs[] = {24, 23, 22};  // the largest first: a smaller one must win by 2 %
     const u32 n = 1u << 23;  // candidates per sample: half a full pass
     int method[kTuneBins];
     double wsc[kTuneBins], plain_ms[kTuneBins], giant_ms[kTuneBins];
     u32 chunk[kTuneBins], plog[kTuneBins];
-    double chunk_ms[kTuneBins][3], pass_ms[kTuneBins][3];
+    double chunk_ms[kTuneBins][3], pass_ms[kTuneBins][3], scale_ms[kTuneBins][kScales];
     for (int b = 0; b < kTuneBins; b++) {
         method[b] = 0;
         wsc[b] = kDefaultWindowScale;
@@ -1931,48 +1935,58 @@ extern "C" int eis_tune(eis_ctx *c)
         chunk[b] = kDefaultWalkChunk;
         plog[b] = 24;
         for (int k = 0; k < 3; k++) chunk_ms[b][k] = pass_ms[b][k] = 0.0;
+        for (int k = 0; k < kScales; k++) scale_ms[b][k] = 0.0;
     }
     float ms = 0.f;
     // one untimed pass of each method allocates every buffer
     int rc = time_range(c, 1000000005ull, n, n, 0, kDefaultWindowScale, kDefaultWalkChunk, ms);
     if (rc == EIS_OK) rc = time_range(c, 1000000005ull, n, n, 1, 5.0, kDefaultWalkChunk, ms);
     if (rc != EIS_OK) return rc;
-    // bins from 10^6 up, each sampled from its geometric middle: the last
-    // sample, at 10^11.75, ends below 10^12
+    // bins from 10^6 up.  The method and the window scale are timed at two
+    // heights of the bin (its lower and upper quarter points, half a sample
+    // each) and chosen by the sum, so that a choice fits the whole bin and
+    // two nearly equal scales are not told apart by one sample's noise; the
+    // walk chunk and the pass size at its geometric middle.  The last
+    // sample, from 10^11.875, ends below 10^12.
     for (int b = kTuneFirstBin; b < kTuneBins - 1; b++) {
         const u64 d0 = eis_first_candidate((u64)std::llround(std::pow(10.0, (b + 0.5) / 2.0)));
-        rc = time_range(c, d0, n, n, 0, kDefaultWindowScale, kDefaultWalkChunk, ms);
+        const u64 dq[2] = {eis_first_candidate((u64)std::llround(std::pow(10.0, (b + 0.25) / 2.0))),
+                           eis_first_candidate((u64)std::llround(std::pow(10.0, (b + 0.75) / 2.0)))};
+        auto two_heights = [&](u32 m, double ws, double &sum) {
+            sum = 0.0;
+            for (int q = 0; q < 2; q++) {
+                const int r = time_range(c, dq[q], n / 2, n / 2, m, ws, kDefaultWalkChunk, ms);
+                if (r != EIS_OK) return r;
+                sum += ms;
+            }
+            return (int)EIS_OK;
+        };
+        rc = two_heights(0, kDefaultWindowScale, plain_ms[b]);
         if (rc != EIS_OK) return rc;
-        plain_ms[b] = ms;
         double best = 1e30, best_ws = kDefaultWindowScale;
-        for (double ws : scales) {
-            rc = time_range(c, d0, n, n, 1, ws, kDefaultWalkChunk, ms);
+        for (int k = 0; k < kScales; k++) {
+            rc = two_heights(1, scales[k], scale_ms[b][k]);
             if (rc != EIS_OK) return rc;
-            if (ms < best) {
-                best = ms;
-                best_ws = ws;
+            if (scale_ms[b][k] < best) {
+                best = scale_ms[b][k];
+                best_ws = scales[k];
             }
         }
         method[b] = best < plain_ms[b] ? 1 : 0;
         wsc[b] = best_ws;
+        giant_ms[b] = best;
         if (method[b]) {
             double cbest = 1e30;
             for (int k = 0; k < 3; k++) {
-                if (chunks[k] == kDefaultWalkChunk) {
-                    ms = (float)best;
-                } else {
-                    rc = time_range(c, d0, n, n, 1, best_ws, chunks[k], ms);
-                    if (rc != EIS_OK) return rc;
-                }
+                rc = time_range(c, d0, n, n, 1, best_ws, chunks[k], ms);
+                if (rc != EIS_OK) return rc;
                 chunk_ms[b][k] = ms;
                 if (ms < cbest) {
                     cbest = ms;
                     chunk[b] = chunks[k];
                 }
             }
-            best = cbest;
         }
-        giant_ms[b] = best;
         double pbest = 1e30;
         for (int k = 0; k < 3; k++) {
             rc = time_range(c, d0, kPassCandidates, u64(1) << plogs[k], (u32)method[b], wsc[b],
@@ -2004,15 +2018,21 @@ extern "C" int eis_tune(eis_ctx *c)
     if (!c->tune_path.empty()) {
         FILE *f = std::fopen(c->tune_path.c_str(), "w");
         if (!f) return EIS_EINVAL;
-        std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"bins\": [\n", n);
-        for (int b = 0; b < kTuneBins; b++)
+        std::fprintf(f, "{\"arch\": \"gfx950\", \"sample_candidates\": %u, \"scales\": [", n);
+        for (int k = 0; k < kScales; k++) std::fprintf(f, "%s%.2f", k ? ", " : "", scales[k]);
+        std::fprintf(f, "], \"bins\": [\n");
+        for (int b = 0; b < kTuneBins; b++) {
             std::fprintf(f,
                          "  {\"b\": %d, \"method\": %d, \"window_scale\": %.3f, \"walk_chunk\": %u, "
                          "\"pass_log2\": %u, \"from\": %llu, \"plain_ms\": %.3f, \"giant_ms\": %.3f, "
-                         "\"chunk_ms_8_16_32\": [%.3f, %.3f, %.3f], \"pass_ms_24_23_22\": [%.3f, %.3f, %.3f]}%s\n",
+                         "\"chunk_ms_8_16_32\": [%.3f, %.3f, %.3f], \"pass_ms_24_23_22\": [%.3f, %.3f, %.3f], "
+                         "\"scale_ms\": [",
                          b, method[b], wsc[b], chunk[b], plog[b], (unsigned long long)bin_start(b),
                          plain_ms[b], giant_ms[b], chunk_ms[b][0], chunk_ms[b][1], chunk_ms[b][2],
-                         pass_ms[b][0], pass_ms[b][1], pass_ms[b][2], b < kTuneBins - 1 ? "," : "");
+                         pass_ms[b][0], pass_ms[b][1], pass_ms[b][2]);
+            for (int k = 0; k < kScales; k++) std::fprintf(f, "%s%.3f", k ? ", " : "", scale_ms[b][k]);
+            std::fprintf(f, "]}%s\n", b < kTuneBins - 1 ? "," : "");
+        }
         std::fprintf(f, "]}\n");
         if (std::fclose(f) != 0) return EIS_EINVAL;
     }

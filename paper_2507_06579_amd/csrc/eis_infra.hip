@@ -74,7 +74,7 @@ constexpr float kDpScale = 1.0f / 16.0f;
 constexpr float kDpHit = 2.0f / 64.0f;
 __device__ __forceinline__ bool is_dp(float Q4) { return __builtin_amdgcn_fractf(Q4 * kDpScale) == kDpHit; }
 
-constexpr u32 kTableMax = 1024;     // largest table (slots) per d
+constexpr u32 kTableMax = kTableSlotsMax;  // largest table (slots) per d
 constexpr u32 kWalkLimit = 4096;    // reduction steps from a giant ideal to a distinguished one
 constexpr u32 kExtraSteps = 6;      // window runs at least this far past mu_1
 constexpr u32 kMinMain = 16;        // mu_1 is at least the 16th distinguished ideal
@@ -423,24 +423,26 @@ constexpr u32 kSlotIndexBits = 9;
 constexpr u32 kSlotIndexMask = (1u << kSlotIndexBits) - 1;
 constexpr u32 kGroup = 8;
 __device__ __forceinline__ u32 slot_fp(u32 h) { return max(h >> (32 - (16 - kSlotIndexBits)), 1u); }
-__device__ __forceinline__ u32 home_slot(u32 h, u32 mask) { return h & mask & ~(kGroup - 1); }
+// The home group of hash h among `groups` groups: the low 24 bits of h
+// scaled to [0, groups) (the fingerprint takes the top bits, independent of
+// these).
+__device__ __forceinline__ u32 home_group(u32 h, u32 groups) { return __umul24(h, groups) >> 24; }
 
-// Insert val (hash h) into a wave's LDS table of mask + 1 slots: at the
-// next position of its home group, or, when that group is full, of the
-// first group after it that is not (so a key lies in its home group, or
-// that group is full and the key lies further on).  fill counts the
+// Insert val (hash h) into a wave's LDS table of `groups` groups: at the next
+// position of its home group, or, when that group is full, of the first
+// group after it (cyclically) that is not (so a key lies in its home group,
+// or that group is full and the key lies further on).  fill counts the
 // insertions per group; a group's entries fill its first slots.
-__device__ __forceinline__ void table_insert(u32 *tab, u32 *fill, u32 h, u32 mask, u32 val)
+__device__ __forceinline__ void table_insert(u32 *tab, u32 *fill, u32 h, u32 groups, u32 val)
 {
-    const u32 gmask = mask / kGroup;
-    u32 g = (h & mask) / kGroup;
-    for (u32 probe = 0; probe <= gmask; probe++) {
+    u32 g = home_group(h, groups);
+    for (u32 probe = 0; probe < groups; probe++) {
         const u32 k = atomicAdd(&fill[g], 1u);
         if (k < kGroup) {
             tab[g * kGroup + k] = val;
             return;
         }
-        g = (g + 1) & gmask;
+        g = (g + 1 == groups) ? 0u : g + 1;
     }
 }
 
@@ -488,7 +490,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
     const u32 wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
-    const u32 mask = p.tsize - 1;
+    const u32 tgroups = p.tsize / kGroup;  // table groups per d
     auto count_of = [&](u32 g) -> u32 {
         const u32 pos = 4 * g + wv;
         return (pos < n) ? p.state[pos].count : 0u;
@@ -502,7 +504,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
     for (u32 g = lb; 4 * g < n; g += nblk) {
         const u32 pos = 4 * g + wv;
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
-        for (u32 t = lane; t < p.tsize / kGroup; t += 64) fill[wv][t] = 0u;
+        for (u32 t = lane; t < tgroups; t += 64) fill[wv][t] = 0u;
         wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoads; k++) {
@@ -511,7 +513,7 @@ __device__ __forceinline__ void build_tables_body(const InfraParams &p, u32 (&ta
                 const u32 qb = (u32)(ent[0][k] >> 32), pb = (u32)ent[0][k];
                 const u32 h = dict_hash(qb, pb);
                 const u32 val = (e + 1) | (slot_fp(h) << kSlotIndexBits);
-                table_insert(tab[wv], fill[wv], h, mask, val);
+                table_insert(tab[wv], fill[wv], h, tgroups, val);
             }
         }
         wave_lds_sync();
@@ -546,7 +548,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
     const u32 wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const u32 total = p.list_ctr->list_len;
     const u32 n = (p.k0 < total) ? min(p.batch, total - p.k0) : 0u;
-    const u32 mask = p.tsize - 1;
+    const u32 tgroups = p.tsize / kGroup;  // table groups per d
     auto count_of = [&](u32 g) -> u32 {
         const u32 pos = 4 * g + wv;
         return (pos < n) ? p.state[pos].count : 0u;
@@ -559,7 +561,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
         const u32 cnt2 = count_of(g + 2 * nblk);
         load_entries<kLoadsLong>(p, pos + 4 * nblk, cnt1, ent1);
         for (u32 t = lane; t < p.tsize; t += 64) tab[wv][t] = 0u;
-        for (u32 t = lane; t < p.tsize / kGroup; t += 64) fill[wv][t] = 0u;
+        for (u32 t = lane; t < tgroups; t += 64) fill[wv][t] = 0u;
         wave_lds_sync();
 #pragma unroll
         for (u32 k = 0; k < kLoadsLong; k++) {
@@ -568,7 +570,7 @@ __device__ __forceinline__ void build_tables_long(const InfraParams &p, u32 (&ta
                 const u32 qb = (u32)(ent0[k] >> 32), pb = (u32)ent0[k];
                 const u32 h = dict_hash(qb, pb);
                 const u32 val = (e + 1) | (slot_fp(h) << kSlotIndexBits);
-                table_insert(tab[wv], fill[wv], h, mask, val);
+                table_insert(tab[wv], fill[wv], h, tgroups, val);
             }
         }
         wave_lds_sync();
@@ -601,7 +603,7 @@ __global__ __launch_bounds__(256) void k_retry_tables(InfraParams p) { build_tab
 hipError_t launch_build_tables(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
     if (p.batch == 0 || grid == 0) return hipSuccess;
-    if (p.tsize > kTableMax || p.tsize < kGroup || (p.tsize & (p.tsize - 1)) != 0) return hipErrorInvalidValue;
+    if (p.tsize > kTableMax || p.tsize < kGroup || p.tsize % kGroup != 0) return hipErrorInvalidValue;
     (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_tables : k_build_tables, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();
@@ -805,13 +807,14 @@ hipError_t launch_giant_square(const InfraParams &p, bool retry, hipStream_t str
 constexpr u32 kNoEntry = ~0u;
 
 // Lookup of the window entries with keys (qb, pa) and (qb, pc) in a d's
-// table: their indices and residue sums, or kNoEntry.  Split in two so that
-// the loads of the two home groups are issued well before their values are
-// needed (their latency then hides behind the composition).  A group's
-// first slot with the key's fingerprint is confirmed against the full key
-// in the list, whose residue sum is loaded with it; the rest (a false first
-// candidate with another after it, or a full group without the key, about
-// one chain in a thousand at the usual load) scans slot by slot.
+// table of `groups` groups: their indices and residue sums, or kNoEntry.  Split in
+// two so that the loads of the two home groups are issued well before their
+// values are needed (their latency then hides behind the composition).  A
+// group's first slot with the key's fingerprint is confirmed against the
+// full key in the list, whose residue sum is loaded with it; the rest (a
+// false first candidate with another after it, or a full group without the
+// key) goes on group by group, in a branch the wave takes only when one of
+// its lanes needs it.
 struct DictProbe {
     unsigned long long ka, kc;  // the two keys
     u32 fa, fc;                 // their fingerprints, shifted to the slot's field
@@ -819,7 +822,7 @@ struct DictProbe {
     uint4 va, vc;               // the home groups (loads in flight)
 };
 
-__device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 mask, u32 qb, u32 pa, u32 pc)
+__device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 groups, u32 qb, u32 pa, u32 pc)
 {
     DictProbe d;
     d.ka = ((unsigned long long)qb << 32) | pa;
@@ -827,32 +830,37 @@ __device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 mask, u32 q
     const u32 ha = dict_hash(qb, pa), hc = dict_hash(qb, pc);
     d.fa = slot_fp(ha) << kSlotIndexBits;
     d.fc = slot_fp(hc) << kSlotIndexBits;
-    d.ga = home_slot(ha, mask);
-    d.gc = home_slot(hc, mask);
+    d.ga = home_group(ha, groups) * kGroup;
+    d.gc = home_group(hc, groups) * kGroup;
     d.va = *reinterpret_cast<const uint4 *>(tbl + d.ga);
     d.vc = *reinterpret_cast<const uint4 *>(tbl + d.gc);
     return d;
 }
 
-// In group g: the position of the first slot whose fingerprint field is f
-// (kGroup if none), whether another such slot follows, and whether the
-// group has an empty slot.
-__device__ __forceinline__ u32 group_match(uint4 g, u32 f, bool &more, bool &open)
+// Slots of group g whose fingerprint field is f, as a bit mask (bit i =
+// slot i; empty slots never match, fingerprints being nonzero).
+__device__ __forceinline__ u32 group_mask(uint4 g, u32 f)
 {
     const u32 pat = f | (f << 16);
     const u32 w[4] = {g.x, g.y, g.z, g.w};
     u32 mb = 0;
-    bool em = false;
 #pragma unroll
     for (u32 k = 0; k < 4; k++) {
         const u32 x = w[k] ^ pat;
         mb |= ((x & 0xfe00u) == 0u ? 1u : 0u) << (2 * k);
         mb |= (x < 0x02000000u ? 1u : 0u) << (2 * k + 1);
-        em = em || (w[k] & 0xffffu) == 0u || w[k] < 0x10000u;
     }
-    more = (mb & (mb - 1u)) != 0u;
-    open = em;
-    return mb ? (u32)__builtin_ctz(mb) : kGroup;
+    return mb;
+}
+
+// whether group g has an empty slot
+__device__ __forceinline__ bool group_open(uint4 g)
+{
+    const u32 w[4] = {g.x, g.y, g.z, g.w};
+    bool em = false;
+#pragma unroll
+    for (u32 k = 0; k < 4; k++) em = em || (w[k] & 0xffffu) == 0u || w[k] < 0x10000u;
+    return em;
 }
 
 // list entry of slot i (< kGroup) of group g
@@ -863,28 +871,35 @@ __device__ __forceinline__ u32 group_entry(uint4 g, u32 i)
     return ((w >> (16u * (i & 1u))) & kSlotIndexMask) - 1u;
 }
 
-// Slot-by-slot scan from slot s (a home group's first) to the first empty
-// slot: the entry with key k and fingerprint field f, or kNoEntry.
-__device__ __forceinline__ u32 dict_scan(const u16 *tbl, const unsigned long long *lst, u32 mask,
-                                         u32 tsize, u32 s, u32 f, unsigned long long k)
+// Group by group from slot s (a home group's first): the entry with key k
+// and fingerprint field f and its residue sum r, or kNoEntry.
+__device__ __forceinline__ u32 dict_scan(const u16 *tbl, const unsigned long long *lst,
+                                         const u32 *lres, u32 tsize, u32 s, u32 f,
+                                         unsigned long long k, u32 &r)
 {
-    for (u32 probe = 0; probe < tsize; probe++) {
-        const u32 v = tbl[s];
-        if (v == 0u) break;
-        if ((v & ~kSlotIndexMask) == f && lst[(v & kSlotIndexMask) - 1] == k)
-            return (v & kSlotIndexMask) - 1;
-        s = (s + 1) & mask;
+    for (u32 t = 0; t < tsize / kGroup; t++) {
+        const uint4 g = *reinterpret_cast<const uint4 *>(tbl + s);
+        for (u32 mb = group_mask(g, f); mb != 0u; mb &= mb - 1u) {
+            const u32 e = group_entry(g, (u32)__builtin_ctz(mb));
+            if (lst[e] == k) {
+                r = lres[e];
+                return e;
+            }
+        }
+        if (group_open(g)) break;
+        s += kGroup;
+        if (s == tsize) s = 0;
     }
     return kNoEntry;
 }
 
 __device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long long *lst,
-                                             const u32 *lres, u32 mask, u32 tsize, const DictProbe &d,
+                                             const u32 *lres, u32 tsize, const DictProbe &d,
                                              u32 &ea, u32 &ec, u32 &ra, u32 &rc)
 {
-    bool morea, moreC, opena, openc;
-    const u32 ia = group_match(d.va, d.fa, morea, opena);
-    const u32 ic = group_match(d.vc, d.fc, moreC, openc);
+    const u32 mba = group_mask(d.va, d.fa), mbc = group_mask(d.vc, d.fc);
+    const u32 ia = mba ? (u32)__builtin_ctz(mba) : kGroup;
+    const u32 ic = mbc ? (u32)__builtin_ctz(mbc) : kGroup;
     // the first candidates, their list keys and residue sums loaded together
     const u32 ca = ia < kGroup ? group_entry(d.va, ia) : 0u;
     const u32 cc = ic < kGroup ? group_entry(d.vc, ic) : 0u;
@@ -900,17 +915,11 @@ __device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long
     }
     ea = (ia < kGroup && la == d.ka) ? ca : kNoEntry;
     ec = (ic < kGroup && lc == d.kc) ? cc : kNoEntry;
-    const bool slowa = ea == kNoEntry && ((ia < kGroup && morea) || !opena);
-    const bool slowc = ec == kNoEntry && ((ic < kGroup && moreC) || !openc);
+    const bool slowa = ea == kNoEntry && ((mba & (mba - 1u)) != 0u || !group_open(d.va));
+    const bool slowc = ec == kNoEntry && ((mbc & (mbc - 1u)) != 0u || !group_open(d.vc));
     if (__builtin_amdgcn_ballot_w64(slowa || slowc)) {
-        if (slowa) {
-            ea = dict_scan(tbl, lst, mask, tsize, d.ga, d.fa, d.ka);
-            if (ea != kNoEntry) ra = lres[ea];
-        }
-        if (slowc) {
-            ec = dict_scan(tbl, lst, mask, tsize, d.gc, d.fc, d.kc);
-            if (ec != kNoEntry) rc = lres[ec];
-        }
+        if (slowa) ea = dict_scan(tbl, lst, lres, tsize, d.ga, d.fa, d.ka, ra);
+        if (slowc) ec = dict_scan(tbl, lst, lres, tsize, d.gc, d.fc, d.kc, rc);
     }
 }
 
@@ -985,7 +994,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
     const u32 lane = __lane_id();
     // reduction steps per walk phase (a tuned shape parameter), even
     const u32 chunk = __builtin_amdgcn_readfirstlane((min(max(p.walk_chunk, 2u), 64u) + 1u) & ~1u);
-    const u32 mask = p.tsize - 1;
+    const u32 tgroups = p.tsize / kGroup;  // table groups per d
     // ring heads and tails (wave-uniform); every slot starts free
     u32 head[3] = {0u, 0u, 0u}, tail[3] = {kPoolSlots, 0u, 0u};
     for (u32 s = lane; s < kPoolSlots; s += 64) pl.ring[kRingFree][s] = (unsigned char)s;
@@ -1087,7 +1096,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                 const float Qw = pl.Qw[s], Pw = pl.Pw[s], Qpw = pl.Qpw[s];
                 float Pn, Qn, acc1 = 0.f;
                 rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
-                dp = dict_start2(p.tables + (u64)pos * p.tsize, mask, __float_as_uint(Qw),
+                dp = dict_start2(p.tables + (u64)pos * p.tsize, tgroups, __float_as_uint(Qw),
                                  __float_as_uint(Pw), __float_as_uint(Pn));
             }
             const bool comp = on && ng > 1 && ng < p.max_giants;
@@ -1119,7 +1128,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
             if (on) {
                 u32 ed, ec, rd, rc;
                 dict_finish2(p.tables + (u64)pos * p.tsize, p.lists + (u64)pos * p.emax,
-                             p.lres + (u64)pos * p.emax, mask, p.tsize, dp, ed, ec, rd, rc);
+                             p.lres + (u64)pos * p.emax, p.tsize, dp, ed, ec, rd, rc);
                 my_looks++;
                 const u32 Sw = (pk >> 4) & 3u;
                 bool done = false, flag = false;
@@ -1255,8 +1264,7 @@ hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStre
 {
     if (grid == 0) return hipSuccess;
     // lookups read whole 16-byte groups of the tables
-    if (p.tsize > kTableMax || p.tsize < kGroup || (p.tsize & (p.tsize - 1)) != 0)
-        return hipErrorInvalidValue;
+    if (p.tsize > kTableMax || p.tsize < kGroup || p.tsize % kGroup != 0) return hipErrorInvalidValue;
     (void)hipGetLastError();  // the check below reports this launch only
     hipLaunchKernelGGL(retry ? k_retry_giant : k_walk_giant, dim3(grid), dim3(256), 0, stream, p);
     return hipGetLastError();

@@ -156,7 +156,7 @@ struct InfraParams {
     u32 *lres;                  // 2 S (twice the residue sum) of each entry, same layout
     u16 *tables;                // hash tables, tsize 16-bit slots per batch position
     u32 emax;                   // list capacity per d (a multiple of 8)
-    u32 tsize;                  // table slots per d (power of two)
+    u32 tsize;                  // table slots per d (whole groups of 8, at most kTableSlotsMax)
     u32 max_steps;              // per-d budget of reduction steps (window)
     u32 max_giants;             // per-d budget of giant steps
     u32 emain_shift;            // mu_1 this many entries later (the retry round)
@@ -165,9 +165,12 @@ struct InfraParams {
     u32 walk_chunk;             // giant walk: reduction steps per walk phase
 };
 
+// Largest dictionary table per d (16-bit slots).
+constexpr u32 kTableSlotsMax = 1024;
+
 // Default reduction steps per walk phase of the giant walk (the tuner's
 // usual choice above 10^10).
-constexpr u32 kDefaultWalkChunk = 8;
+constexpr u32 kDefaultWalkChunk = 16;
 
 // Method variants (all give the same bits).  kVariantNoConjugate: the giant
 // step is mu_1 itself (the paper's stride) and only direct lookups are made;

@@ -146,7 +146,7 @@ def test_batch_ranges_tuned_mixed_choices(tmp_path):
     """A tuned context whose per-height choices alternate between the plain
     walk and giant steps at several window scales: one batch mixes all of
     them and must still equal the oracle."""
-    scales = [1.0, 1.5, 2.0, 2.5, 3.5, 5.0]
+    scales = [1.0, 1.5, 1.75, 2.0, 2.25, 2.5, 3.5, 5.0]
     path = _tune_file(tmp_path, lambda b: (b % 3 != 0) * 1, lambda b: scales[b % len(scales)])
     a, b, want = _batch("batch")
     with eis.Context(tune_cache_path=path) as c:

@@ -253,15 +253,15 @@ def test_window_scale_does_not_change_bits(scale):
 
 
 def test_small_memory_budget_runs_many_giant_batches():
-    # a budget that leaves room for about 2^16 dictionaries forces the
-    # giant-step method through many batches of one pass; bits and counts
-    # must not depend on that
+    # a budget that leaves room for one or two batches of 2^16 dictionaries
+    # (about 1.6 KB each at this height) forces the giant-step method through
+    # many batches of one pass; bits and counts must not depend on that
     a, b = 4 * 10**10, 4 * 10**10 + 10**7
     with eis.Context(method=eis.Method.BABY) as cb:
         ref = cb.eis_classify(a, b)
-    with eis.Context(method=eis.Method.INFRA, mem_budget_bytes=300 << 20,
+    with eis.Context(method=eis.Method.INFRA, mem_budget_bytes=340 << 20,
                      flags=eis.EIS_FLAG_KERNEL_TIMES) as ci:
-        _say("infra with a 300 MiB budget")
+        _say("infra with a 340 MiB budget")
         got = ci.eis_classify(a, b)
         st = ci.eis_get_stats()
     launches = st["kernel_launches"][eis.KERNELS.index("walk_giant")]

@@ -12,7 +12,7 @@ import paper_2507_06579_amd as eis
 
 pytestmark = pytest.mark.gpu
 
-SCALES = {1.0, 1.5, 2.0, 2.5, 3.5, 5.0}
+SCALES = {1.0, 1.5, 1.75, 2.0, 2.25, 2.5, 3.5, 5.0}
 
 
 def _say(msg):
@@ -37,11 +37,17 @@ def test_tune_choices_cache_and_bits(tmp_path):
     with open(path) as f:
         doc = json.load(f)
     assert doc["arch"] == "gfx950" and len(doc["bins"]) == 25
+    assert set(doc["scales"]) == SCALES
     for bn in doc["bins"]:
         assert bn["walk_chunk"] in (8, 16, 32) and bn["pass_log2"] in (22, 23, 24)
         if bn["b"] >= 12 and bn["b"] < 24:
-            # every timing behind the choice is recorded
+            # every timing behind the choice is recorded, and the scale kept
+            # is the fastest one timed
             assert min(bn["pass_ms_24_23_22"]) > 0
+            assert len(bn["scale_ms"]) == len(SCALES) and min(bn["scale_ms"]) > 0
+            best = doc["scales"][bn["scale_ms"].index(min(bn["scale_ms"]))]
+            assert bn["window_scale"] == pytest.approx(best)
+            assert bn["giant_ms"] == pytest.approx(min(bn["scale_ms"]), abs=1e-3)
             if bn["method"] == 1:
                 assert min(bn["chunk_ms_8_16_32"]) > 0
     with eis.Context(method=eis.Method.BABY) as c:
