@@ -140,7 +140,7 @@ __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned
     rg.key[slot][lane] = entry_of(Q, P);
     rg.res[slot][lane] = res2;
     cnt++;
-    if (cnt % kRing == 0) ring_flush(rg, lane, lb, rb, cnt - kRing);
+    if (slot == kRing - 1) ring_flush(rg, lane, lb, rb, cnt - kRing);
 }
 
 // How a lane's window ended, kept until the wave's next pause (the lane
