@@ -44,13 +44,15 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # rules measured on the device (SQ_ACTIVE_INST_VALU / _VALU2 counters):
 # v_rcp_f32 takes two slots, and v_fract_f32 / v_floor_f32 issue beside
 # another VALU instruction of the same quad-cycle (no slot of their own).
-# Plain walk: 11 VALU + rcp: the biased quotient (fma, mul, floor), the
-# overshoot test, P' and Q' (fma, sub, fma), the residue (fract, fma) and
-# two exit tests -> 11 + 2 (rcp) - 2 (floor, fract) = 11 slots.
-VALU_SLOTS_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0}
+# Plain walk: 10 VALU + rcp: the biased quotient (fma, mul, floor), P' and Q'
+# (fma, sub, fma), the residue (fract, fma) and two exit tests -> 10 + 2
+# (rcp) - 2 (floor, fract) = 10 slots.  These counts are for passes whose d's
+# are all at most 1.45e11 (every workload here): their walks leave the
+# quotient's overshoot test out; above that height a step has one more slot.
+VALU_SLOTS_PER_STEP = {"walk_plain": 10.0, "walk_handoff": 10.0}
 # Window walk, per lane path like the giant walk's model, counted in the
 # gfx950 code of the built kernel with the same issue rules: per rho step the
-# step with its two half-period compares (11), the distinguished-ideal test
+# step with its two half-period compares (10), the distinguished-ideal test
 # (mul, fract, cmp: 2) and half of the two per-pair window tests (mu_1
 # staged, window end: 1); per distinguished ideal appended (counted by the
 # kernel, eis_stats.window_entries) the append: the selection of the pair's
@@ -59,7 +61,7 @@ VALU_SLOTS_PER_STEP = {"walk_plain": 11.0, "walk_handoff": 11.0}
 # whenever any of its lanes appends; the lanes that do not append are not
 # counted.  mu_1's bookkeeping (once per window) and a window's end (written
 # at the wave's next pause) are not counted.
-WINDOW_SLOTS = {"rho_steps": 14.0, "entries": 15.375}
+WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 # Giant-step walk: VALU issue slots per unit of its work, counted the same
 # way in the gfx950 code of the built kernel (per-lane path; a branch that a
 # lane does not take is not counted for it), the units being counted by the
@@ -72,13 +74,13 @@ WINDOW_SLOTS = {"rho_steps": 14.0, "entries": 15.375}
 #   Euclid step (extended or partial Euclid, two per loop iteration of 27):
 #     13.5;
 #   reduction step after a composition (fp64, with its checks): 47;
-#   walk step towards the next distinguished ideal (the step, the test): 11;
+#   walk step towards the next distinguished ideal (the step, the test): 10;
 #   lookup of a distinguished ideal and its conjugate (two hashes, the scan
 #     of two 8-slot groups for fingerprints and empty slots, the tests on a
 #     lane's path when no slot matches, the extra step for the conjugate's
 #     key): 140.
 GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "euclid_steps": 13.5,
-               "reduce_steps": 47.0, "walk_steps": 11.0, "lookups": 140.0}
+               "reduce_steps": 47.0, "walk_steps": 10.0, "lookups": 140.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the

@@ -741,7 +741,11 @@ struct PassPlan {
     u32 grid_plain = 0, grid_win = 0, grid_giant = 0, grid_fb = 0, grid_tables = 0;
     u64 roff_total = 0;
     u32 walk_chunk = kDefaultWalkChunk;  // that of the highest giant-step segment
+    u64 dmax = 0;                        // the largest candidate d of the pass
 };
+
+// Whether the walks of the pass may leave the quotient's overshoot test out.
+static bool exact_quot(const PassPlan &pl) { return pl.dmax <= kExactQuotMaxD; }
 
 // Fill the pinned segment table and the plan of a pass.
 static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u64 infra_avail,
@@ -761,6 +765,7 @@ static void plan_pass(eis_ctx *c, const HostSeg *segs, u32 nseg, SegInfo *hs, u6
         g.word_off = word;
         g.block_off = block;
         const u64 dlast = h.d0 + 8ull * (h.n - 1);
+        if (h.n) pl.dmax = std::max(pl.dmax, dlast);
         g.np = primes_needed(c, dlast);
         g.roff_off = (u32)roff;
         g.method = h.method;
@@ -877,6 +882,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, const PassBufs &B, 
     wp.nseg = pl.nseg;
     wp.eis_words = B.eis_words;
     wp.max_steps = (u32)c->cfg.max_steps_per_d;
+    wp.exact_quot = exact_quot(pl) ? 1u : 0u;
     if (pl.plain_cand) {
         wp.list = B.list_plain;
         wp.ctr = ctr_plain;
@@ -908,6 +914,7 @@ static int enqueue_pass_body(eis_ctx *c, const PassPlan &pl, const PassBufs &B, 
         ip.emain_shift = 0;
         ip.variant = variant_of(c);
         ip.walk_chunk = pl.walk_chunk;
+        ip.exact_quot = wp.exact_quot;
         ip.eis_words = B.eis_words;
         for (u32 bi = 0; bi < pl.nbatches; bi++) {
             ip.k0 = (u32)(bi * pl.batch);
@@ -966,7 +973,8 @@ static std::vector<u64> plan_key(const eis_ctx *c, const PassPlan &pl)
 {
     return {pl.nseg, pl.nblocks, pl.np_max, pl.words, pl.plain_cand ? 1ull : 0ull,
             pl.giant_cand ? 1ull : 0ull, pl.emax, pl.tsize, pl.batch, pl.nbatches, pl.grid_plain,
-            pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d, pl.walk_chunk};
+            pl.grid_win, pl.grid_giant, pl.grid_fb, c->cfg.max_steps_per_d, pl.walk_chunk,
+            exact_quot(pl) ? 1ull : 0ull};
 }
 
 // Enqueue a planned pass on buffer set B, whose segment table is in place:

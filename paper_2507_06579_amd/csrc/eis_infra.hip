@@ -149,14 +149,10 @@ __device__ __forceinline__ void window_append(WindowRing &rg, u32 lane, unsigned
 // not).
 constexpr u32 kFinNone = 0, kFinWindow = 1, kFinRange = 2, kFinHalf = 4;
 
-__device__ __forceinline__ void walk_window_body(InfraParams p)
+template <bool kCheck>
+__device__ __forceinline__ void walk_window_body(const InfraParams &p, const SegLds *segs,
+                                                 WindowRing *rings)
 {
-    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
-    // The segment table is sized at launch (p.nseg entries): with one segment
-    // the rings alone bound the workgroups per CU (six instead of five).
-    extern __shared__ SegLds segs[];
-    __shared__ WindowRing rings[4];
-    load_segs(segs, p.segs, p.nseg);
     const u32 lane = __lane_id();
     WindowRing &rg = rings[threadIdx.x >> 6];
     const u32 total = p.list_ctr->list_len;
@@ -261,10 +257,10 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
         float P1 = 0.f, Q1 = 0.f, acc = 0.f;
         for (;;) {
             float P2, Q2;
-            rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
+            rho_step_q<kCheck>(sq, sqc, P, Q, Qp, P1, Q1, acc);
             const u64 mA = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
             const float accA = acc;
-            rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
+            rho_step_q<kCheck>(sq, sqc, P1, Q1, Q, P2, Q2, acc);
             const u64 mB = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
             // The pair's distinguished ideals, in walk order: one append for
             // the first, which the wave runs at almost every pair, and a
@@ -386,8 +382,22 @@ __device__ __forceinline__ void walk_window_body(InfraParams p)
     }
 }
 
-__global__ __launch_bounds__(256) void k_walk_window(InfraParams p) { walk_window_body(p); }
-__global__ __launch_bounds__(256) void k_retry_window(InfraParams p) { walk_window_body(p); }
+__device__ __forceinline__ void walk_window_entry(const InfraParams &p)
+{
+    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
+    // The segment table is sized at launch (p.nseg entries): with one segment
+    // the rings alone bound the workgroups per CU (six instead of five).
+    extern __shared__ SegLds segs[];
+    __shared__ WindowRing rings[4];
+    load_segs(segs, p.segs, p.nseg);
+    if (p.exact_quot)
+        walk_window_body<false>(p, segs, rings);
+    else
+        walk_window_body<true>(p, segs, rings);
+}
+
+__global__ __launch_bounds__(256) void k_walk_window(InfraParams p) { walk_window_entry(p); }
+__global__ __launch_bounds__(256) void k_retry_window(InfraParams p) { walk_window_entry(p); }
 
 hipError_t launch_walk_window(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {
@@ -968,21 +978,10 @@ __device__ __forceinline__ u32 lanes_below(u64 m)
     return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
 }
 
-__device__ __forceinline__ void walk_giant_body(InfraParams p)
+template <bool kCheck>
+__device__ __forceinline__ void walk_giant_body(const InfraParams &p, const SegLds *segs,
+                                                const u32 *bstart, GiantPool *pools)
 {
-    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
-    __shared__ SegLds segs[kMaxSegments];
-    __shared__ u32 bstart[kCostBuckets + 1];  // queue index of each bucket's first task
-    __shared__ GiantPool pools[4];
-    if (threadIdx.x == 0) {
-        u32 acc = 0;
-        for (u32 b = 0; b < kCostBuckets; b++) {
-            bstart[b] = acc;
-            acc += p.gbuckets[16 * b];
-        }
-        bstart[kCostBuckets] = acc;
-    }
-    load_segs(segs, p.segs, p.nseg);  // ends with a barrier
     const u32 n = bstart[kCostBuckets];
     auto task_of = [&](u32 q) -> const GiantTask * {
         u32 b = 0;
@@ -1095,7 +1094,7 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                 const float sq = pl.sq[s], sqc = sq * kQuotBias;
                 const float Qw = pl.Qw[s], Pw = pl.Pw[s], Qpw = pl.Qpw[s];
                 float Pn, Qn, acc1 = 0.f;
-                rho_step_q(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
+                rho_step_q<kCheck>(sq, sqc, Pw, Qw, Qpw, Pn, Qn, acc1);
                 dp = dict_start2(p.tables + (u64)pos * p.tsize, tgroups, __float_as_uint(Qw),
                                  __float_as_uint(Pw), __float_as_uint(Pn));
             }
@@ -1202,12 +1201,12 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
                 bool run = !is_dp(Qa);
                 for (u32 k = 0; k < chunk; k += 2) {
                     if (run) {
-                        rho_step_q(sq, sqc, Pa, Qa, Qb, Pb, Qb, acc);
+                        rho_step_q<kCheck>(sq, sqc, Pa, Qa, Qb, Pb, Qb, acc);
                         u++;
                         run = !is_dp(Qb);
                     }
                     if (run) {
-                        rho_step_q(sq, sqc, Pb, Qb, Qa, Pa, Qa, acc);
+                        rho_step_q<kCheck>(sq, sqc, Pb, Qb, Qa, Pa, Qa, acc);
                         u++;
                         run = !is_dp(Qa);
                     }
@@ -1257,8 +1256,29 @@ __device__ __forceinline__ void walk_giant_body(InfraParams p)
     }
 }
 
-__global__ __launch_bounds__(256) void k_walk_giant(InfraParams p) { walk_giant_body(p); }
-__global__ __launch_bounds__(256) void k_retry_giant(InfraParams p) { walk_giant_body(p); }
+__device__ __forceinline__ void walk_giant_entry(const InfraParams &p)
+{
+    if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
+    __shared__ SegLds segs[kMaxSegments];
+    __shared__ u32 bstart[kCostBuckets + 1];  // queue index of each bucket's first task
+    __shared__ GiantPool pools[4];
+    if (threadIdx.x == 0) {
+        u32 acc = 0;
+        for (u32 b = 0; b < kCostBuckets; b++) {
+            bstart[b] = acc;
+            acc += p.gbuckets[16 * b];
+        }
+        bstart[kCostBuckets] = acc;
+    }
+    load_segs(segs, p.segs, p.nseg);  // ends with a barrier
+    if (p.exact_quot)
+        walk_giant_body<false>(p, segs, bstart, pools);
+    else
+        walk_giant_body<true>(p, segs, bstart, pools);
+}
+
+__global__ __launch_bounds__(256) void k_walk_giant(InfraParams p) { walk_giant_entry(p); }
+__global__ __launch_bounds__(256) void k_retry_giant(InfraParams p) { walk_giant_entry(p); }
 
 hipError_t launch_walk_giant(const InfraParams &p, u32 grid, bool retry, hipStream_t stream)
 {

@@ -101,6 +101,7 @@ struct WalkParams {
     PassCounters *ctr;            // list_len, queue head, error and step counters
     u32 *eis_words;               // output bitmaps of the pass
     u32 max_steps;                // per-d step budget
+    u32 exact_quot;               // 1: every d of the pass is at most kExactQuotMaxD
 };
 
 // ---- infrastructure method ------------------------------------------------
@@ -163,7 +164,13 @@ struct InfraParams {
     u32 *eis_words;             // output bitmaps of the pass
     u32 variant;                // kVariant* bits (0: the default method)
     u32 walk_chunk;             // giant walk: reduction steps per walk phase
+    u32 exact_quot;             // 1: every d of the pass is at most kExactQuotMaxD
 };
+
+// Heights up to which the biased fp32 quotient of a reduction step is never
+// one too large (the step's overshoot test can be left out; the bound is
+// derived beside rho_step_q and holds with margin: 4.1 10^11).
+constexpr u64 kExactQuotMaxD = 145000000000ull;
 
 // Largest dictionary table per d (16-bit slots).
 constexpr u32 kTableSlotsMax = 1024;

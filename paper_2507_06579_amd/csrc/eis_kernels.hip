@@ -265,10 +265,9 @@ __device__ __forceinline__ u32 exit_batch(float s)
     return (u32)fminf(fmaxf(rintf(sqrtf(5.2e6f / s)), 1.f), 32.f);
 }
 
-__global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
+template <bool kCheck>
+__device__ __forceinline__ void walk_baby_body(const WalkParams &p, const SegLds *segs)
 {
-    __shared__ SegLds segs[kMaxSegments];
-    load_segs(segs, p.segs, p.nseg);
     const u32 n = p.ctr->list_len;
     // inner-loop length between budget checks; a walk that has not ended
     // after max_steps (rounded up to a multiple of K) is abandoned and counted
@@ -338,9 +337,9 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
         float P1 = 0.f, Q1 = 0.f, acc = 0.f;
         for (;;) {
             float P2, Q2;
-            rho_step_q(sq, sqc, P, Q, Qp, P1, Q1, acc);
+            rho_step_q<kCheck>(sq, sqc, P, Q, Qp, P1, Q1, acc);
             const u64 mA = __builtin_amdgcn_ballot_w64(Q1 == Q) | __builtin_amdgcn_ballot_w64(P1 == P);
-            rho_step_q(sq, sqc, P1, Q1, Q, P2, Q2, acc);
+            rho_step_q<kCheck>(sq, sqc, P1, Q1, Q, P2, Q2, acc);
             const u64 mB = __builtin_amdgcn_ballot_w64(Q2 == Q1) | __builtin_amdgcn_ballot_w64(P2 == P1);
             const u64 em = (mA | mB) & lm;
             if (em) {
@@ -389,6 +388,16 @@ __global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
         atomicAdd(&p.ctr->baby_steps, (unsigned long long)my_steps);
         atomicAdd(&p.ctr->refills, (unsigned long long)my_refills);
     }
+}
+
+__global__ __launch_bounds__(256) void k_walk_baby(WalkParams p)
+{
+    __shared__ SegLds segs[kMaxSegments];
+    load_segs(segs, p.segs, p.nseg);
+    if (p.exact_quot)
+        walk_baby_body<false>(p, segs);
+    else
+        walk_baby_body<true>(p, segs);
 }
 
 hipError_t launch_walk_baby(const WalkParams &p, u32 grid, hipStream_t stream)

@@ -50,15 +50,20 @@ __device__ __forceinline__ void emit_flag(u32 *eis_words, u32 idx, bool eis)
 // when P' = 3 (mod 4); acc sums 4 fract(P'/4), i.e. 1 or 3 per step (an exact
 // integer while acc < 2^24), and the caller folds it into S: over k steps,
 // the residues r = 1 + bit1(P') add up to (k + acc) / 2.
+// kCheck = false leaves the overshoot test out, for walks whose every d is at
+// most kExactQuotMaxD: an overshoot needs (k + 1) Q - t <= t (2^-21 + 5 2^-24)
+// with (k + 1) Q - t >= 1 for the integers t = P + s and Q, i.e. t >= 2^24 / 13,
+// and t <= 2 s, so it cannot happen below d = 4.1 10^11.
 constexpr float kQuotBias = 1.f + 0x1p-21f;
 
+template <bool kCheck = true>
 __device__ __forceinline__ void rho_step_q(float sq, float sqc, float P, float Q, float Qp,
                                            float &Pn, float &Qn, float &acc)
 {
     const float rq = __builtin_amdgcn_rcpf(Q);
     float q = floorf(fmaf(P, kQuotBias, sqc) * rq);
     Pn = fmaf(q, Q, -P);
-    if (__builtin_amdgcn_ballot_w64(Pn > sq)) {
+    if (kCheck && __builtin_amdgcn_ballot_w64(Pn > sq)) {
         // rare: keep it a branch (an empty volatile asm is not speculated)
         __asm__ volatile("");
         if (Pn > sq) {
