@@ -15,10 +15,16 @@ workload: d1 the plain walk on [5, 10^6]; d2 [10^9, 10^9 + 10^7) with both
 methods (identical bitmaps required); d3 the 64 seeded uneven ranges, one
 batched call against 64 single calls; d5 the seeded Poisson request stream
 served at 10 to 10^4 requests/s, past saturation (p50/p99 latency,
-throughput).  The headline roofline comes from the headline steps alone.
+throughput).  The headline roofline comes from the headline steps alone;
+its `traffic` (HBM bytes per launch of the dominant kernel) is measured in
+the same run: the headline step once more in two child processes under
+rocprofv3 --pmc (FETCH_SIZE, then WRITE_SIZE), with this run's tuned choices
+and a 1 GiB copy to scale the counters (profiles/traffic.json is the
+fallback when rocprofv3 is missing, valid only for the recorded sources).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--method auto|baby|infra]
                   [--no-configs] [--no-serving] [--no-cpu-baseline] [--no-tune]
+                  [--tune-cache PATH] [--no-traffic]
 """
 from __future__ import annotations
 
@@ -117,19 +123,20 @@ def measured_traffic(kernel: str, workload: str):
 TRAFFIC_KERNELS = ["k_walk_giant", "k_walk_window", "k_build_tables", "k_giant_square"]
 
 
-def record_traffic(fetch_dir: str, write_dir: str, probe_mib: int, commands):
-    """Write profiles/traffic.json from two rocprofv3 --pmc runs of this bench
-    (one step, --copy-probe-mib probe_mib): FETCH_SIZE and WRITE_SIZE (KiB per
-    dispatch) of each kernel's last dispatch, each scaled by what the same
-    counter reads for the copy probe (probe_mib MiB read and written).  Runs
-    on the host from the counter files alone."""
+def traffic_from_counters(fetch_dir: str, write_dir: str, probe_mib: int):
+    """HBM bytes per launch of each kernel in TRAFFIC_KERNELS from the output
+    folders of two rocprofv3 --pmc runs of this bench (one step,
+    --copy-probe-mib probe_mib): FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    of the kernel's last dispatch, each scaled by what the same counter reads
+    for the copy probe (probe_mib MiB read and written).  Returns
+    ({kernel: (fetch_kib, write_kib, bytes)}, probe record); host only."""
     import csv
     import glob
 
     def read(d, counter):
         files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
         if not files:
-            raise SystemExit(f"no counter_collection.csv under {d}")
+            raise RuntimeError(f"no counter_collection.csv under {d}")
         per = {}
         for fn in files:
             with open(fn) as f:
@@ -150,28 +157,84 @@ def record_traffic(fetch_dir: str, write_dir: str, probe_mib: int, commands):
     fcopy = max(v for (k, _), v in fetch.items() if "elementwise" in k)
     wcopy = max(v for (k, _), v in write.items() if "elementwise" in k)
     fs, ws = probe_kib / fcopy, probe_kib / wcopy
+    out = {}
+    for k in TRAFFIC_KERNELS:
+        fk, wk = last_of(fetch, k), last_of(write, k)
+        if fk is not None and wk is not None:
+            out[k] = (fk, wk, int(round((fk * fs + wk * ws) * 1024)))
+    probe = {"mib": probe_mib, "fetch_kib": fcopy, "write_kib": wcopy, "fetch_scale": fs,
+             "write_scale": ws}
+    return out, probe
+
+
+def record_traffic(fetch_dir: str, write_dir: str, probe_mib: int, commands):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of this bench
+    (see traffic_from_counters); runs on the host from the counter files."""
+    per, probe = traffic_from_counters(fetch_dir, write_dir, probe_mib)
     doc = {"_note": "HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs "
                     "(KiB per dispatch, the last dispatch of each kernel), each scaled by the "
                     "reading of the same counter for an elementwise copy of "
                     f"{probe_mib} MiB read + {probe_mib} MiB written in the same run "
                     "(bench.py --copy-probe-mib); valid while the device sources hash to "
                     "device_sources_sha256",
-           "copy_probe": {"mib": probe_mib, "fetch_kib": fcopy, "write_kib": wcopy,
-                          "fetch_scale": fs, "write_scale": ws}}
+           "copy_probe": probe}
     sha = device_sources_sha256()
-    for k in TRAFFIC_KERNELS:
-        fk, wk = last_of(fetch, k), last_of(write, k)
-        if fk is None or wk is None:
-            continue
+    for k, (fk, wk, nbytes) in per.items():
         doc[k] = {"large:infra": {"device_sources_sha256": sha, "fetch_kib": fk, "write_kib": wk,
-                                  "fetch_scale": fs, "write_scale": ws,
-                                  "hbm_bytes_per_launch": int(round((fk * fs + wk * ws) * 1024)),
-                                  "commands": list(commands)}}
+                                  "fetch_scale": probe["fetch_scale"],
+                                  "write_scale": probe["write_scale"],
+                                  "hbm_bytes_per_launch": nbytes, "commands": list(commands)}}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)
         f.write("\n")
     return doc
+
+
+def live_traffic(tune_path: str, log, timeout_s: float = 180.0):
+    """HBM bytes per launch of the kernels measured in this run: the headline
+    step once more in two child processes under rocprofv3 --pmc (FETCH_SIZE,
+    then WRITE_SIZE), with this run's tuned choices (its tune cache) and a
+    1 GiB copy probe for the scale.  Returns ({kernel: bytes}, the commands)
+    or (None, reason) when rocprofv3 is missing or a run fails."""
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3") or ("/opt/rocm/bin/rocprofv3"
+                                         if os.path.exists("/opt/rocm/bin/rocprofv3") else None)
+    if prof is None:
+        return None, "rocprofv3 not found"
+    work = tempfile.mkdtemp(prefix="eis_pmc_", dir="/tmp")
+    child = [sys.executable, os.path.abspath(__file__), "--steps", "1", "--warmup", "0",
+             "--no-cpu-baseline", "--no-serving", "--no-configs", "--no-traffic",
+             "--copy-probe-mib", "1024"]
+    if tune_path:
+        child += ["--tune-cache", tune_path]
+    else:
+        child += ["--no-tune"]
+    dirs, cmds = [], []
+    env = dict(os.environ, TMPDIR="/tmp")
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = os.path.join(work, counter.lower())
+        cmd = [prof, "--pmc", counter, "--output-format", "csv", "-d", d, "-o", "run", "--"] + child
+        log(f"traffic: {counter} run")
+        try:
+            with open(os.path.join(work, counter.lower() + ".log"), "w") as lf:
+                r = subprocess.run(cmd, cwd="/tmp", env=env, stdout=lf, stderr=subprocess.STDOUT,
+                                   timeout=timeout_s)
+        except subprocess.TimeoutExpired:
+            return None, f"{counter} run timed out"
+        # rocprofv3 itself may end with a fault after writing its results
+        if r.returncode != 0 and not os.path.isdir(d):
+            return None, f"{counter} run failed ({r.returncode})"
+        dirs.append(d)
+        cmds.append(" ".join(["rocprofv3", "--pmc", counter, "--", "python3", "bench.py"] +
+                             child[2:]))
+    try:
+        per, _ = traffic_from_counters(dirs[0], dirs[1], 1024)
+    except (RuntimeError, ValueError) as e:
+        return None, f"counters unreadable: {e}"
+    return {k: v[2] for k, v in per.items()}, cmds
 
 
 def log(msg):
@@ -528,6 +591,11 @@ def main():
                     help="giant-step window scale (0: tuned or default)")
     ap.add_argument("--no-tune", action="store_true",
                     help="auto method without running the autotuner first")
+    ap.add_argument("--tune-cache", default=None,
+                    help="auto method with the choices of this tune cache (no tuning)")
+    ap.add_argument("--no-traffic", action="store_true",
+                    help="do not measure the dominant kernel's HBM traffic in child "
+                         "rocprofv3 runs (then it comes from profiles/traffic.json, if current)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving sweep (config d5)")
@@ -567,11 +635,14 @@ def main():
     eb = torch.zeros(nb, dtype=torch.uint8, device=dev)
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
     import tempfile
-    tune_dir = tempfile.mkdtemp(prefix="eis_tune_")
-    tune_path = os.path.join(tune_dir, "tune.json")
+    if args.tune_cache:
+        tune_path = args.tune_cache
+    else:
+        tune_dir = tempfile.mkdtemp(prefix="eis_tune_")
+        tune_path = os.path.join(tune_dir, "tune.json")
     ctx = eis.Context(device=0, method=method, flags=eis.EIS_FLAG_KERNEL_TIMES,
                       window_scale=args.window_scale, tune_cache_path=tune_path)
-    if method == eis.Method.AUTO and not args.no_tune:
+    if method == eis.Method.AUTO and not args.no_tune and not args.tune_cache:
         t = time.perf_counter()
         ctx.eis_tune()
         log(f"autotuner: {time.perf_counter() - t:.1f} s")
@@ -727,6 +798,21 @@ def main():
         "roofline_other_walks": others,
     }
     ctx.close()
+    roofline["traffic_source"] = None
+    if roofline["traffic"] is not None:
+        roofline["traffic_source"] = "profiles/traffic.json (recorded for these device sources)"
+    if not args.no_traffic:
+        per, how = live_traffic(tune_path if os.path.exists(tune_path) else None, log)
+        if per is not None and roofline["kernel"] in per:
+            roofline["traffic"] = per[roofline["kernel"]]
+            roofline["traffic_source"] = "measured in this run: " + " ; ".join(how)
+            for name, ent in others.items():
+                kn = KERNEL_NAME.get(name)
+                if kn in per:
+                    ent["traffic"] = per[kn]
+            log(f"traffic: {roofline['traffic'] / 1e9:.2f} GB per launch of {roofline['kernel']}")
+        else:
+            log(f"traffic not measured: {how}")
     if not args.no_configs:
         if not os.path.exists(tune_path):
             tune_path = None  # untuned: the contexts of the configs take the defaults
