@@ -81,12 +81,13 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 #     13.5;
 #   reduction step after a composition (fp64, with its checks): 47;
 #   walk step towards the next distinguished ideal (the step, the test): 10;
-#   lookup of a distinguished ideal and its conjugate (two hashes, the scan
-#     of two 8-slot groups for fingerprints and empty slots, the tests on a
-#     lane's path when no slot matches, the extra step for the conjugate's
-#     key): 140.
+#   lookup of a distinguished ideal and its conjugate (the extra step for
+#     the conjugate's key, two hashes, home groups, fingerprints and group
+#     addresses: 43; the byte-parallel fingerprint match of two 8-slot
+#     groups, the list addresses and the tests on a lane's path when no slot
+#     matches: 69): 112.
 GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "euclid_steps": 13.5,
-               "reduce_steps": 47.0, "walk_steps": 10.0, "lookups": 140.0}
+               "reduce_steps": 47.0, "walk_steps": 10.0, "lookups": 112.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the

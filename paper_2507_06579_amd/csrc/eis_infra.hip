@@ -847,38 +847,39 @@ __device__ __forceinline__ DictProbe dict_start2(const u16 *tbl, u32 groups, u32
     return d;
 }
 
-// Slots of group g whose fingerprint field is f, as a bit mask (bit i =
-// slot i; empty slots never match, fingerprints being nonzero).
-__device__ __forceinline__ u32 group_mask(uint4 g, u32 f)
+// Slots of group g whose fingerprint field is f: bit 8 i + 7 is set for
+// slot i (empty slots never match, fingerprints being nonzero).  In each
+// 32-bit word, x = word ^ f in both fields, bit 15 of a field of
+// ((x & 0x7e00) + 0x7e00) | x is set iff the field's fingerprint bits 9-15
+// differ from f's (the sum carries into bit 15 iff one of bits 9-14 of x is
+// set, and never out of the field); a byte permute gathers the high byte of
+// every field, slot order kept.
+__device__ __forceinline__ unsigned long long group_match(uint4 g, u32 f)
 {
     const u32 pat = f | (f << 16);
-    const u32 w[4] = {g.x, g.y, g.z, g.w};
-    u32 mb = 0;
-#pragma unroll
-    for (u32 k = 0; k < 4; k++) {
-        const u32 x = w[k] ^ pat;
-        mb |= ((x & 0xfe00u) == 0u ? 1u : 0u) << (2 * k);
-        mb |= (x < 0x02000000u ? 1u : 0u) << (2 * k + 1);
-    }
-    return mb;
+    auto differs = [pat](u32 w) {
+        const u32 x = w ^ pat;
+        return ((x & 0x7e007e00u) + 0x7e007e00u) | x;
+    };
+    // result bytes: byte 1 and byte 3 of the low word, then of the high word
+    const u32 lo = __builtin_amdgcn_perm(differs(g.y), differs(g.x), 0x07050301u);
+    const u32 hi = __builtin_amdgcn_perm(differs(g.w), differs(g.z), 0x07050301u);
+    return ~(((unsigned long long)hi << 32) | lo) & 0x8080808080808080ull;
 }
 
-// whether group g has an empty slot
-__device__ __forceinline__ bool group_open(uint4 g)
-{
-    const u32 w[4] = {g.x, g.y, g.z, g.w};
-    bool em = false;
-#pragma unroll
-    for (u32 k = 0; k < 4; k++) em = em || (w[k] & 0xffffu) == 0u || w[k] < 0x10000u;
-    return em;
-}
+// the lowest set bit of m (m != 0)
+__device__ __forceinline__ u32 low_bit(unsigned long long m) { return (u32)__builtin_ctzll(m); }
 
-// list entry of slot i (< kGroup) of group g
-__device__ __forceinline__ u32 group_entry(uint4 g, u32 i)
+// Whether group g has an empty slot.  A group's entries fill its first
+// slots (insertion takes the group's next position), so its last slot tells.
+__device__ __forceinline__ bool group_open(uint4 g) { return g.w < 0x10000u; }
+
+// list entry of the slot whose match bit is b (= 8 i + 7 for slot i)
+__device__ __forceinline__ u32 group_entry(uint4 g, u32 b)
 {
-    const u32 lo = (i & 2u) ? g.y : g.x, hi = (i & 2u) ? g.w : g.z;
-    const u32 w = (i & 4u) ? hi : lo;
-    return ((w >> (16u * (i & 1u))) & kSlotIndexMask) - 1u;
+    const unsigned long long h = (b >= 32u) ? (((unsigned long long)g.w << 32) | g.z)
+                                            : (((unsigned long long)g.y << 32) | g.x);
+    return ((u32)(h >> ((b << 1) & 0x30u)) & kSlotIndexMask) - 1u;
 }
 
 // Group by group from slot s (a home group's first): the entry with key k
@@ -889,8 +890,8 @@ __device__ __forceinline__ u32 dict_scan(const u16 *tbl, const unsigned long lon
 {
     for (u32 t = 0; t < tsize / kGroup; t++) {
         const uint4 g = *reinterpret_cast<const uint4 *>(tbl + s);
-        for (u32 mb = group_mask(g, f); mb != 0u; mb &= mb - 1u) {
-            const u32 e = group_entry(g, (u32)__builtin_ctz(mb));
+        for (unsigned long long m = group_match(g, f); m != 0ull; m &= m - 1ull) {
+            const u32 e = group_entry(g, low_bit(m));
             if (lst[e] == k) {
                 r = lres[e];
                 return e;
@@ -907,26 +908,25 @@ __device__ __forceinline__ void dict_finish2(const u16 *tbl, const unsigned long
                                              const u32 *lres, u32 tsize, const DictProbe &d,
                                              u32 &ea, u32 &ec, u32 &ra, u32 &rc)
 {
-    const u32 mba = group_mask(d.va, d.fa), mbc = group_mask(d.vc, d.fc);
-    const u32 ia = mba ? (u32)__builtin_ctz(mba) : kGroup;
-    const u32 ic = mbc ? (u32)__builtin_ctz(mbc) : kGroup;
+    const unsigned long long ma = group_match(d.va, d.fa), mc = group_match(d.vc, d.fc);
+    const bool ha = ma != 0ull, hc = mc != 0ull;
     // the first candidates, their list keys and residue sums loaded together
-    const u32 ca = ia < kGroup ? group_entry(d.va, ia) : 0u;
-    const u32 cc = ic < kGroup ? group_entry(d.vc, ic) : 0u;
+    const u32 ca = ha ? group_entry(d.va, low_bit(ma)) : 0u;
+    const u32 cc = hc ? group_entry(d.vc, low_bit(mc)) : 0u;
     unsigned long long la = 0, lc = 0;
     ra = rc = 0u;
-    if (ia < kGroup) {
+    if (ha) {
         la = lst[ca];
         ra = lres[ca];
     }
-    if (ic < kGroup) {
+    if (hc) {
         lc = lst[cc];
         rc = lres[cc];
     }
-    ea = (ia < kGroup && la == d.ka) ? ca : kNoEntry;
-    ec = (ic < kGroup && lc == d.kc) ? cc : kNoEntry;
-    const bool slowa = ea == kNoEntry && ((mba & (mba - 1u)) != 0u || !group_open(d.va));
-    const bool slowc = ec == kNoEntry && ((mbc & (mbc - 1u)) != 0u || !group_open(d.vc));
+    ea = (ha && la == d.ka) ? ca : kNoEntry;
+    ec = (hc && lc == d.kc) ? cc : kNoEntry;
+    const bool slowa = ea == kNoEntry && ((ma & (ma - 1ull)) != 0ull || !group_open(d.va));
+    const bool slowc = ec == kNoEntry && ((mc & (mc - 1ull)) != 0ull || !group_open(d.vc));
     if (__builtin_amdgcn_ballot_w64(slowa || slowc)) {
         if (slowa) ea = dict_scan(tbl, lst, lres, tsize, d.ga, d.fa, d.ka, ra);
         if (slowc) ec = dict_scan(tbl, lst, lres, tsize, d.gc, d.fc, d.kc, rc);
