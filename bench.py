@@ -77,8 +77,12 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 #     set-up and final checks of the reduction, the kernel's bookkeeping: 330;
 #   NUCOMP's gcd branch, when taken (the second Bezout cofactor, H, l and
 #     their reductions mod H): 136;
-#   Euclid step (extended or partial Euclid, two per loop iteration of 27):
-#     13.5;
+#   extended Euclid step (nearest-integer quotients, two per loop iteration
+#     of 18: the iteration count's copy 1, per step the reciprocal 2, the
+#     quotient, remainder, cofactor, tests and selects 6; v_rndne_f32
+#     counted like v_floor_f32): 9;
+#   partial Euclid step (floor quotients with the overshoot correction, two
+#     per loop iteration of 30): 15;
 #   reduction step after a composition (fp64, with its checks): 47;
 #   walk step towards the next distinguished ideal (the step, the test): 10;
 #   lookup of a distinguished ideal and its conjugate (the extra step for
@@ -86,8 +90,9 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 #     addresses: 43; the byte-parallel fingerprint match of two 8-slot
 #     groups, the list addresses and the tests on a lane's path when no slot
 #     matches: 69): 112.
-GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "euclid_steps": 13.5,
-               "reduce_steps": 47.0, "walk_steps": 10.0, "lookups": 112.0}
+GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "xgcd_steps": 9.0,
+               "partial_euclid_steps": 15.0, "reduce_steps": 47.0, "walk_steps": 10.0,
+               "lookups": 112.0}
 
 
 # Device code whose HBM byte counts profiles/traffic.json records; the
@@ -343,8 +348,9 @@ def slot_model(eis, name, d):
     if name != "walk_giant":
         return VALU_SLOTS_PER_STEP[name] * ks[k], ks[k], "rho step", None
     work = {key: d["giant_" + key]
-            for key in ("compositions", "gcd_branches", "euclid_steps", "reduce_steps",
+            for key in ("compositions", "gcd_branches", "xgcd_steps", "reduce_steps",
                         "lookups")}
+    work["partial_euclid_steps"] = d["giant_euclid_steps"] - d["giant_xgcd_steps"]
     work["walk_steps"] = ks[k]
     slots = sum(GIANT_SLOTS[key] * v for key, v in work.items())
     fill = {}
@@ -723,8 +729,10 @@ def main():
         if name != "walk_giant":
             return VALU_SLOTS_PER_STEP[name] * ks[k], ks[k], "rho step", None
         work = {key: st["giant_" + key] - base["giant_" + key]
-                for key in ("compositions", "gcd_branches", "euclid_steps", "reduce_steps",
+                for key in ("compositions", "gcd_branches", "xgcd_steps", "reduce_steps",
                             "lookups")}
+        work["partial_euclid_steps"] = (st["giant_euclid_steps"] - base["giant_euclid_steps"]
+                                        - work["xgcd_steps"])
         work["walk_steps"] = ks[k]
         slots = sum(GIANT_SLOTS[key] * v for key, v in work.items())
         fill = {}

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define EIS_ABI_VERSION 7
+#define EIS_ABI_VERSION 8
 
 /* Largest supported exclusive upper bound b.  The baby-step walk keeps every
  * quantity below 2^24 and exact in fp32 up to this height, and the giant-step
@@ -170,6 +170,9 @@ typedef struct {
      * eis_submit) */
     uint64_t serve_bytes_reserved;
     uint64_t serve_bytes_budget;
+    /* of giant_euclid_steps, the steps of the extended Euclid loops (the two
+     * loops have different instruction counts) */
+    uint64_t giant_xgcd_steps;
 } eis_stats;
 
 /* Fill *cfg with defaults (device 0, EIS_METHOD_AUTO). */
@@ -304,7 +307,7 @@ int eis_cancel(eis_ctx *ctx, uint64_t ticket);
  * upper quarter points, and keep the faster method and its best scale by the
  * summed times (below 10^6: the plain walk); at the bin's geometric middle,
  * for the giant-step method, time the giant walk's walk chunk (8, 16, 32
- * reduction steps per phase) at that scale on 2^23 candidates; then time a
+ * reduction steps per phase) at that scale on 2^24 candidates; then time a
  * full pass's worth of candidates cut into passes of 2^22, 2^23 and 2^24
  * candidates.  The AUTO
  * method then follows these choices (an explicit method or window scale in

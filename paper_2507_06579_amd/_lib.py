@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libeis.so")
 
 EIS_MAX_D = 10**12
-ABI_VERSION = 7  # must match EIS_ABI_VERSION of include/eis.h
+ABI_VERSION = 8  # must match EIS_ABI_VERSION of include/eis.h
 EIS_SET_SQUAREFREE = 0
 EIS_SET_PRIME = 1
 EIS_FLAG_NO_GRAPHS = 1
@@ -93,6 +93,7 @@ class EisStats(ctypes.Structure):
         ("giant_walk_lanes", ctypes.c_uint64),
         ("serve_bytes_reserved", ctypes.c_uint64),
         ("serve_bytes_budget", ctypes.c_uint64),
+        ("giant_xgcd_steps", ctypes.c_uint64),
     ]
 
     def as_dict(self):

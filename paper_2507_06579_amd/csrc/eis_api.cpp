@@ -1118,6 +1118,7 @@ static int add_counters(eis_ctx *c, const PassCounters *h, bool retry)
     c->stats.giant_steps += h[1].giant_steps;
     c->stats.giant_compositions += h[1].giant_comps;
     c->stats.giant_euclid_steps += h[1].giant_euclid;
+    c->stats.giant_xgcd_steps += h[1].giant_xgcd;
     c->stats.giant_reduce_steps += h[1].giant_reduce;
     c->stats.giant_gcd_branches += h[1].giant_gcd_branch;
     c->stats.giant_lookups += h[1].giant_lookups;
@@ -1919,9 +1920,11 @@ static int time_range(eis_ctx *c, u64 d0, u64 n, u64 ps, u32 method, double ws, 
 // the bin's lower and upper quarter points (plain_ms, giant_ms and scale_ms
 // are these sums); then, at the bin's geometric middle, for the giant-step
 // method the walk chunk (8, 16, 32 reduction steps per walk phase) at the
-// chosen scale on 2^23 candidates, and the pass size (2^24, 2^23, 2^22
-// candidates; a smaller pass must be 2 % faster to be kept) on a full pass
-// of candidates.  The cache records every timing beside the choices.
+// chosen scale on a full pass of candidates (on half a pass the giant walk
+// has half the d's per wave and its walk phases run less full, which made
+// 32 look best where it is 2-5 % slower on full passes), and the pass size
+// (2^24, 2^23, 2^22 candidates; a smaller pass must be 2 % faster to be
+// kept) on a full pass of candidates.  The cache records every timing beside the choices.
 extern "C" int eis_tune(eis_ctx *c)
 {
     if (!c) return EIS_EINVAL;
@@ -1986,7 +1989,7 @@ extern "C" int eis_tune(eis_ctx *c)
         if (method[b]) {
             double cbest = 1e30;
             for (int k = 0; k < 3; k++) {
-                rc = time_range(c, d0, n, n, 1, best_ws, chunks[k], ms);
+                rc = time_range(c, d0, kPassCandidates, kPassCandidates, 1, best_ws, chunks[k], ms);
                 if (rc != EIS_OK) return rc;
                 chunk_ms[b][k] = ms;
                 if (ms < cbest) {

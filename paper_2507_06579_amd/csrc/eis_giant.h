@@ -95,21 +95,30 @@ __device__ __forceinline__ float neg_fl_div32(float a, float b, float &r)
 }
 
 // Work counts of one composition (for the instruction model of the giant
-// walk): Euclid steps of the extended and partial Euclid loops, reduction
-// steps after the composition, and whether NUCOMP took its gcd branch.
+// walk): Euclid steps of the extended and partial Euclid loops (and, of
+// those, the extended Euclid's), reduction steps after the composition, and
+// whether NUCOMP took its gcd branch.
 struct GiantWork {
-    u32 euclid = 0, reduce = 0, gcd_branch = 0;
+    u32 euclid = 0, xgcd = 0, reduce = 0, gcd_branch = 0;
 };
 
 // Extended Euclid, the first cofactor only: g = gcd(a, b) >= 0 and x with
 // x a + y b = g for some integer y (so x a = g mod b), for integers |a|,
-// |b| < 2^21 (then |x| < 2^21 too): exact in fp32.  Invariants: x0 A = a and
-// x1 A = b modulo B, for the inputs A = |a|, B = |b|; the loop ends when one
-// of a, b is 0, and the other is the gcd.  A caller that needs y computes
-// (g - x a) / b, an exact division.  Two division steps per iteration, the
-// second with the roles of (a, x0) and (b, x1) exchanged and applied only if
-// the first left a != 0 (a select, not a branch), so that no step moves
-// registers around.
+// |b| < 2^21: exact in fp32.  Invariants: x0 A = a and x1 A = b modulo B,
+// for the inputs A = |a|, B = |b|; the loop ends when one of a, b is 0, and
+// the other is +-g.  Each division step takes the quotient nearest to a / b
+// (remainders of either sign), which needs about 30 % fewer steps than
+// floor quotients (1 / 1.71 against 1 / 1.19 steps per unit of ln b for the
+// nearest-integer and the regular continued fraction) and no correction:
+// the estimate rint(a rcp(b)) is within 0.875 of a / b (relative error of
+// rcp and the product below 1.5 2^-23, a / b < 2^21), so |remainder| <
+// 0.875 |b| and the remainders fall strictly.  The cofactors stay below B / g
+// in magnitude.  x is determined modulo B / g, which is all the callers use
+// (their results are the same for every such x).  A caller that needs y
+// computes (g - x a) / b, an exact division.  Two division steps per
+// iteration, the second with the roles of (a, x0) and (b, x1) exchanged
+// and applied only if the first left a != 0 (a select, not a branch), so
+// that no step moves registers around.
 __device__ __forceinline__ void xgcd1(double ad, double bd, double &x, double &g, GiantWork &wk)
 {
     const float sa = ad < 0.0 ? -1.f : 1.f;
@@ -117,22 +126,24 @@ __device__ __forceinline__ void xgcd1(double ad, double bd, double &x, double &g
     float x0 = 1.f, x1 = 0.f;
     u32 iters = 0;
     while (a != 0.f && b != 0.f) {
-        float r;
-        float nq = neg_fl_div32(a, b, r);
-        a = r;
-        x0 = fmaf(nq, x1, x0);
+        float q = rintf(a * __builtin_amdgcn_rcpf(b));
+        a = fmaf(-q, b, a);
+        x0 = fmaf(-q, x1, x0);
         const bool go = a != 0.f;
-        nq = neg_fl_div32(b, go ? a : 1.f, r);
-        b = go ? r : b;
-        x1 = go ? fmaf(nq, x0, x1) : x1;
+        q = rintf(b * __builtin_amdgcn_rcpf(go ? a : 1.f));
+        b = go ? fmaf(-q, a, b) : b;
+        x1 = go ? fmaf(-q, x0, x1) : x1;
         iters++;
     }
     const bool az = a == 0.f;
     // every iteration takes two steps but the last, whose second step is
     // skipped when it leaves a = 0
-    wk.euclid += iters ? 2u * iters - (az ? 1u : 0u) : 0u;
-    g = (double)(az ? b : a);
-    x = (double)((az ? x1 : x0) * sa);
+    const u32 steps = iters ? 2u * iters - (az ? 1u : 0u) : 0u;
+    wk.euclid += steps;
+    wk.xgcd += steps;
+    const float gs = az ? b : a, xs = az ? x1 : x0;
+    g = (double)fabsf(gs);
+    x = (double)((gs < 0.f ? -xs : xs) * sa);
 }
 
 struct Form {

@@ -1008,7 +1008,7 @@ __device__ __forceinline__ void walk_giant_body(const InfraParams &p, const SegL
     };
     bool drained = false;
     u32 cbase = 0, cend = 0;  // the wave's claimed chunk of the task queue
-    u32 my_giants = 0, my_comps = 0, my_eu = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
+    u32 my_giants = 0, my_comps = 0, my_eu = 0, my_xg = 0, my_red = 0, my_gcdb = 0, my_looks = 0;
     u64 my_steps = 0;
     // phases run (compose, walk) and the lanes they kept busy (wave-uniform)
     u32 phases[2] = {0u, 0u}, lanes_on[2] = {0u, 0u};
@@ -1164,6 +1164,7 @@ __device__ __forceinline__ void walk_giant_body(const InfraParams &p, const SegL
                 } else {
                     my_comps++;
                     my_eu += cwk.euclid;
+                    my_xg += cwk.xgcd;
                     my_red += cwk.reduce;
                     my_gcdb += cwk.gcd_branch;
                     pl.cQ[s] = cQ4;
@@ -1235,11 +1236,11 @@ __device__ __forceinline__ void walk_giant_body(const InfraParams &p, const SegL
             push(kRingFree, gone, s);
         }
     }
-    u64 sums[6] = {my_giants, my_comps, my_eu, my_red, my_gcdb, my_looks};
+    u64 sums[7] = {my_giants, my_comps, my_eu, my_red, my_gcdb, my_looks, my_xg};
     for (int off = 32; off > 0; off >>= 1) {
         my_steps += __shfl_down(my_steps, off, 64);
 #pragma unroll
-        for (int k = 0; k < 6; k++) sums[k] += __shfl_down(sums[k], off, 64);
+        for (int k = 0; k < 7; k++) sums[k] += __shfl_down(sums[k], off, 64);
     }
     if (lane == 0) {
         atomicAdd(&p.ctr->chunk_steps, (unsigned long long)my_steps);
@@ -1249,6 +1250,7 @@ __device__ __forceinline__ void walk_giant_body(const InfraParams &p, const SegL
         atomicAdd(&p.ctr->giant_reduce, (unsigned long long)sums[3]);
         atomicAdd(&p.ctr->giant_gcd_branch, (unsigned long long)sums[4]);
         atomicAdd(&p.ctr->giant_lookups, (unsigned long long)sums[5]);
+        atomicAdd(&p.ctr->giant_xgcd, (unsigned long long)sums[6]);
         for (int k = 0; k < 2; k++) {
             atomicAdd(&p.ctr->giant_phases[k], (unsigned long long)phases[k]);
             atomicAdd(&p.ctr->giant_lanes[k], (unsigned long long)lanes_on[k]);

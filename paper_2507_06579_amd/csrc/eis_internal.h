@@ -69,6 +69,7 @@ struct PassCounters {
     unsigned long long chunk_steps;  // rho steps inside the giant-step walk
     // work of the giant walk's compositions (see GiantWork)
     unsigned long long giant_comps, giant_euclid, giant_reduce, giant_lookups, giant_gcd_branch;
+    unsigned long long giant_xgcd;  // of giant_euclid, the extended Euclid's steps
     unsigned long long window_entries;  // list appends of the window walk
     // phases of the giant walk (compose, walk) and the lanes they kept busy
     unsigned long long giant_phases[2], giant_lanes[2];

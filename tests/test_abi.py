@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version_and_strings():
-    assert eis.eis_abi_version() == eis.ABI_VERSION == 7
+    assert eis.eis_abi_version() == eis.ABI_VERSION == 8
     for st in eis.Status:
         assert eis.eis_strerror(int(st))
     assert eis.eis_strerror(12345) == "unknown status"

@@ -94,21 +94,23 @@ def test_kernel_times_and_step_counts():
         k = eis.KERNELS
         assert kl[k.index("sieve")] == 1 and kl[k.index("popcount")] == 1
         gw = [st[f] for f in ("giant_compositions", "giant_euclid_steps", "giant_reduce_steps",
-                              "giant_gcd_branches", "giant_lookups")]
+                              "giant_gcd_branches", "giant_lookups", "giant_xgcd_steps")]
         if method == eis.Method.BABY:
             assert kl[k.index("walk_plain")] == 1 and kl[k.index("walk_window")] == 0
             assert ks[k.index("walk_plain")] == st["baby_steps"]
-            assert gw == [0, 0, 0, 0, 0] and st["window_entries"] == 0
+            assert gw == [0, 0, 0, 0, 0, 0] and st["window_entries"] == 0
         else:
             assert kl[k.index("walk_window")] >= 1 and kl[k.index("walk_giant")] >= 1
             assert kl[k.index("giant_square")] == kl[k.index("walk_giant")]
             assert ks[k.index("walk_window")] > 0 and st["giant_steps"] > 0
-            comps, euclid, red, gcdb, looks = gw
+            comps, euclid, red, gcdb, looks, xgcd = gw
             # every giant ideal (g, g2 and each composition) is looked up
             # once, unless a check fails first; every composition runs at
-            # least one Euclid step, and some take NUCOMP's gcd branch
+            # least one Euclid step, and some take NUCOMP's gcd branch; the
+            # extended Euclid's steps are part of the Euclid steps
             assert 0 < comps < st["giant_steps"] and 0 < looks <= st["giant_steps"]
             assert looks >= comps and euclid > comps and 0 <= gcdb < comps and red >= 0
+            assert comps < xgcd < euclid
             # the window walk appends its distinguished ideals (Q = 2 mod 64):
             # about one reduction step in 16
             ent = st["window_entries"]
