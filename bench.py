@@ -81,8 +81,9 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 #     of 18: the iteration count's copy 1, per step the reciprocal 2, the
 #     quotient, remainder, cofactor, tests and selects 6; v_rndne_f32
 #     counted like v_floor_f32): 9;
-#   partial Euclid step (floor quotients with the overshoot correction, two
-#     per loop iteration of 30): 15;
+#   partial Euclid step (floor quotients, whose estimate needs no
+#     correction for the norms of d <= 10^12; two per loop iteration of 21,
+#     the iteration count's copy included): 10.5;
 #   reduction step after a composition (fp64, with its checks): 47;
 #   walk step towards the next distinguished ideal (the step, the test): 10;
 #   lookup of a distinguished ideal and its conjugate (the extra step for
@@ -91,7 +92,7 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
 #     groups, the list addresses and the tests on a lane's path when no slot
 #     matches: 69): 112.
 GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "xgcd_steps": 9.0,
-               "partial_euclid_steps": 15.0, "reduce_steps": 47.0, "walk_steps": 10.0,
+               "partial_euclid_steps": 10.5, "reduce_steps": 47.0, "walk_steps": 10.0,
                "lookups": 112.0}
 
 

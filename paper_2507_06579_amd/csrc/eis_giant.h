@@ -72,26 +72,23 @@ __device__ __forceinline__ double ex_div(double a, double b, Chk &c)
     return q;
 }
 
-// -q and r = a - q b, for q = floor(a / b) and integer-valued fp32 0 <= a < 2^21,
-// 0 < b < 2^21.  The estimate floor(fl(a c) rcp(b)) with c = 1 + 2^-21 is
-// never below the true quotient k: the relative errors of the roundings
-// (the product a c, the reciprocal's 1 ulp, the final product) add up to
-// less than 2^-21.  It is at most k + 1: for b <= 2 the reciprocal and the
-// last product are exact and a 2^-21 < 1, and for b >= 3 the excess is
-// below (a / b) 1.5 2^-21 < 0.5.  An overshoot needs (k + 1) b - a <= 1.5 a
-// 2^-21, i.e. r = b - 1 and a >= 2^21 / 1.5: it cannot happen below
-// 1.4 10^6 and is rare above; r < 0 detects it, and it is undone by
-// arithmetic (a wave-uniform branch around the correction measured slower).
+// -q and r = a - q b, for q = floor(a / b) and integer-valued fp32
+// 0 <= a <= kShortDivMax, 0 < b.  The estimate floor(fl(a c) rcp(b)) with
+// c = 1 + 2^-21 is never below the true quotient k: the relative errors of
+// the roundings (the product a c, the reciprocal's 1 ulp, the final
+// product) add up to less than 2^-21.  It exceeds a / b by at most
+// (a / b) 1.5 2^-21, so an overshoot to k + 1 needs (k + 1) b - a <=
+// 1.5 a 2^-21 with (k + 1) b - a >= 1, i.e. a >= 2^21 / 1.5: below that
+// the estimate is exact and no correction is needed.  (-q, so that callers
+// fold it into an fma without a negation.)
 constexpr float kDivBias = 1.f + 0x1p-21f;
+constexpr double kShortDivMax = 1398101.0;  // floor(2^21 / 1.5)
 
-// (-q, so that callers fold it into an fma without a negation)
 __device__ __forceinline__ float neg_fl_div32(float a, float b, float &r)
 {
-    float nq = ceilf(-(a * kDivBias) * __builtin_amdgcn_rcpf(b));
-    const float r0 = fmaf(nq, b, a);
-    const float over = r0 < 0.f ? 1.f : 0.f;
-    r = fmaf(over, b, r0);
-    return nq + over;
+    const float nq = ceilf(-(a * kDivBias) * __builtin_amdgcn_rcpf(b));
+    r = fmaf(nq, b, a);
+    return nq;
 }
 
 // Work counts of one composition (for the instruction model of the giant
@@ -157,15 +154,19 @@ struct Gamma {
 
 // Partial Euclid shared by NUCOMP and NUDUPL: run while |b_y| > L and b_x != 0
 // (both stay non-negative), then flip the signs of b_y and y when the number
-// of steps z is odd.  0 <= b_x < b_y < 2^21, so the loop runs in fp32.  A
-// step takes q = floor(b_y / b_x) and maps (b_x, b_y, x, y) to
-// (b_y - q b_x, b_x, y - q x, x).  Two steps per iteration, the second on
-// the exchanged roles (u, v, X, Y) -> (v, u, Y, X) and applied only if the
-// loop condition holds after the first (a select, not a branch), so that no
-// step moves registers around.
+// of steps z is odd.  0 <= b_x < b_y, so the loop runs in fp32.  A step
+// takes q = floor(b_y / b_x) and maps (b_x, b_y, x, y) to
+// (b_y - q b_x, b_x, y - q x, x).  Every dividend is at most the first b_y,
+// a norm's divisor u_1 / G < sqrt d <= 10^6 for the forms of reduced ideals
+// and d <= 10^12, so the quotient's estimate needs no correction (a larger
+// b_y fails the composition's checks).  Two steps per iteration, the second
+// on the exchanged roles (u, v, X, Y) -> (v, u, Y, X) and applied only if
+// the loop condition holds after the first (a select, not a branch), so that
+// no step moves registers around.
 __device__ __forceinline__ void partial_euclid(double &bxd, double &byd, double &x, double &y,
-                                               int &z, double L)
+                                               int &z, double L, Chk &bad)
 {
+    bad.fail |= !(byd <= kShortDivMax);
     float u = (float)bxd, v = (float)byd, X = 1.f, Y = 0.f;  // (b_x, b_y, x, y)
     const float Lf = (float)L;
     bool odd = false;  // the last iteration took one step: the roles stay exchanged
@@ -242,7 +243,7 @@ __device__ __forceinline__ void nucomp(Form f1, Form f2, double L, Form &f3, Gam
     }
     double bx = nn_mod(Bx, By), by = By, x, y;
     int z;
-    partial_euclid(bx, by, x, y, z, L);
+    partial_euclid(bx, by, x, y, z, L, bad);
     wk.euclid += (u32)z;
     const double ax = G * x, ay = G * y;
     double u3, v3, w3;
@@ -318,7 +319,7 @@ __device__ __forceinline__ void nudupl(Form f, double L, Form &f3, Gamma &g, Chk
     const double Bx = nn_mod(nn_mod(y0, By) * nn_mod(f.w, By), By);
     double bx = Bx, by = By, x, y;
     int z;
-    partial_euclid(bx, by, x, y, z, L);
+    partial_euclid(bx, by, x, y, z, L, bad);
     wk.euclid += (u32)z;
     const double ax = G * x, ay = G * y;
     double u3, v3, w3;
