@@ -63,11 +63,11 @@ VALU_SLOTS_PER_STEP = {"walk_plain": 10.0, "walk_handoff": 10.0}
 # staged, window end: 1); per distinguished ideal appended (counted by the
 # kernel, eis_stats.window_entries) the append: the selection of the pair's
 # first distinguished ideal, its residue sum and step, LDS staging and count
-# (15) and an eighth of a chunk write-out (3).  The wave runs the append
+# (15) and a quarter of a four-entry chunk write-out (3).  The wave runs the append
 # whenever any of its lanes appends; the lanes that do not append are not
 # counted.  mu_1's bookkeeping (once per window) and a window's end (written
 # at the wave's next pause) are not counted.
-WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.375}
+WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.75}
 # Giant-step walk: VALU issue slots per unit of its work, counted the same
 # way in the gfx950 code of the built kernel (per-lane path; a branch that a
 # lane does not take is not counted for it), the units being counted by the

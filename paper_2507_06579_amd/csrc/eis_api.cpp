@@ -666,7 +666,7 @@ static void infra_geometry(double scaled_root, u32 variant, u32 &emax, u32 &tsiz
     u32 emain = (u32)std::max(2.0, std::floor(n + 1.0));
     emain = std::max<u32>(emain, 16);
     const u32 want = (variant & kVariantNoConjugate) ? emain + (3 * emain) / 4 + 16 : emain + 16;
-    emax = (want + 7) / 8 * 8;  // whole 8-entry chunks (64-byte write-outs)
+    emax = (want + 7) / 8 * 8;  // whole 4-entry chunks of the window walk's write-outs
     if (emax > 496) emax = 496;
     // whole 8-slot groups (one 16-byte load each) at a load of at most 0.3
     // for the usual count: a lookup then reads a second group for fewer than

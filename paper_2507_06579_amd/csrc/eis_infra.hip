@@ -95,10 +95,14 @@ __device__ __forceinline__ unsigned long long entry_of(float Q4, float P4)
 // period) or it was handed to the plain walk.
 //
 // List entries are staged in LDS, kRing per lane, and written out as one
-// contiguous chunk per kRing entries (64 bytes of keys, 32 of residue sums),
-// instead of one scattered 8-byte write each.
+// contiguous chunk per kRing entries (32 bytes of keys, 16 of residue sums),
+// instead of one scattered 8-byte write each.  Four entries per lane keep
+// the rings at 12 KB per block and the kernel at 66 VGPRs, seven waves per
+// SIMD (with eight entries, 24 KB and 80 VGPRs: six waves, and the walk took
+// 9.8 instead of 8.5 ms per 10^8 window at 10^11; two entries: 9.8 ms).
 // ---------------------------------------------------------------------------
-constexpr u32 kRing = 8;
+constexpr u32 kRing = 4;
+static_assert(kRing % 4 == 0, "the residue sums are written four at a time");
 
 struct WindowRing {
     unsigned long long key[kRing][64];
@@ -385,8 +389,9 @@ __device__ __forceinline__ void walk_window_body(const InfraParams &p, const Seg
 __device__ __forceinline__ void walk_window_entry(const InfraParams &p)
 {
     if (p.k0 >= p.list_ctr->list_len) return;  // nothing in this batch (an empty retry)
-    // The segment table is sized at launch (p.nseg entries): with one segment
-    // the rings alone bound the workgroups per CU (six instead of five).
+    // The segment table is sized at launch (p.nseg entries), so that LDS
+    // (the rings, 12 KB per block) stays below the register limit on the
+    // workgroups per CU.
     extern __shared__ SegLds segs[];
     __shared__ WindowRing rings[4];
     load_segs(segs, p.segs, p.nseg);
