@@ -238,3 +238,34 @@ def test_nucomp_gcd_branch_cofactor_class():
         assert len(seen) == 1
         tested += 1
     assert math.isfinite(tested)
+
+
+# ---------------------------------------------------------------------------
+# the reduction step's quotient (eis_walk.h, rho_step_q) needs no overshoot
+# test for d <= 1.45 10^11, where s <= 380,788 and t = P + s < 2^24 / 13
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_rho_quotient_exact_below_bound(mode):
+    rng = np.random.default_rng(23 + mode)
+    n = 400000
+    s = rng.integers(100000, 380789, n)
+    P = rng.integers(1, s + 1)
+    # reduced: s - P < Q <= s + P; a third of the Q divide P + s exactly
+    # and a third divide P + s + 1, so that t / Q sits at or just below an
+    # integer
+    lo, hi = s - P + 1, s + P
+    Q = rng.integers(lo, hi + 1)
+    t = P + s
+    for part, off in ((1, 0), (2, 1)):
+        sl = slice(part * n // 3, (part + 1) * n // 3)
+        k = np.maximum(1, (t[sl] + off) // np.maximum(lo[sl], 1))
+        q = (t[sl] + off) // k
+        ok = (q >= lo[sl]) & (q <= hi[sl]) & ((t[sl] + off) % np.maximum(q, 1) == 0)
+        Q[sl] = np.where(ok, q, Q[sl])
+    c = 1.0 + 2.0 ** -21
+    P4, Q4, s4 = (P / 4.0).astype(F32), (Q / 4.0).astype(F32), (s / 4.0).astype(F32)
+    sqc = (s4.astype(np.float64) * np.float64(F32(c))).astype(F32)
+    num = (P4.astype(np.float64) * np.float64(F32(c)) + sqc.astype(np.float64)).astype(F32)  # one fma
+    q = np.floor((num * rcp32(Q4, mode)).astype(F32)).astype(np.int64)
+    assert np.array_equal(q, t // Q)
