@@ -84,7 +84,8 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.75}
 #   partial Euclid step (floor quotients, whose estimate needs no
 #     correction for the norms of d <= 10^12; two per loop iteration of 21,
 #     the iteration count's copy included): 10.5;
-#   reduction step after a composition (fp64, with its checks): 47;
+#   reduction step after a composition (fp64, with its checks and the loop
+#     test, two steps per iteration on swapping registers): 45;
 #   walk step towards the next distinguished ideal (the step, the test): 10;
 #   lookup of a distinguished ideal and its conjugate (the extra step for
 #     the conjugate's key, two hashes, home groups, fingerprints and group
@@ -92,7 +93,7 @@ WINDOW_SLOTS = {"rho_steps": 13.0, "entries": 15.75}
 #     groups, the list addresses and the tests on a lane's path when no slot
 #     matches: 69): 112.
 GIANT_SLOTS = {"compositions": 330.0, "gcd_branches": 136.0, "xgcd_steps": 9.0,
-               "partial_euclid_steps": 10.5, "reduce_steps": 47.0, "walk_steps": 10.0,
+               "partial_euclid_steps": 10.5, "reduce_steps": 45.0, "walk_steps": 10.0,
                "lookups": 112.0}
 
 

@@ -471,36 +471,54 @@ __device__ __forceinline__ bool is_reduced(double Q, double P, double s)
     return Q > 0.0 && P > 0.0 && P <= s && s - P < Q && Q <= s + P;
 }
 
+__device__ __forceinline__ bool reduce_more(double Q, double P, double s, int it, const Chk &bad)
+{
+    return !is_reduced(Q, P, s) && it < kMaxReduce && Q != 0.0 && bad.mx < kExactLimit;
+}
+
+// One step from (Q, P) with predecessor Qp: the new P goes to Pn and the new
+// Q overwrites Qp (so the caller's two register sets swap roles each step).
+__device__ __forceinline__ u32 reduce_step(double Q, double P, double s, double &Qp, double &Pn,
+                                           Chk &bad)
+{
+    const double num = (Q > 0.0) ? P + s : -P - s - 1.0;
+    const double q = fl_div(num, fabs(Q));
+    const double qQ = q * Q;
+    chk(qQ, bad);
+    Pn = qQ - P;
+    const double t = q * (P - Pn);
+    chk(t, bad);
+    Qp = Qp + t;
+    chk(Qp, bad);
+    const double t4 = Pn * 0.25;
+    return (t4 - floor(t4) > 0.5) ? 2u : 1u;
+}
+
 __device__ __forceinline__ u32 reduce_form(const Form &f, double d, double s, double &Q,
                                            double &P, double &Qp, Chk &bad, GiantWork &wk)
 {
-    Q = fabs(2.0 * f.u);
-    P = -f.v;
-    Qp = (f.u > 0.0) ? -2.0 * f.w : 2.0 * f.w;
+    double Qa = fabs(2.0 * f.u), Pa = -f.v, Qb = (f.u > 0.0) ? -2.0 * f.w : 2.0 * f.w, Pb = 0.0;
     u32 S = 0;
     int it = 0;
-    // One exit: the loop also stops once a value is no longer exact or Q
-    // vanished (then the final checks fail).
-    while (!is_reduced(Q, P, s) && it < kMaxReduce && Q != 0.0 && bad.mx < kExactLimit) {
-        it++;
-        wk.reduce++;
-        const double num = (Q > 0.0) ? P + s : -P - s - 1.0;
-        const double q = fl_div(num, fabs(Q));
-        const double qQ = q * Q;
-        chk(qQ, bad);
-        const double Pn = qQ - P;
-        const double t = q * (P - Pn);
-        chk(t, bad);
-        const double Qn = Qp + t;
-        chk(Qn, bad);
-        // r(Pn) = 1 + bit 1 of the odd Pn: 2 when Pn = 3 (mod 4), i.e. when
-        // the fractional part of Pn / 4 is 3/4 (for either sign of Pn)
-        const double t4 = Pn * 0.25;
-        S += (t4 - floor(t4) > 0.5) ? 2u : 1u;
-        Qp = Q;
-        Q = Qn;
-        P = Pn;
+    bool run = reduce_more(Qa, Pa, s, it, bad);
+    for (;;) {
+        if (run) {
+            S += reduce_step(Qa, Pa, s, Qb, Pb, bad);  // now (Qb, Pb), predecessor Qa
+            it++;
+            run = reduce_more(Qb, Pb, s, it, bad);
+        }
+        if (run) {
+            S += reduce_step(Qb, Pb, s, Qa, Pa, bad);  // back to (Qa, Pa), predecessor Qb
+            it++;
+            run = reduce_more(Qa, Pa, s, it, bad);
+        }
+        if (!__any(run)) break;
     }
+    wk.reduce += (u32)it;
+    const bool odd = (it & 1) != 0;
+    Q = odd ? Qb : Qa;
+    P = odd ? Pb : Pa;
+    Qp = odd ? Qa : Qb;
     bad.fail |= !is_reduced(Q, P, s);
     bad.fail |= (fma(Q, Qp, P * P) != d);
     return S;

@@ -45,8 +45,10 @@ def test_tune_choices_cache_and_bits(tmp_path):
             # is the fastest one timed
             assert min(bn["pass_ms_24_23_22"]) > 0
             assert len(bn["scale_ms"]) == len(SCALES) and min(bn["scale_ms"]) > 0
-            best = doc["scales"][bn["scale_ms"].index(min(bn["scale_ms"]))]
-            assert bn["window_scale"] == pytest.approx(best)
+            # (the cache prints times to 0.001 ms, so two scales can tie
+            # there; the one kept must be one of the fastest)
+            kept = bn["scale_ms"][doc["scales"].index(bn["window_scale"])]
+            assert kept == pytest.approx(min(bn["scale_ms"]), abs=1e-3)
             assert bn["giant_ms"] == pytest.approx(min(bn["scale_ms"]), abs=1e-3)
             if bn["method"] == 1:
                 assert min(bn["chunk_ms_8_16_32"]) > 0
