@@ -619,22 +619,40 @@ static u64 infra_bytes_per_d(u32 emax, u32 tsize)
 }
 
 // Scratch of the giant-step method: `batch` d's (whole tiles of 64), `emax`
-// list entries and `tsize` table slots each.
+// list entries and `tsize` table slots each.  A reallocation grows past the
+// need when the budget allows: twice the d's held before (at most a full
+// pass) and an eighth more entries and slots than asked for, so that a sweep
+// of rising heights, whose lists and tables grow slowly, does not free and
+// allocate its scratch (gigabytes, and at times hundreds of milliseconds
+// each way) at almost every call.
+constexpr u32 kEmaxMax = 496;  // list entries per d at most (9-bit slot indices)
+
+static u32 round8_up(u64 x) { return (u32)((x + 7) / 8 * 8); }
+
 static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
 {
-    const u64 cap = (batch + 63) / 64 * 64;
-    if (c->pb.lists && c->pb.infra_batch_cap >= cap && c->pb.infra_emax_cap >= emax &&
+    const u64 need = (batch + 63) / 64 * 64;
+    if (c->pb.lists && c->pb.infra_batch_cap >= need && c->pb.infra_emax_cap >= emax &&
         c->pb.infra_tsize_cap >= tsize)
         return EIS_OK;
+    const u64 old_cap = c->pb.lists ? c->pb.infra_batch_cap : 0;
     int qrc = quiesce(c);
     if (qrc != EIS_OK) return qrc;
     free_infra(c);
     drop_graphs(c);
-    const u64 bytes = cap * infra_bytes_per_d(emax, tsize);
+    u64 cap = std::max(need, std::min<u64>(2 * old_cap, kPassCandidates));
+    u32 ecap = std::max(emax, std::min(round8_up(emax + emax / 8), kEmaxMax));
+    u32 tcap = std::max(tsize, std::min(round8_up(tsize + tsize / 8), kTableSlotsMax));
+    if (c->bytes_held + cap * infra_bytes_per_d(ecap, tcap) > c->cfg.mem_budget_bytes) {
+        cap = need;
+        ecap = emax;
+        tcap = tsize;
+    }
+    const u64 bytes = cap * infra_bytes_per_d(ecap, tcap);
     if (c->bytes_held + bytes > c->cfg.mem_budget_bytes) return EIS_ENOMEM;
-    if (hipMalloc(&c->pb.lists, cap * emax * 8) != hipSuccess ||
-        hipMalloc(&c->pb.lres, cap * emax * 4) != hipSuccess ||
-        hipMalloc(&c->pb.tables, cap * tsize * 2) != hipSuccess ||
+    if (hipMalloc(&c->pb.lists, cap * ecap * 8) != hipSuccess ||
+        hipMalloc(&c->pb.lres, cap * ecap * 4) != hipSuccess ||
+        hipMalloc(&c->pb.tables, cap * tcap * 2) != hipSuccess ||
         hipMalloc(&c->pb.state, cap * sizeof(WindowState)) != hipSuccess ||
         hipMalloc(&c->pb.tasks, cap * kCostBuckets * sizeof(GiantTask)) != hipSuccess) {
         free_infra(c);
@@ -643,8 +661,8 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
     c->pb.infra_bytes = bytes;
     c->bytes_held += bytes;
     c->pb.infra_batch_cap = cap;
-    c->pb.infra_emax_cap = emax;
-    c->pb.infra_tsize_cap = tsize;
+    c->pb.infra_emax_cap = ecap;
+    c->pb.infra_tsize_cap = tcap;
     return EIS_OK;
 }
 
@@ -667,7 +685,7 @@ static void infra_geometry(double scaled_root, u32 variant, u32 &emax, u32 &tsiz
     emain = std::max<u32>(emain, 16);
     const u32 want = (variant & kVariantNoConjugate) ? emain + (3 * emain) / 4 + 16 : emain + 16;
     emax = (want + 7) / 8 * 8;  // whole 4-entry chunks of the window walk's write-outs
-    if (emax > 496) emax = 496;
+    if (emax > kEmaxMax) emax = kEmaxMax;
     // whole 8-slot groups (one 16-byte load each) at a load of at most 0.3
     // for the usual count: a lookup then reads a second group for fewer than
     // one key in 300; at most kTableSlotsMax slots
