@@ -569,16 +569,20 @@ static int quiesce(eis_ctx *c)
     return EIS_OK;
 }
 
+// The prime offsets of a pass's segments; grows by half again at least, as
+// rising heights need slowly more primes (each reallocation also drops the
+// captured graphs).
 static int ensure_roff(eis_ctx *c, u64 n)
 {
     if (c->pb.roff_cap >= n) return EIS_OK;
     int qrc = quiesce(c);
     if (qrc != EIS_OK) return qrc;
+    const u64 cap = std::max(n, c->pb.roff_cap + c->pb.roff_cap / 2);
     (void)hipFree(c->pb.roff);
     c->pb.roff = nullptr;
     c->pb.roff_cap = 0;
-    if (hipMalloc(&c->pb.roff, n * sizeof(u64)) != hipSuccess) return EIS_ENOMEM;
-    c->pb.roff_cap = n;
+    if (hipMalloc(&c->pb.roff, cap * sizeof(u64)) != hipSuccess) return EIS_ENOMEM;
+    c->pb.roff_cap = cap;
     drop_graphs(c);  // captured sequences hold the old pointer
     return EIS_OK;
 }
