@@ -623,12 +623,13 @@ static u64 infra_bytes_per_d(u32 emax, u32 tsize)
 }
 
 // Scratch of the giant-step method: `batch` d's (whole tiles of 64), `emax`
-// list entries and `tsize` table slots each.  A reallocation grows past the
-// need when the budget allows: twice the d's held before (at most a full
-// pass) and an eighth more entries and slots than asked for, so that a sweep
-// of rising heights, whose lists and tables grow slowly, does not free and
-// allocate its scratch (gigabytes, and at times hundreds of milliseconds
-// each way) at almost every call.
+// list entries and `tsize` table slots each.  A reallocation keeps room for
+// the d's held before and adds an eighth more entries and slots than asked
+// for, when the budget allows, so that a sweep of rising heights, whose lists
+// and tables grow slowly, does not free and allocate its scratch (gigabytes,
+// and at times hundreds of milliseconds each way) at almost every call.  The
+// d's themselves get no room beyond the need: serving measured worse with it
+// (a larger allocation is a longer stall when a burst outgrows the scratch).
 constexpr u32 kEmaxMax = 496;  // list entries per d at most (9-bit slot indices)
 
 static u32 round8_up(u64 x) { return (u32)((x + 7) / 8 * 8); }
@@ -644,7 +645,7 @@ static int ensure_infra(eis_ctx *c, u64 batch, u32 emax, u32 tsize)
     if (qrc != EIS_OK) return qrc;
     free_infra(c);
     drop_graphs(c);
-    u64 cap = std::max(need, std::min<u64>(2 * old_cap, kPassCandidates));
+    u64 cap = std::max(need, old_cap);
     u32 ecap = std::max(emax, std::min(round8_up(emax + emax / 8), kEmaxMax));
     u32 tcap = std::max(tsize, std::min(round8_up(tsize + tsize / 8), kTableSlotsMax));
     if (c->bytes_held + cap * infra_bytes_per_d(ecap, tcap) > c->cfg.mem_budget_bytes) {
